@@ -1,0 +1,254 @@
+/*
+ * wdirac: Wilson-clover Dirac operator and FGMRES on one AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * The operator (arXiv 2407.00041, Eq. (1.13) with lattice spacing a = 1, i.e.
+ * D = D_sc - D_nc of Eqs. (2.5)-(2.7)):
+ *
+ *   (D psi)(x) = A(x) psi(x)
+ *              - 1/2 sum_mu (I_4 - gamma_mu) (x) U_mu(x)       psi(x+mu)
+ *              - 1/2 sum_mu (I_4 + gamma_mu) (x) U_mu(x-mu)^H  psi(x-mu)
+ *   A(x)       = (4 + m0) I_12 + c_sw C(x),
+ *   C(x)       = -(1/32) sum_{mu,nu} (gamma_mu gamma_nu) (x) (Q_mu,nu(x) - Q_nu,mu(x))
+ *
+ * with the clover leaves Q of Eq. (1.12) (Eq. (1.11) for C).  Lattice
+ * directions T,Z,Y,X and (anti-)periodic neighbours follow Sec. 1.1,
+ * Eqs. (1.7)-(1.9).  The paper does not print its gamma basis; this library
+ * uses the chiral Euclidean basis gamma_mu = [[0, B_mu], [B_mu^H, 0]] with
+ * B_T = 1, B_Z = -i sigma_3, B_Y = -i sigma_2, B_X = -i sigma_1, so
+ * gamma_5 = diag(1, 1, -1, -1) and C(x) is block-diagonal in chirality.
+ *
+ * ---------------------------------------------------------------------------
+ * Canonical (host-facing) layouts.  A complex number is two consecutive
+ * doubles (re, im); the site index is lexicographic
+ * i = ((t*nZ + z)*nY + y)*nX + x (x fastest); dims[] = {nT, nZ, nY, nX}.
+ *   spinor : [nrhs][V][12] complex128, component 3*sigma + colour
+ *            (Eqs. (1.1)-(1.3): colour fastest).
+ *   links  : [V][4][3][3]  complex128, mu = T,Z,Y,X, U_mu(x) = link x -> x+mu,
+ *            row-major ((U v)_a = sum_b U[3a+b] v_b).
+ *   clover : [V][42]       complex128, the unit-c_sw term C(x): chirality
+ *            block + (spins 0,1) then block - (spins 2,3); each block = its
+ *            6 diagonal entries then its 15 strict-upper entries in row-major
+ *            pair order (0,1),(0,2),...,(4,5); block-local index
+ *            3*(sigma mod 2) + colour.  Diagonal imaginary parts are ignored.
+ *
+ * Native (device) field layouts, per right-hand side, one 16-byte vector of
+ * consecutive spinor components per (block, site):
+ *   WDIRAC_F64  : [12][V] complex128                       192 B/site
+ *   WDIRAC_F32  : [ 6][V] (2 x complex64)                    96 B/site
+ *   WDIRAC_F16S : [ 3][V] (4 x complex fp16), then [V] fp32 per-site scales;
+ *                 stored value = scale * fp16 value, scale = max |real part or
+ *                 imaginary part| over the site's 24 reals (0 -> all zero).
+ * Consecutive right-hand sides are dirac_field_bytes(op, prec, 1) apart.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point.
+ *   Return value : WDIRAC_OK (0); negative = error; positive = warning.
+ *                  dirac_last_error() gives a thread-local message.
+ *   Streams      : `stream` is a hipStream_t (NULL = the null stream).
+ *                  Entry points documented "asynchronous" only enqueue work.
+ *   Ownership    : the handle owns every device buffer it allocates;
+ *                  dirac_destroy frees them.  Caller buffers stay the caller's.
+ *   Threads      : a handle is immutable after dirac_create, so concurrent
+ *                  applies on different streams are safe.
+ */
+#ifndef WDIRAC_H
+#define WDIRAC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define WDIRAC_OK 0
+#define WDIRAC_EINVAL (-1)       /* bad argument (null, alias, size, enum)  */
+#define WDIRAC_ENOMEM (-2)       /* device allocation failed                */
+#define WDIRAC_EHIP (-3)         /* a HIP runtime call or launch failed     */
+#define WDIRAC_EUNSUPPORTED (-4) /* precision not materialised, no device   */
+#define WDIRAC_ENOTCONV 1        /* solver hit maxit; result still valid    */
+
+/* precisions */
+#define WDIRAC_F64 0
+#define WDIRAC_F32 1
+#define WDIRAC_F16S 2
+
+/* dirac_create flags */
+#define WDIRAC_ANTIPERIODIC_T 1u /* hops across the T boundary get sign -1 */
+#define WDIRAC_WITH_F32 2u       /* also materialise FP32 links + clover    */
+#define WDIRAC_WITH_F16 4u       /* also materialise FP16 links + clover    */
+
+typedef struct dirac_op dirac_op;
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *dirac_last_error(void);
+
+/* Library version string. */
+const char *dirac_version(void);
+
+/*
+ * Create an operator (Sec. 2.3: the operator data are the links and the
+ * per-site self-coupling matrices; the clover part is computed once, not per
+ * application).
+ *   dims   : {nT, nZ, nY, nX}, each >= 2.
+ *   links  : HOST canonical links (see above).
+ *   clover : HOST canonical packed unit-c_sw term C(x), or NULL to build it
+ *            from the links on the device (Eqs. (1.11)-(1.12)).
+ *   m0,csw : mass and clover coefficient; A(x) = (4 + m0) I + csw C(x).
+ *   flags  : WDIRAC_* flags above.  FP64 data are always materialised.
+ * Synchronous.  Copies everything into device memory owned by the handle;
+ * the caller may free its arrays on return.  Errors: EINVAL (null pointer,
+ * dims < 2), ENOMEM, EHIP, EUNSUPPORTED (no HIP device).
+ */
+int dirac_create(dirac_op **op, const int dims[4], const double *links, const double *clover,
+                 double m0, double csw, unsigned flags);
+
+/* Free the handle and its device memory.  NULL is accepted. */
+int dirac_destroy(dirac_op *op);
+
+/* Number of lattice sites V of the handle (0 for NULL). */
+long long dirac_volume(const dirac_op *op);
+
+/* Bytes of a native field of `nrhs` right-hand sides at precision `prec`
+ * (0 on bad arguments). */
+size_t dirac_field_bytes(const dirac_op *op, int prec, int nrhs);
+
+/*
+ * out = D in (Eq. (1.13)), for nrhs right-hand sides in native layout at
+ * precision prec, on device buffers of dirac_field_bytes(op, prec, nrhs)
+ * bytes each.  Reads each link and clover entry once per site and block of
+ * right-hand sides.  Asynchronous on `stream`; no allocation, no host sync.
+ * Errors: EINVAL (null, nrhs < 1, out overlapping in, unknown prec),
+ * EUNSUPPORTED (prec not materialised by dirac_create), EHIP (launch).
+ */
+int dirac_apply(const dirac_op *op, void *out, const void *in, int nrhs, int prec, void *stream);
+
+/*
+ * out = D^H in.  The adjoint swaps the projectors of Eq. (1.13):
+ * -1/2 (I + gamma_mu) (x) U_mu(x) psi(x+mu) - 1/2 (I - gamma_mu) (x)
+ * U_mu(x-mu)^H psi(x-mu), with A(x) Hermitian; equivalently gamma_5 D gamma_5.
+ * Same arguments, behaviour and errors as dirac_apply.
+ */
+int dirac_apply_adjoint(const dirac_op *op, void *out, const void *in, int nrhs, int prec,
+                        void *stream);
+
+/*
+ * Several independent batches of right-hand sides (possibly of different
+ * sizes) through ONE persistent launch: out_b = D in_b (or D^H when
+ * dagger != 0) for every batch.  Each link and clover entry is read once per
+ * site tile and register block of right-hand sides.
+ */
+typedef struct {
+    void *out;       /* native, nrhs fields                                 */
+    const void *in;  /* native, nrhs fields, must not overlap out           */
+    int nrhs;        /* >= 1                                                */
+} dirac_batch;
+
+int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbatch, int prec,
+                        int dagger, void *stream);
+
+/*
+ * Process-wide launch parameters of the stencil kernels (the autotuner's
+ * knobs).  Keys: "block" (threads per work-group: 64, 128, 192, 256),
+ * "order" (0 linear, 1 one contiguous 1/8 of the lattice per XCD, 2 every
+ * XCD takes 1/8 of each T-slice and the slices are swept in order),
+ * "persistent_blocks" (work-groups of a dirac_apply_batched launch, >= 8),
+ * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
+ * or 4).  Not synchronised with launches in flight; set before applying.
+ * Errors: EINVAL (unknown key or value out of range).
+ */
+int dirac_tune_set(const char *key, int value);
+int dirac_tune_get(const char *key, int *value);
+
+/*
+ * Canonical <-> native conversion of device fields.
+ *   dirac_pack   : native[prec] <- canonical complex128 [nrhs][V][12]
+ *                  (F32: round to nearest even; F16S: per-site scale as
+ *                  documented above, round to nearest even).
+ *   dirac_unpack : canonical complex128 <- native[prec].
+ * Both buffers on the device.  Asynchronous.  Errors: EINVAL.
+ */
+int dirac_pack(const dirac_op *op, void *native, const double *canonical, int nrhs, int prec,
+               void *stream);
+int dirac_unpack(const dirac_op *op, double *canonical, const void *native, int nrhs, int prec,
+                 void *stream);
+
+/*
+ * Unit-c_sw clover term from device canonical links (Eqs. (1.11)-(1.12)):
+ * clover_out = C(x), canonical packed [V][42] complex128, device buffers.
+ * Independent of any handle.  Asynchronous.  Errors: EINVAL, EHIP.
+ */
+int dirac_clover_term(const int dims[4], const double *links_dev, double *clover_dev, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* FGMRES (Algorithm 2, Sec. 1.2) for D x = b.                               */
+
+#define FGMRES_F64 0        /* plain FP64 FGMRES(restart), no preconditioner */
+#define FGMRES_MIXED_F32 1  /* FP64 outer FGMRES, inner GMRES on FP32 D     */
+#define FGMRES_MIXED_F16S 2 /* FP64 outer FGMRES, inner GMRES on FP16S D    */
+
+typedef struct {
+    int restart;        /* outer Krylov dimension m (>= 1)                   */
+    double tol;         /* stop when ||b - D x|| < tol ||b - D x0||          */
+    long long maxit;    /* maximum FP64 operator applications                */
+    int mode;           /* FGMRES_F64 / FGMRES_MIXED_F32 / FGMRES_MIXED_F16S */
+    int inner_restart;  /* inner GMRES dimension (mixed modes)               */
+    double inner_tol;   /* inner relative residual target (mixed modes)      */
+    int inner_maxit;    /* inner operator applications per outer step        */
+} fgmres_params;
+
+#define FGMRES_HIST_MAX 4096
+
+typedef struct {
+    long long applies;          /* FP64 operator applications                */
+    long long inner_applies;    /* low-precision applications (mixed)        */
+    long long restarts;         /* outer cycles                              */
+    int converged;              /* 1 if the tolerance was met                */
+    int breakdown;              /* 1 if |h_{j+1,j}| < tol/10 ended a cycle   */
+    double true_residual;       /* final ||b - D x|| / ||b - D x0||, FP64    */
+    double seconds;             /* wall time of the solve                    */
+    int nhist;                  /* entries in hist[]                         */
+    double hist[FGMRES_HIST_MAX]; /* relative residual estimate per step    */
+} fgmres_stats;
+
+/* Workspace bytes fgmres_solve needs for `nrhs` right-hand sides. */
+size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nrhs);
+
+/*
+ * Solve D x_r = b_r for nrhs right-hand sides.  Every right-hand side runs
+ * its own FGMRES (its own Krylov space, residuals and convergence test); the
+ * operator applications of the right-hand sides still iterating are issued
+ * together as one batched launch.
+ *   x, b : device, native FP64, nrhs fields each.  x is the initial guess on
+ *          entry (x0) and the solution on return.
+ *   st   : host array of nrhs stats records (may be NULL).
+ *   work : device workspace of at least fgmres_workspace_bytes(op, p, nrhs).
+ * Blocks until done (one host synchronisation per Arnoldi step to read the
+ * residual estimates).  Returns WDIRAC_ENOTCONV (> 0) when some right-hand
+ * side reached maxit (x still holds its last iterate); errors: EINVAL,
+ * EUNSUPPORTED (mixed-mode precision not materialised), EHIP.
+ */
+int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs,
+                 const fgmres_params *p, fgmres_stats *st, void *work, size_t work_bytes,
+                 void *stream);
+
+/* ------------------------------------------------------------------------ */
+/*
+ * Link derivative ("force") of L = Re sum_r <eta_r, D(U) x_r> (FP64).
+ *   dU  : device [V][4][3][3] complex128 (canonical link layout), written:
+ *         F_mu(x) = P_TA(G_mu(x) U_mu(x)^H), P_TA(M) = (M - M^H)/2 -
+ *         tr(M - M^H)/6, with G = dL/dRe U + i dL/dIm U, summed over the
+ *         nrhs pairs; with raw != 0, G itself is written instead.
+ *   eta, x : device native FP64, nrhs fields each.
+ * Includes the clover contribution when csw != 0 and the clover term was
+ * built from the links.  Asynchronous.  Errors: EINVAL, EHIP.
+ */
+int dirac_force(const dirac_op *op, double *dU, const double *eta, const double *x, int nrhs,
+                int raw, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDIRAC_H */

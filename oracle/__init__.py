@@ -157,11 +157,13 @@ def dirac_apply(dims, links, psi, m0: float, csw: float = 0.0, clover=None,
 
 
 def dirac_apply_sites(dims, links, psi, sites, m0: float, csw: float = 0.0, clover=None,
-                      antiperiodic_t: bool = False, dagger: bool = False) -> np.ndarray:
+                      antiperiodic_t: bool = False, dagger: bool = False,
+                      clover_rows=None) -> np.ndarray:
     """(D psi)(x) at the listed sites only; returns [len(sites), 12].
 
     ``clover`` may be the full packed [V, 42] array or None (then, if csw != 0,
-    the clover term is built at the listed sites only).
+    the clover term is built at the listed sites only); ``clover_rows`` may
+    instead give the packed term of the listed sites, [len(sites), 42].
     """
     d = _dims(dims)
     V = volume(d)
@@ -169,7 +171,9 @@ def dirac_apply_sites(dims, links, psi, sites, m0: float, csw: float = 0.0, clov
     s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
     x = _c128(psi, (V, 12)).reshape(V, 12)
     out = np.zeros((len(s), 12), np.complex128)
-    if clover is None:
+    if clover_rows is not None:
+        C = _c128(clover_rows, (42,)).reshape(len(s), 42)
+    elif clover is None:
         # A(x) enters at the output site only: build C there and nowhere else
         C = clover_term_sites(d, U, s) if csw != 0.0 else None
     else:

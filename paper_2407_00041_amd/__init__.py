@@ -1,0 +1,174 @@
+"""wdirac: the Wilson-clover Dirac operator of arXiv 2407.00041 (Eq. (1.13)) and
+FGMRES (Algorithm 2) on an AMD Instinct MI355X, behind the C ABI of
+``include/wdirac.h``.
+
+Python here only marshals arguments: torch supplies device memory and the
+current HIP stream; every step runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (ANTIPERIODIC_T, EUNSUPPORTED, F16S, F32, F64, FGMRES_F64,  # noqa: F401
+                   FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
+
+PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
+
+
+def _prec(p) -> int:
+    return PRECS[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return int(t.data_ptr())
+
+
+def _host_c128(a, shape_tail):
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    assert a.shape[-len(shape_tail):] == tuple(shape_tail), (a.shape, shape_tail)
+    return a
+
+
+class DiracOp:
+    """Operator handle: D = A - 1/2 sum hop terms on a periodic 4-D lattice.
+
+    dims = (nT, nZ, nY, nX); links canonical [V, 4, 3, 3] complex128 (host or
+    device tensor / ndarray); clover None (build from links when csw != 0) or
+    the packed unit-c_sw term [V, 42].
+    """
+
+    def __init__(self, dims, links, m0: float, csw: float = 0.0, clover=None,
+                 antiperiodic_t: bool = False, precisions=("f64", "f32", "f16s")):
+        self.lib = _lib.load()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.m0, self.csw = float(m0), float(csw)
+        self.antiperiodic_t = bool(antiperiodic_t)
+        flags = ANTIPERIODIC_T if antiperiodic_t else 0
+        if "f32" in precisions:
+            flags |= WITH_F32
+        if "f16s" in precisions:
+            flags |= WITH_F16
+        self.precisions = tuple(precisions)
+        L = _host_c128(links, (4, 3, 3)).reshape(self.V, 4, 3, 3)
+        C = None if clover is None else _host_c128(clover, (42,)).reshape(self.V, 42)
+        d = (ctypes.c_int * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        check(self.lib.dirac_create(ctypes.byref(h), d, L.ctypes.data, None if C is None else C.ctypes.data,
+                                    self.m0, self.csw, flags), "dirac_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dirac_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- fields
+    def field_bytes(self, prec="f64", nrhs: int = 1) -> int:
+        return int(self.lib.dirac_field_bytes(self.handle, _prec(prec), int(nrhs)))
+
+    def empty(self, prec="f64", nrhs: int = 1, device="cuda") -> torch.Tensor:
+        """Native field buffer (uint8 tensor of field_bytes)."""
+        return torch.empty(self.field_bytes(prec, nrhs), dtype=torch.uint8, device=device)
+
+    def pack(self, canonical: torch.Tensor, prec="f64", out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+        """canonical [nrhs, V, 12] (or [V, 12]) complex128 on the device -> native."""
+        c = canonical.contiguous()
+        assert c.dtype == torch.complex128 and c.is_cuda
+        nrhs = c.numel() // (12 * self.V)
+        assert nrhs * 12 * self.V == c.numel()
+        out = self.empty(prec, nrhs, c.device) if out is None else out
+        check(self.lib.dirac_pack(self.handle, _ptr(out), _ptr(c), nrhs, _prec(prec), _stream(stream)),
+              "dirac_pack")
+        return out
+
+    def unpack(self, native: torch.Tensor, prec="f64", nrhs: int | None = None,
+               stream=None) -> torch.Tensor:
+        """native -> canonical [nrhs, V, 12] complex128."""
+        p = _prec(prec)
+        if nrhs is None:
+            nrhs = native.numel() * native.element_size() // self.field_bytes(p, 1)
+        out = torch.empty((nrhs, self.V, 12), dtype=torch.complex128, device=native.device)
+        check(self.lib.dirac_unpack(self.handle, _ptr(out), _ptr(native), nrhs, p, _stream(stream)),
+              "dirac_unpack")
+        return out
+
+    # ---------------------------------------------------------------- applies
+    def apply_native(self, out: torch.Tensor, inp: torch.Tensor, nrhs: int = 1, prec="f64",
+                     dagger: bool = False, stream=None) -> torch.Tensor:
+        f = self.lib.dirac_apply_adjoint if dagger else self.lib.dirac_apply
+        check(f(self.handle, _ptr(out), _ptr(inp), int(nrhs), _prec(prec), _stream(stream)),
+              "dirac_apply_adjoint" if dagger else "dirac_apply")
+        return out
+
+    def apply_batched(self, batches, prec="f32", dagger: bool = False, stream=None):
+        """batches: list of (out, inp, nrhs) native buffers; one launch."""
+        arr = (_lib.DiracBatch * len(batches))()
+        for k, (o, i, n) in enumerate(batches):
+            arr[k].out, arr[k].inp, arr[k].nrhs = _ptr(o), _ptr(i), int(n)
+        check(self.lib.dirac_apply_batched(self.handle, arr, len(batches), _prec(prec), int(bool(dagger)),
+                                           _stream(stream)), "dirac_apply_batched")
+
+    def apply(self, psi: torch.Tensor, prec="f64", dagger: bool = False) -> torch.Tensor:
+        """Canonical in, canonical out (pack -> apply -> unpack), for convenience."""
+        shape = psi.shape
+        c = psi.reshape(-1, self.V, 12)
+        nrhs = c.shape[0]
+        a = self.pack(c, prec)
+        b = self.empty(prec, nrhs, c.device)
+        self.apply_native(b, a, nrhs, prec, dagger)
+        return self.unpack(b, prec, nrhs).reshape(shape)
+
+    def force(self, eta: torch.Tensor, x: torch.Tensor, nrhs: int = 1, raw: bool = False,
+              stream=None) -> torch.Tensor:
+        """dL/dU for L = Re sum <eta, D x>; eta, x native FP64.  [V, 4, 3, 3] c128."""
+        out = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=x.device)
+        check(self.lib.dirac_force(self.handle, _ptr(out), _ptr(eta), _ptr(x), int(nrhs), int(bool(raw)),
+                                   _stream(stream)), "dirac_force")
+        return out
+
+
+def tune_set(key: str, value: int) -> None:
+    """Set a process-wide launch parameter of the stencil (see dirac_tune_set)."""
+    check(_lib.load().dirac_tune_set(key.encode(), int(value)), "dirac_tune_set")
+
+
+def tune_get(key: str) -> int:
+    v = ctypes.c_int()
+    check(_lib.load().dirac_tune_get(key.encode(), ctypes.byref(v)), "dirac_tune_get")
+    return int(v.value)
+
+
+TUNE_KEYS = ("block", "order", "persistent_blocks", "nr_f64", "nr_f32", "nr_f16s")
+
+
+def clover_term(dims, links_dev: torch.Tensor, stream=None) -> torch.Tensor:
+    """Unit-c_sw clover term [V, 42] c128 built on the device from device links."""
+    lib = _lib.load()
+    L = links_dev.contiguous()
+    assert L.dtype == torch.complex128 and L.is_cuda
+    V = int(np.prod(dims))
+    out = torch.empty((V, 42), dtype=torch.complex128, device=L.device)
+    d = (ctypes.c_int * 4)(*[int(x) for x in dims])
+    check(lib.dirac_clover_term(d, _ptr(L), _ptr(out), _stream(stream)), "dirac_clover_term")
+    return out

@@ -1,0 +1,277 @@
+// C ABI of the library: operator handle, applies, layout conversion.
+#include <cstring>
+#include <string>
+
+#include "common.h"
+#include "dslash.h"
+
+namespace wd {
+
+hipError_t pack_launch(void *nat, const double *can, int nrhs, int prec, int V, hipStream_t st);
+hipError_t unpack_launch(double *can, const void *nat, int nrhs, int prec, int V, hipStream_t st);
+hipError_t clover_build_launch(double *out, const double *links, const Geom &g, hipStream_t st);
+hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const double *clover_can_dev,
+                              hipStream_t st);
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+Geom make_geom(const int dims[4]) {
+    Geom g;
+    long long V = 1;
+    for (int k = 0; k < 4; k++) {
+        g.n[k] = dims[k];
+        V *= dims[k];
+    }
+    g.V = (int)V;
+    g.stride[3] = 1;
+    g.stride[2] = dims[3];
+    g.stride[1] = dims[3] * dims[2];
+    g.stride[0] = dims[3] * dims[2] * dims[1];
+    return g;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + nb && y < x + na;
+}
+
+int check_apply(const dirac_op *op, const void *out, const void *in, int nrhs, int prec) {
+    if (!op) return fail(WDIRAC_EINVAL, "null operator");
+    if (!out || !in) return fail(WDIRAC_EINVAL, "null field pointer");
+    if (nrhs < 1) return fail(WDIRAC_EINVAL, "nrhs must be >= 1");
+    if (prec != WDIRAC_F64 && prec != WDIRAC_F32 && prec != WDIRAC_F16S)
+        return fail(WDIRAC_EINVAL, "unknown precision " + std::to_string(prec));
+    if (!op->data(prec).links)
+        return fail(WDIRAC_EUNSUPPORTED, "precision " + std::to_string(prec) + " not materialised at create");
+    size_t n = field_rhs_bytes(prec, op->g.V) * (size_t)nrhs;
+    if (overlap(out, n, in, n)) return fail(WDIRAC_EINVAL, "out overlaps in");
+    if ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(in)) & 15)
+        return fail(WDIRAC_EINVAL, "field pointers must be 16-byte aligned");
+    return WDIRAC_OK;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+const char *dirac_last_error(void) { return g_err.c_str(); }
+
+const char *dirac_version(void) { return "wdirac 0.1 (gfx950)"; }
+
+long long dirac_volume(const dirac_op *op) { return op ? op->g.V : 0; }
+
+size_t dirac_field_bytes(const dirac_op *op, int prec, int nrhs) {
+    if (!op || nrhs < 0) return 0;
+    return field_rhs_bytes(prec, op->g.V) * (size_t)nrhs;
+}
+
+int dirac_destroy(dirac_op *op) {
+    if (!op) return WDIRAC_OK;
+    void *bufs[] = {op->links64, op->clover64, op->links32, op->clover32, op->links16, op->clover16,
+                    op->links_canon};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    delete op;
+    return WDIRAC_OK;
+}
+
+int dirac_create(dirac_op **out, const int dims[4], const double *links, const double *clover, double m0,
+                 double csw, unsigned flags) {
+    if (!out) return fail(WDIRAC_EINVAL, "null handle pointer");
+    *out = nullptr;
+    if (!dims || !links) return fail(WDIRAC_EINVAL, "null dims or links");
+    long long V = 1;
+    for (int k = 0; k < 4; k++) {
+        if (dims[k] < 2) return fail(WDIRAC_EINVAL, "every lattice extent must be >= 2");
+        V *= dims[k];
+    }
+    // native offsets are 32-bit: 36 link entries per site must stay addressable
+    if (V * 36 >= (1LL << 31)) return fail(WDIRAC_EINVAL, "lattice too large (V*36 >= 2^31)");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(WDIRAC_EUNSUPPORTED, "no HIP device");
+    dirac_op *op = new dirac_op();
+    op->g = make_geom(dims);
+    op->m0 = m0;
+    op->csw = csw;
+    op->flags = flags;
+    (void)hipGetDevice(&op->device);
+    const size_t nl = (size_t)V * 36 * 16, nc = (size_t)V * 42 * 16;
+    double *lc = nullptr, *cc = nullptr;
+    int rc = WDIRAC_OK;
+    auto alloc = [&](void **p, size_t n) -> bool {
+        if (hipMalloc(p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(WDIRAC_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+            return false;
+        }
+        return true;
+    };
+    hipStream_t st = nullptr;
+    do {
+        if (!alloc((void **)&op->links64, nl) || !alloc((void **)&op->clover64, (size_t)V * 36 * 16)) break;
+        if ((flags & WDIRAC_WITH_F32) &&
+            (!alloc((void **)&op->links32, (size_t)V * 36 * 8) || !alloc((void **)&op->clover32, (size_t)V * 72 * 4)))
+            break;
+        if ((flags & WDIRAC_WITH_F16) &&
+            (!alloc((void **)&op->links16, (size_t)V * 36 * 4) || !alloc((void **)&op->clover16, (size_t)V * 72 * 2)))
+            break;
+        if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
+        lc = op->links_canon;
+        if (hipMemcpy(lc, links, nl, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(WDIRAC_EHIP, "copy of links to the device failed");
+            break;
+        }
+        if (clover) {
+            if (hipMemcpy(cc, clover, nc, hipMemcpyHostToDevice) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "copy of clover to the device failed");
+                break;
+            }
+        } else if (csw != 0.0) {
+            op->clover_from_links = true;
+            if (clover_build_launch(cc, lc, op->g, st) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "clover build launch failed");
+                break;
+            }
+        } else if (hipMemsetAsync(cc, 0, nc, st) != hipSuccess) {
+            rc = fail(WDIRAC_EHIP, "memset failed");
+            break;
+        }
+        if (operator_to_native(op, lc, cc, st) != hipSuccess) {
+            rc = fail(WDIRAC_EHIP, "layout conversion launch failed");
+            break;
+        }
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            rc = fail(WDIRAC_EHIP, std::string("operator setup failed: ") + hipGetErrorString(e));
+            break;
+        }
+    } while (false);
+    if (cc) (void)hipFree(cc);
+    if (rc != WDIRAC_OK) {
+        dirac_destroy(op);
+        return rc;
+    }
+    *out = op;
+    return WDIRAC_OK;
+}
+
+static int apply_common(const dirac_op *op, void *out, const void *in, int nrhs, int prec, bool dagger,
+                        void *stream) {
+    int rc = check_apply(op, out, in, nrhs, prec);
+    if (rc) return rc;
+    dirac_batch b{out, in, nrhs};
+    hipError_t e = dslash_launch_batches(&b, 1, prec, dagger, op->data(prec), op->g,
+                                         (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, false, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("dslash launch: ") + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbatch, int prec, int dagger,
+                        void *stream) {
+    if (!op || !batches || nbatch < 1) return fail(WDIRAC_EINVAL, "bad batched-apply arguments");
+    for (int b = 0; b < nbatch; b++) {
+        int rc = check_apply(op, batches[b].out, batches[b].in, batches[b].nrhs, prec);
+        if (rc) return rc;
+        const size_t n = field_rhs_bytes(prec, op->g.V) * (size_t)batches[b].nrhs;
+        for (int c = 0; c < nbatch; c++) {
+            if (c == b) continue;
+            const size_t m = field_rhs_bytes(prec, op->g.V) * (size_t)batches[c].nrhs;
+            if (overlap(batches[b].out, n, batches[c].out, m) || overlap(batches[b].out, n, batches[c].in, m))
+                return fail(WDIRAC_EINVAL, "an output of batch " + std::to_string(b) + " overlaps batch " +
+                                               std::to_string(c));
+        }
+    }
+    hipError_t e = dslash_launch_batches(batches, nbatch, prec, dagger != 0, op->data(prec), op->g,
+                                         (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, true, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("batched dslash launch: ") + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+int dirac_tune_set(const char *key, int value) {
+    if (!key) return fail(WDIRAC_EINVAL, "null key");
+    Tuning &t = tuning();
+    std::string k(key);
+    if (k == "block") {
+        if (value < 64 || value > 256 || value % 64) return fail(WDIRAC_EINVAL, "block must be 64, 128, 192 or 256");
+        t.block = value;
+    } else if (k == "order") {
+        if (value < 0 || value > 2) return fail(WDIRAC_EINVAL, "order must be 0, 1 or 2");
+        t.order = value;
+    } else if (k == "persistent_blocks") {
+        if (value < 8) return fail(WDIRAC_EINVAL, "persistent_blocks must be >= 8");
+        t.persistent_blocks = value;
+    } else if (k == "nr_f64" || k == "nr_f32" || k == "nr_f16s") {
+        if (value != 1 && value != 2 && value != 4) return fail(WDIRAC_EINVAL, "register block must be 1, 2 or 4");
+        t.nr[k == "nr_f64" ? 0 : k == "nr_f32" ? 1 : 2] = value;
+    } else {
+        return fail(WDIRAC_EINVAL, "unknown tuning key " + k);
+    }
+    return WDIRAC_OK;
+}
+
+int dirac_tune_get(const char *key, int *value) {
+    if (!key || !value) return fail(WDIRAC_EINVAL, "null argument");
+    const Tuning &t = tuning();
+    std::string k(key);
+    if (k == "block") *value = t.block;
+    else if (k == "order") *value = t.order;
+    else if (k == "persistent_blocks") *value = t.persistent_blocks;
+    else if (k == "nr_f64") *value = t.nr[0];
+    else if (k == "nr_f32") *value = t.nr[1];
+    else if (k == "nr_f16s") *value = t.nr[2];
+    else return fail(WDIRAC_EINVAL, "unknown tuning key " + k);
+    return WDIRAC_OK;
+}
+
+int dirac_apply(const dirac_op *op, void *out, const void *in, int nrhs, int prec, void *stream) {
+    return apply_common(op, out, in, nrhs, prec, false, stream);
+}
+
+int dirac_apply_adjoint(const dirac_op *op, void *out, const void *in, int nrhs, int prec, void *stream) {
+    return apply_common(op, out, in, nrhs, prec, true, stream);
+}
+
+int dirac_pack(const dirac_op *op, void *native, const double *canonical, int nrhs, int prec, void *stream) {
+    if (!op || !native || !canonical || nrhs < 1) return fail(WDIRAC_EINVAL, "bad pack arguments");
+    if (prec != WDIRAC_F64 && prec != WDIRAC_F32 && prec != WDIRAC_F16S) return fail(WDIRAC_EINVAL, "unknown precision");
+    if (overlap(native, field_rhs_bytes(prec, op->g.V) * nrhs, canonical, (size_t)op->g.V * 192 * nrhs))
+        return fail(WDIRAC_EINVAL, "pack buffers overlap");
+    hipError_t e = pack_launch(native, canonical, nrhs, prec, op->g.V, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("pack launch: ") + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+int dirac_unpack(const dirac_op *op, double *canonical, const void *native, int nrhs, int prec, void *stream) {
+    if (!op || !native || !canonical || nrhs < 1) return fail(WDIRAC_EINVAL, "bad unpack arguments");
+    if (prec != WDIRAC_F64 && prec != WDIRAC_F32 && prec != WDIRAC_F16S) return fail(WDIRAC_EINVAL, "unknown precision");
+    if (overlap(native, field_rhs_bytes(prec, op->g.V) * nrhs, canonical, (size_t)op->g.V * 192 * nrhs))
+        return fail(WDIRAC_EINVAL, "unpack buffers overlap");
+    hipError_t e = unpack_launch(canonical, native, nrhs, prec, op->g.V, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("unpack launch: ") + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+int dirac_clover_term(const int dims[4], const double *links_dev, double *clover_dev, void *stream) {
+    if (!dims || !links_dev || !clover_dev) return fail(WDIRAC_EINVAL, "null argument");
+    long long V = 1;
+    for (int k = 0; k < 4; k++) {
+        if (dims[k] < 2) return fail(WDIRAC_EINVAL, "every lattice extent must be >= 2");
+        V *= dims[k];
+    }
+    if (V * 42 >= (1LL << 31)) return fail(WDIRAC_EINVAL, "lattice too large");
+    Geom g = make_geom(dims);
+    hipError_t e = clover_build_launch(clover_dev, links_dev, g, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("clover launch: ") + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+}  // extern "C"

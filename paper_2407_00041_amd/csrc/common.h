@@ -1,0 +1,125 @@
+// Internal definitions shared by the HIP sources of the library (not part of
+// the C ABI).  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/wdirac.h"
+
+namespace wd {
+
+// ---------------------------------------------------------------------------
+// error state (thread-local message, status codes of the C ABI)
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+#define WD_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::wd::fail(WDIRAC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// lattice geometry: dims = {nT, nZ, nY, nX}, site = ((t*nZ + z)*nY + y)*nX + x
+struct Geom {
+    int n[4];       // nT, nZ, nY, nX
+    int V;          // volume (< 2^31 / 12 is enforced at create)
+    int stride[4];  // site stride of one step in direction mu: nZ*nY*nX, nY*nX, nX, 1
+};
+
+Geom make_geom(const int dims[4]);
+
+// ---------------------------------------------------------------------------
+// complex arithmetic in the compute type T (float or double)
+template <typename T> struct cx {
+    T r, i;
+};
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return {r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+// a * b
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b) {
+    return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+// acc + a * b
+template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.r = fma(a.r, b.r, acc.r);
+    acc.r = fma(-a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i);
+    acc.i = fma(a.i, b.r, acc.i);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cjfma(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.r = fma(a.r, b.r, acc.r);
+    acc.r = fma(a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i);
+    acc.i = fma(-a.i, b.r, acc.i);
+    return acc;
+}
+template <typename T> __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
+template <typename T> __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
+
+// ---------------------------------------------------------------------------
+// storage precisions of the native layouts (see wdirac.h)
+enum class Prec : int { F64 = WDIRAC_F64, F32 = WDIRAC_F32, F16S = WDIRAC_F16S };
+
+// bytes of one right-hand side of a native field (16-byte aligned)
+inline size_t field_rhs_bytes(int prec, long long V) {
+    switch (prec) {
+    case WDIRAC_F64: return (size_t)V * 192;
+    case WDIRAC_F32: return (size_t)V * 96;
+    case WDIRAC_F16S: return ((size_t)V * 52 + 15) / 16 * 16;
+    default: return 0;
+    }
+}
+
+// device-resident operator data at one precision
+struct OpData {
+    const void *links = nullptr;   // F64: [4][9][V] double2; F32: float2; F16: half2
+    const void *clover = nullptr;  // F64: [2][18][V] double2; F32: [2][9][V] float4; F16: [2][9][V] 4 x half
+};
+
+// wavefront-level constants
+constexpr int kWave = 64;
+
+// Work-group index -> logical tile index, so that the tiles handled by one XCD
+// are contiguous along the lattice (the hardware deals work-groups to the 8
+// XCDs round-robin, and each XCD has its own L2).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+    constexpr int kXcd = 8;
+    int q = nblocks / kXcd, r = nblocks % kXcd;
+    int k = b % kXcd, j = b / kXcd;
+    return k * q + (k < r ? k : r) + j;
+}
+
+}  // namespace wd
+
+struct dirac_op {
+    wd::Geom g;
+    double m0 = 0, csw = 0;
+    unsigned flags = 0;
+    bool clover_from_links = false;
+    int device = 0;
+    // device buffers (owned)
+    void *links64 = nullptr, *clover64 = nullptr;
+    void *links32 = nullptr, *clover32 = nullptr;
+    void *links16 = nullptr, *clover16 = nullptr;
+    double *links_canon = nullptr;  // canonical FP64 links (force kernels)
+    wd::OpData data(int prec) const {
+        wd::OpData d;
+        if (prec == WDIRAC_F64) { d.links = links64; d.clover = clover64; }
+        if (prec == WDIRAC_F32) { d.links = links32; d.clover = clover32; }
+        if (prec == WDIRAC_F16S) { d.links = links16; d.clover = clover16; }
+        return d;
+    }
+};

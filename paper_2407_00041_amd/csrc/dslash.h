@@ -1,0 +1,54 @@
+// Launch-side types of the stencil kernels (internal).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace wd {
+
+// A register block: up to NR right-hand sides handled by the same lanes.
+template <int NR> struct Chunk {
+    const void *in[NR];
+    void *out[NR];
+    int nr;  // valid entries; the rest repeat the last valid pointers
+};
+
+constexpr int kMaxChunks = 24;  // register blocks per launch (kernel-argument budget)
+
+template <int NR> struct ChunkTable {
+    Chunk<NR> c[kMaxChunks];
+    int nchunks;
+};
+
+// Tile orders (site range of a tile slot)
+constexpr int kOrderLinear = 0;    // tile slot = tile, lexicographic
+constexpr int kOrderXcdChunk = 1;  // each XCD gets a contiguous 1/8 of the lattice
+constexpr int kOrderTSweep = 2;    // each XCD gets 1/8 of every T-slice; slices in order
+
+struct TileMap {
+    int order;
+    int block;            // sites per tile = threads per work-group
+    int V;
+    int slice;            // sites per T-slice
+    int tiles_per_range;  // kOrderTSweep: tiles per (slice, XCD) range
+    int ntiles;           // tile slots holding sites
+    int nslots;           // ntiles rounded up to a multiple of 8
+};
+
+TileMap make_tilemap(const Geom &g, int order, int block);
+
+// Process-wide launch parameters (set through dirac_tune_set).
+struct Tuning {
+    int block = 256;             // threads per work-group: 64, 128, 192 or 256
+    int order = kOrderTSweep;    // tile order
+    int persistent_blocks = 2048;  // grid of persistent (batched) launches
+    int nr[3] = {2, 2, 2};       // register block size per precision (1, 2 or 4)
+};
+
+Tuning &tuning();
+
+hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
+                                 const Geom &g, int apbc, bool persistent, hipStream_t st);
+
+}  // namespace wd

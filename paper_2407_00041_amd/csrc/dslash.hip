@@ -1,0 +1,378 @@
+// Fused Wilson-clover stencil (Eq. (1.13); D = D_sc - D_nc of Eqs. (2.5)-(2.7)).
+//
+// One lane owns one lattice site and a register block of NR right-hand
+// sides, and performs in registers what the paper splits into 16 kernel
+// launches plus a self-coupling kernel (Algorithm 4 and the clover kernel):
+// the self-coupling product A(x) psi(x), then for each of the 8 neighbours
+// the spin projection to a half-spinor h = u + s B_mu d (the prp kernels of
+// Listing 4.2), the SU(3) product with U_mu(x) or U_mu(x-mu)^H, and the
+// reconstruction of the lower half as s B_mu^H (U h) (the back-substitution
+// of Sec. 2.2).  Every link and clover entry is loaded once per site and
+// register block and used for all NR right-hand sides; nothing but the
+// result is written.
+//
+// Gamma basis: gamma_mu = [[0, B_mu], [B_mu^H, 0]], B_T = 1, B_Z = -i s3,
+// B_Y = -i s2, B_X = -i s1, so the projector (I + s gamma_mu) maps
+// (u, d) -> (h, s B_mu^H h) with h = u + s B_mu d.  D uses s = -1 for the
+// forward hop and s = +1 for the backward hop; D^H swaps them.
+//
+// Work decomposition: a work item is (tile of up to 256 consecutive sites,
+// register block of right-hand sides).  Items are dealt so that the
+// work-group running on XCD k (work-groups go to the 8 XCDs round-robin)
+// always gets tiles of the same 1/8 of every T-slice, and all XCDs advance
+// through the T-slices together: the T-neighbours of a slice are then read
+// while the slice is still in the Infinity Cache, and the Z-neighbours
+// mostly come from the same XCD's L2.  The register blocks of one tile are
+// consecutive items on the same XCD, so their shared links and clover stay
+// in that XCD's L2.  With fewer work-groups than items the kernel is
+// persistent: each work-group strides through the item list.
+#include "spinor_io.h"
+#include "dslash.h"
+
+namespace wd {
+
+// h = f (u + S B_mu d)  (u = spins 0,1; d = spins 2,3)
+template <int MU, int S, typename T>
+__device__ __forceinline__ void project(const cx<T> p[12], cx<T> h[6], T f) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<T> d0 = p[6 + c], d1 = p[9 + c], b0, b1;
+        if (MU == 0) { b0 = d0; b1 = d1; }
+        else if (MU == 1) { b0 = times_mi(d0); b1 = times_i(d1); }
+        else if (MU == 2) { b0 = mk<T>(-d1.r, -d1.i); b1 = d0; }
+        else { b0 = times_mi(d1); b1 = times_mi(d0); }
+        if (S > 0) { h[c] = f * (p[c] + b0); h[3 + c] = f * (p[3 + c] + b1); }
+        else { h[c] = f * (p[c] - b0); h[3 + c] = f * (p[3 + c] - b1); }
+    }
+}
+
+// upper += chi; lower += S B_mu^H chi
+template <int MU, int S, typename T>
+__device__ __forceinline__ void reconstruct(cx<T> acc[12], const cx<T> chi[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<T> c0 = chi[c], c1 = chi[3 + c], l0, l1;
+        acc[c] = acc[c] + c0;
+        acc[3 + c] = acc[3 + c] + c1;
+        if (MU == 0) { l0 = c0; l1 = c1; }
+        else if (MU == 1) { l0 = times_i(c0); l1 = times_mi(c1); }
+        else if (MU == 2) { l0 = c1; l1 = mk<T>(-c0.r, -c0.i); }
+        else { l0 = times_i(c1); l1 = times_i(c0); }
+        if (S > 0) { acc[6 + c] = acc[6 + c] + l0; acc[9 + c] = acc[9 + c] + l1; }
+        else { acc[6 + c] = acc[6 + c] - l0; acc[9 + c] = acc[9 + c] - l1; }
+    }
+}
+
+// chi_s = U h_s (DAGU = false) or U^H h_s (DAGU = true), s = 0, 1
+template <bool DAGU, typename T>
+__device__ __forceinline__ void su3_mul(const cx<T> U[9], const cx<T> h[6], cx<T> chi[6]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; sp++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                acc = DAGU ? cjfma(acc, U[3 * b + a], h[3 * sp + b]) : cfma(acc, U[3 * a + b], h[3 * sp + b]);
+            chi[3 * sp + a] = acc;
+        }
+}
+
+// y = A_blk x for one 6x6 Hermitian chirality block (real diagonal d, strict
+// upper u in row-major pair order)
+template <typename T>
+__device__ __forceinline__ void clover_block(const T d[6], const cx<T> u[15], const cx<T> x[6], cx<T> y[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = d[i] * x[i];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i + 1; j < 6; j++, k++) {
+            y[i] = cfma(y[i], u[k], x[j]);
+            y[j] = cjfma(y[j], u[k], x[i]);
+        }
+}
+
+struct Nbr {
+    int fwd[4], bwd[4];
+    bool fwd_wrapT, bwd_wrapT;
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geom &g, int s) {
+    Nbr n;
+    int c[4];
+    int r = s;
+    c[3] = r % g.n[3]; r /= g.n[3];
+    c[2] = r % g.n[2]; r /= g.n[2];
+    c[1] = r % g.n[1];
+    c[0] = r / g.n[1];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        int st = g.stride[mu], L = g.n[mu];
+        n.fwd[mu] = (c[mu] == L - 1) ? s - (L - 1) * st : s + st;
+        n.bwd[mu] = (c[mu] == 0) ? s + (L - 1) * st : s - st;
+    }
+    n.fwd_wrapT = c[0] == g.n[0] - 1;
+    n.bwd_wrapT = c[0] == 0;
+    return n;
+}
+
+// Scheduling fences between hops bound how far the compiler hoists the
+// loads of later hops (and with them the register pressure).
+#ifndef WD_HOP_FENCE
+#define WD_HOP_FENCE 1
+#endif
+__device__ __forceinline__ void hop_fence(int level) {
+    if (WD_HOP_FENCE >= level) __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int P, int MU, bool DAG, int NR>
+__device__ __forceinline__ void hop_pair(const Chunk<NR> &ch, const OpData &d, int V, int s, const Nbr &nb,
+                                         bool apbc, cx<typename Store<P>::T> (&acc)[NR][12]) {
+    using T = typename Store<P>::T;
+    constexpr int SF = DAG ? +1 : -1;  // forward projector (I + SF gamma)
+    constexpr int SB = -SF;            // backward projector
+    cx<T> U[9];
+    // forward: -1/2 (I + SF gamma) (x) U_mu(x) psi(x+mu)
+    {
+        const T f = (MU == 0 && apbc && nb.fwd_wrapT) ? T(0.5) : T(-0.5);
+        Store<P>::load_link(d.links, V, MU, s, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < ch.nr) {
+                cx<T> p[12], h[6], chi[6];
+                Store<P>::load_spinor(ch.in[r], V, nb.fwd[MU], p);
+                project<MU, SF>(p, h, f);
+                su3_mul<false>(U, h, chi);
+                reconstruct<MU, SF>(acc[r], chi);
+            }
+        }
+    }
+    hop_fence(2);
+    // backward: -1/2 (I + SB gamma) (x) U_mu(x-mu)^H psi(x-mu)
+    {
+        const T f = (MU == 0 && apbc && nb.bwd_wrapT) ? T(0.5) : T(-0.5);
+        Store<P>::load_link(d.links, V, MU, nb.bwd[MU], U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < ch.nr) {
+                cx<T> p[12], h[6], chi[6];
+                Store<P>::load_spinor(ch.in[r], V, nb.bwd[MU], p);
+                project<MU, SB>(p, h, f);
+                su3_mul<true>(U, h, chi);
+                reconstruct<MU, SB>(acc[r], chi);
+            }
+        }
+    }
+}
+
+template <int P, bool DAG, int NR>
+__device__ __forceinline__ void site_apply(const Chunk<NR> &ch, const OpData &d, const Geom &g, int s, bool apbc) {
+    using T = typename Store<P>::T;
+    const int V = g.V;
+    cx<T> acc[NR][12];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        T dd[6];
+        cx<T> uu[15];
+        Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < ch.nr) {
+                cx<T> p[6];
+                Store<P>::load_half(ch.in[r], V, s, b, p);
+                clover_block(dd, uu, p, &acc[r][6 * b]);
+            }
+        }
+    }
+    const Nbr nb = neighbours(g, s);
+    hop_fence(1);
+    hop_pair<P, 0, DAG, NR>(ch, d, V, s, nb, apbc, acc);
+    hop_fence(1);
+    hop_pair<P, 1, DAG, NR>(ch, d, V, s, nb, apbc, acc);
+    hop_fence(1);
+    hop_pair<P, 2, DAG, NR>(ch, d, V, s, nb, apbc, acc);
+    hop_fence(1);
+    hop_pair<P, 3, DAG, NR>(ch, d, V, s, nb, apbc, acc);
+    hop_fence(1);
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+        if (r < ch.nr) Store<P>::store_spinor(ch.out[r], V, s, acc[r]);
+}
+
+// site range [lo, hi) of tile slot vb (see TileMap in dslash.h)
+__device__ __forceinline__ void tile_range(const TileMap &m, int vb, int &lo, int &hi) {
+    if (m.order == kOrderTSweep) {
+        const int k = vb & 7, j = vb >> 3;
+        const int t = j / m.tiles_per_range, tile = j - t * m.tiles_per_range;
+        const int base = t * m.slice;
+        const int r0 = base + (int)(((long long)k * m.slice) >> 3);
+        const int r1 = base + (int)(((long long)(k + 1) * m.slice) >> 3);
+        lo = r0 + tile * m.block;
+        hi = min(lo + m.block, r1);
+    } else {
+        int tile = vb;
+        if (m.order == kOrderXcdChunk) {
+            // contiguous ranges of tiles per XCD
+            const int q = m.ntiles >> 3, rr = m.ntiles & 7;
+            const int k = vb & 7, j = vb >> 3;
+            tile = k * q + (k < rr ? k : rr) + j;
+        }
+        lo = tile * m.block;
+        hi = min(lo + m.block, m.V);
+    }
+}
+
+// Minimum waves per SIMD the register allocation must allow, per precision
+// and register block (the compiler otherwise trades occupancy for early
+// load hoisting).  Values from launch sweeps at 48^3 x 96.
+#ifndef WD_OCC_F64_1
+#define WD_OCC_F64_1 2
+#endif
+#ifndef WD_OCC_F64_2
+#define WD_OCC_F64_2 2
+#endif
+#ifndef WD_OCC_F64_4
+#define WD_OCC_F64_4 1
+#endif
+#ifndef WD_OCC_F32_1
+#define WD_OCC_F32_1 4
+#endif
+#ifndef WD_OCC_F32_2
+#define WD_OCC_F32_2 4
+#endif
+#ifndef WD_OCC_F32_4
+#define WD_OCC_F32_4 3
+#endif
+#ifndef WD_OCC_F16_1
+#define WD_OCC_F16_1 6
+#endif
+#ifndef WD_OCC_F16_2
+#define WD_OCC_F16_2 4
+#endif
+#ifndef WD_OCC_F16_4
+#define WD_OCC_F16_4 3
+#endif
+template <int P, int NR> constexpr int occupancy() {
+    return P == WDIRAC_F64 ? (NR == 1 ? WD_OCC_F64_1 : NR == 2 ? WD_OCC_F64_2 : WD_OCC_F64_4)
+         : P == WDIRAC_F32 ? (NR == 1 ? WD_OCC_F32_1 : NR == 2 ? WD_OCC_F32_2 : WD_OCC_F32_4)
+                           : (NR == 1 ? WD_OCC_F16_1 : NR == 2 ? WD_OCC_F16_2 : WD_OCC_F16_4);
+}
+
+template <int P, bool DAG, int NR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(occupancy<P, NR>())))
+void dslash_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int apbc) {
+    const int nitems = m.nslots * tab.nchunks;   // nslots is a multiple of 8
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        // XCD-affine dealing: w % 8 == vb % 8, consecutive items of one XCD
+        // walk through the register blocks of a tile before the next tile
+        const int xcd = w & 7, q = w >> 3;
+        const int vb = (q / tab.nchunks) * 8 + xcd;
+        const int c = q - (q / tab.nchunks) * tab.nchunks;
+        int lo, hi;
+        tile_range(m, vb, lo, hi);
+        const int s = lo + (int)threadIdx.x;
+        if (s < hi) site_apply<P, DAG, NR>(tab.c[c], d, g, s, apbc != 0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+TileMap make_tilemap(const Geom &g, int order, int block) {
+    TileMap m;
+    m.order = order;
+    m.block = block;
+    m.V = g.V;
+    m.slice = g.V / g.n[0];
+    if (order == kOrderTSweep) {
+        const int per_range = (m.slice + 7) / 8;
+        m.tiles_per_range = (per_range + block - 1) / block;
+        m.ntiles = g.n[0] * 8 * m.tiles_per_range;
+    } else {
+        m.tiles_per_range = 0;
+        m.ntiles = (g.V + block - 1) / block;
+    }
+    m.nslots = (m.ntiles + 7) / 8 * 8;
+    return m;
+}
+
+static Tuning g_tuning;
+
+Tuning &tuning() { return g_tuning; }
+
+template <int P, bool DAG, int NR>
+static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpData &d, const Geom &g, int apbc,
+                                bool persistent, hipStream_t st) {
+    const Tuning &tu = g_tuning;
+    const TileMap m = make_tilemap(g, tu.order, tu.block);
+    for (size_t c0 = 0; c0 < chunks.size(); c0 += kMaxChunks) {
+        ChunkTable<NR> tab;
+        tab.nchunks = (int)std::min(chunks.size() - c0, (size_t)kMaxChunks);
+        for (int i = 0; i < tab.nchunks; i++) tab.c[i] = chunks[c0 + i];
+        long long items = (long long)m.nslots * tab.nchunks;
+        long long grid = items;
+        if (persistent && tu.persistent_blocks > 0 && grid > tu.persistent_blocks)
+            grid = (tu.persistent_blocks + 7) / 8 * 8;
+        if (grid > (1LL << 30)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((dslash_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d, g, m,
+                           apbc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Split batches into register blocks of at most NR right-hand sides.
+template <int P, bool DAG, int NR>
+static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
+                            bool persistent, hipStream_t st) {
+    const size_t rb = field_rhs_bytes(P, g.V);
+    std::vector<Chunk<NR>> chunks;
+    for (int b = 0; b < nbatch; b++) {
+        const char *in = static_cast<const char *>(batches[b].in);
+        char *out = static_cast<char *>(batches[b].out);
+        for (int r0 = 0; r0 < batches[b].nrhs; r0 += NR) {
+            Chunk<NR> c;
+            c.nr = std::min(NR, batches[b].nrhs - r0);
+            for (int r = 0; r < NR; r++) {
+                const int rr = r0 + std::min(r, c.nr - 1);
+                c.in[r] = in + rr * rb;
+                c.out[r] = out + rr * rb;
+            }
+            chunks.push_back(c);
+        }
+    }
+    return launch_chunks<P, DAG, NR>(chunks, d, g, apbc, persistent, st);
+}
+
+template <int P, bool DAG>
+static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
+                           bool persistent, hipStream_t st) {
+    int total = 0;
+    for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
+    int nr = g_tuning.nr[P];
+    if (total == 1) nr = 1;
+    if (nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, st);
+    if (nr >= 2) return launch_nr<P, DAG, 2>(batches, nbatch, d, g, apbc, persistent, st);
+    return launch_nr<P, DAG, 1>(batches, nbatch, d, g, apbc, persistent, st);
+}
+
+hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
+                                 const Geom &g, int apbc, bool persistent, hipStream_t st) {
+    switch (prec) {
+    case WDIRAC_F64:
+        return dagger ? launch_p<WDIRAC_F64, true>(batches, nbatch, d, g, apbc, persistent, st)
+                      : launch_p<WDIRAC_F64, false>(batches, nbatch, d, g, apbc, persistent, st);
+    case WDIRAC_F32:
+        return dagger ? launch_p<WDIRAC_F32, true>(batches, nbatch, d, g, apbc, persistent, st)
+                      : launch_p<WDIRAC_F32, false>(batches, nbatch, d, g, apbc, persistent, st);
+    case WDIRAC_F16S:
+        return dagger ? launch_p<WDIRAC_F16S, true>(batches, nbatch, d, g, apbc, persistent, st)
+                      : launch_p<WDIRAC_F16S, false>(batches, nbatch, d, g, apbc, persistent, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wd

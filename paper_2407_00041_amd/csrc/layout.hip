@@ -1,0 +1,201 @@
+// Layout conversion kernels: canonical complex128 arrays <-> native
+// structure-of-arrays layouts (the paper's componentwise storage, Eq. (4.1)
+// of Sec. 4.5, here with one 16-byte vector per (block, site)), and the
+// reduced-precision copies of the operator data.
+//
+// Each thread owns one site: it reads the site's contiguous canonical record
+// (whole cache lines per wavefront) and writes each native component at
+// consecutive sites across the wavefront.
+#include "spinor_io.h"
+
+namespace wd {
+
+// canonical spinor [V][12] c128 (one rhs) -> native
+template <int P>
+__global__ __launch_bounds__(256) void pack_kernel(void *__restrict__ nat, const double2 *__restrict__ can,
+                                                   int V, size_t rhs_bytes) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *src = can + (size_t)blockIdx.y * 12 * V + (size_t)12 * s;
+    char *dst = static_cast<char *>(nat) + (size_t)blockIdx.y * rhs_bytes;
+    if (P == WDIRAC_F64) {
+        double2 *o = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[(size_t)k * V + s] = src[k];
+    } else if (P == WDIRAC_F32) {
+        float4 *o = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            double2 a = src[2 * k], b = src[2 * k + 1];
+            o[(size_t)k * V + s] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        }
+    } else {
+        // F16S: scale = fp32(max |component|), q = fp16_rn(fp32(v) / scale)
+        float v[24];
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 a = src[k];
+            v[2 * k] = (float)a.x;
+            v[2 * k + 1] = (float)a.y;
+            m = fmaxf(m, fmaxf(fabsf(v[2 * k]), fabsf(v[2 * k + 1])));
+        }
+        half8 *o = reinterpret_cast<half8 *>(dst);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8 q;
+#pragma unroll
+            for (int j = 0; j < 8; j++) q[j] = m > 0.f ? (_Float16)(v[8 * k + j] / m) : (_Float16)0.f;
+            o[(size_t)k * V + s] = q;
+        }
+        reinterpret_cast<float *>(dst + (size_t)48 * V)[s] = m;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void unpack_kernel(double2 *__restrict__ can, const void *__restrict__ nat,
+                                                     int V, size_t rhs_bytes) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    double2 *dst = can + (size_t)blockIdx.y * 12 * V + (size_t)12 * s;
+    const char *src = static_cast<const char *>(nat) + (size_t)blockIdx.y * rhs_bytes;
+    if (P == WDIRAC_F64) {
+        const double2 *i = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+        for (int k = 0; k < 12; k++) dst[k] = i[(size_t)k * V + s];
+    } else if (P == WDIRAC_F32) {
+        const float4 *i = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 a = i[(size_t)k * V + s];
+            dst[2 * k] = make_double2(a.x, a.y);
+            dst[2 * k + 1] = make_double2(a.z, a.w);
+        }
+    } else {
+        const half8 *i = reinterpret_cast<const half8 *>(src);
+        float m = reinterpret_cast<const float *>(src + (size_t)48 * V)[s];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8 q = i[(size_t)k * V + s];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                dst[4 * k + j] = make_double2((double)(m * (float)q[2 * j]), (double)(m * (float)q[2 * j + 1]));
+        }
+    }
+}
+
+hipError_t pack_launch(void *nat, const double *can, int nrhs, int prec, int V, hipStream_t st) {
+    dim3 grid((V + 255) / 256, nrhs);
+    size_t rb = field_rhs_bytes(prec, V);
+    const double2 *c = reinterpret_cast<const double2 *>(can);
+    switch (prec) {
+    case WDIRAC_F64: hipLaunchKernelGGL(pack_kernel<WDIRAC_F64>, grid, dim3(256), 0, st, nat, c, V, rb); break;
+    case WDIRAC_F32: hipLaunchKernelGGL(pack_kernel<WDIRAC_F32>, grid, dim3(256), 0, st, nat, c, V, rb); break;
+    case WDIRAC_F16S: hipLaunchKernelGGL(pack_kernel<WDIRAC_F16S>, grid, dim3(256), 0, st, nat, c, V, rb); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t unpack_launch(double *can, const void *nat, int nrhs, int prec, int V, hipStream_t st) {
+    dim3 grid((V + 255) / 256, nrhs);
+    size_t rb = field_rhs_bytes(prec, V);
+    double2 *c = reinterpret_cast<double2 *>(can);
+    switch (prec) {
+    case WDIRAC_F64: hipLaunchKernelGGL(unpack_kernel<WDIRAC_F64>, grid, dim3(256), 0, st, c, nat, V, rb); break;
+    case WDIRAC_F32: hipLaunchKernelGGL(unpack_kernel<WDIRAC_F32>, grid, dim3(256), 0, st, c, nat, V, rb); break;
+    case WDIRAC_F16S: hipLaunchKernelGGL(unpack_kernel<WDIRAC_F16S>, grid, dim3(256), 0, st, c, nat, V, rb); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// operator data
+
+// canonical links [V][4][3][3] c128 -> native FP64 [4][9][V] double2
+__global__ __launch_bounds__(256) void links_to_native(double2 *__restrict__ nat, const double2 *__restrict__ can,
+                                                       int V) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int e = 0; e < 36; e++) nat[(size_t)e * V + s] = can[(size_t)36 * s + e];
+}
+
+// canonical unit clover [V][42] c128 -> native FP64 A(x) = (4+m0) I + csw C(x):
+// [2 blocks][18][V] double2, per block 3 vectors of diagonal reals then 15
+// strict-upper complex entries.
+__global__ __launch_bounds__(256) void clover_to_native(double2 *__restrict__ nat, const double2 *__restrict__ can,
+                                                        int V, double diag, double csw) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *c = can + (size_t)42 * s;
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        double2 *o = nat + (size_t)b * 18 * V;
+#pragma unroll
+        for (int e = 0; e < 3; e++)
+            o[(size_t)e * V + s] = make_double2(diag + csw * c[21 * b + 2 * e].x, diag + csw * c[21 * b + 2 * e + 1].x);
+#pragma unroll
+        for (int e = 0; e < 15; e++) {
+            double2 u = c[21 * b + 6 + e];
+            o[(size_t)(3 + e) * V + s] = make_double2(csw * u.x, csw * u.y);
+        }
+    }
+}
+
+// native FP64 links -> FP32 float2 / FP16 half2 (same [4][9][V] order)
+__global__ __launch_bounds__(256) void links_narrow(float2 *__restrict__ o32, half2v *__restrict__ o16,
+                                                    const double2 *__restrict__ nat, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 a = nat[i];
+    if (o32) o32[i] = make_float2((float)a.x, (float)a.y);
+    if (o16) {
+        half2v h;
+        h[0] = (_Float16)a.x;
+        h[1] = (_Float16)a.y;
+        o16[i] = h;
+    }
+}
+
+// native FP64 clover [2][18][V] double2 -> [2][9][V] float4 / 4 x half
+// (the block's 36 reals in the same order, four per vector)
+__global__ __launch_bounds__(256) void clover_narrow(float4 *__restrict__ o32, half4 *__restrict__ o16,
+                                                     const double2 *__restrict__ nat, int V) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            double2 a = nat[(size_t)(b * 18 + 2 * q) * V + s];
+            double2 c = nat[(size_t)(b * 18 + 2 * q + 1) * V + s];
+            if (o32) o32[(size_t)(b * 9 + q) * V + s] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+            if (o16) {
+                half4 h;
+                h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)c.x; h[3] = (_Float16)c.y;
+                o16[(size_t)(b * 9 + q) * V + s] = h;
+            }
+        }
+}
+
+hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const double *clover_can_dev,
+                              hipStream_t st) {
+    int V = op->g.V;
+    dim3 grid((V + 255) / 256);
+    hipLaunchKernelGGL(links_to_native, grid, dim3(256), 0, st, (double2 *)op->links64,
+                       (const double2 *)links_can_dev, V);
+    hipLaunchKernelGGL(clover_to_native, grid, dim3(256), 0, st, (double2 *)op->clover64,
+                       (const double2 *)clover_can_dev, V, 4.0 + op->m0, op->csw);
+    if (op->links32 || op->links16) {
+        size_t n = (size_t)36 * V;
+        hipLaunchKernelGGL(links_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (float2 *)op->links32, (half2v *)op->links16, (const double2 *)op->links64, n);
+        hipLaunchKernelGGL(clover_narrow, grid, dim3(256), 0, st, (float4 *)op->clover32, (half4 *)op->clover16,
+                           (const double2 *)op->clover64, V);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace wd

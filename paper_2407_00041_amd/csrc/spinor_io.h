@@ -1,0 +1,192 @@
+// Loads and stores of native-layout spinors, links and self-coupling matrices
+// (layouts documented in wdirac.h and common.h).  Every access is one
+// 16-, 8- or 4-byte vector per lane at consecutive sites, so a wavefront
+// touches whole cache lines.
+#pragma once
+
+#include "common.h"
+
+namespace wd {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+template <int P> struct Store;
+
+// ---------------------------------------------------------------- FP64
+template <> struct Store<WDIRAC_F64> {
+    using T = double;
+    static __device__ __forceinline__ void load_spinor(const void *base, int V, int s, cx<T> v[12]) {
+        const double2 *p = static_cast<const double2 *>(base);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 a = p[(size_t)k * V + s];
+            v[k] = {a.x, a.y};
+        }
+    }
+    // components [6 h, 6 h + 6) (chirality block h)
+    static __device__ __forceinline__ void load_half(const void *base, int V, int s, int h, cx<T> v[6]) {
+        const double2 *p = static_cast<const double2 *>(base) + (size_t)6 * h * V;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            double2 a = p[(size_t)k * V + s];
+            v[k] = {a.x, a.y};
+        }
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int V, int s, const cx<T> v[12]) {
+        d2v *p = static_cast<d2v *>(base);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2v a = {v[k].r, v[k].i};
+            __builtin_nontemporal_store(a, &p[(size_t)k * V + s]);
+        }
+    }
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+        const double2 *p = static_cast<const double2 *>(base);
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            double2 a = p[(size_t)(mu * 9 + e) * V + s];
+            U[e] = {a.x, a.y};
+        }
+    }
+    // block b of A(x): 6 real diagonal entries and 15 complex strict-upper entries
+    static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
+                                                       cx<T> u[15]) {
+        const double2 *p = static_cast<const double2 *>(base) + (size_t)b * 18 * V;
+#pragma unroll
+        for (int e = 0; e < 3; e++) {
+            double2 a = p[(size_t)e * V + s];
+            d[2 * e] = a.x;
+            d[2 * e + 1] = a.y;
+        }
+#pragma unroll
+        for (int e = 0; e < 15; e++) {
+            double2 a = p[(size_t)(3 + e) * V + s];
+            u[e] = {a.x, a.y};
+        }
+    }
+};
+
+// ---------------------------------------------------------------- FP32
+template <> struct Store<WDIRAC_F32> {
+    using T = float;
+    static __device__ __forceinline__ void load_spinor(const void *base, int V, int s, cx<T> v[12]) {
+        const float4 *p = static_cast<const float4 *>(base);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 a = p[(size_t)k * V + s];
+            v[2 * k] = {a.x, a.y};
+            v[2 * k + 1] = {a.z, a.w};
+        }
+    }
+    static __device__ __forceinline__ void load_half(const void *base, int V, int s, int h, cx<T> v[6]) {
+        const float4 *p = static_cast<const float4 *>(base) + (size_t)3 * h * V;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            float4 a = p[(size_t)k * V + s];
+            v[2 * k] = {a.x, a.y};
+            v[2 * k + 1] = {a.z, a.w};
+        }
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int V, int s, const cx<T> v[12]) {
+        f4v *p = static_cast<f4v *>(base);
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            f4v a = {v[2 * k].r, v[2 * k].i, v[2 * k + 1].r, v[2 * k + 1].i};
+            __builtin_nontemporal_store(a, &p[(size_t)k * V + s]);
+        }
+    }
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+        const float2 *p = static_cast<const float2 *>(base);
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            float2 a = p[(size_t)(mu * 9 + e) * V + s];
+            U[e] = {a.x, a.y};
+        }
+    }
+    static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
+                                                       cx<T> u[15]) {
+        const float4 *p = static_cast<const float4 *>(base) + (size_t)b * 9 * V;
+        float r[36];
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            float4 a = p[(size_t)e * V + s];
+            r[4 * e] = a.x; r[4 * e + 1] = a.y; r[4 * e + 2] = a.z; r[4 * e + 3] = a.w;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) d[k] = r[k];
+#pragma unroll
+        for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    }
+};
+
+// ---------------------------------------------------------------- FP16 + per-site scale
+template <> struct Store<WDIRAC_F16S> {
+    using T = float;
+    static __device__ __forceinline__ const float *scales(const void *base, int V) {
+        return reinterpret_cast<const float *>(static_cast<const char *>(base) + (size_t)48 * V);
+    }
+    static __device__ __forceinline__ void load_spinor(const void *base, int V, int s, cx<T> v[12]) {
+        const half8 *p = static_cast<const half8 *>(base);
+        float sc = scales(base, V)[s];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8 a = p[(size_t)k * V + s];
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[4 * k + j] = {sc * (float)a[2 * j], sc * (float)a[2 * j + 1]};
+        }
+    }
+    static __device__ __forceinline__ void load_half(const void *base, int V, int s, int h, cx<T> v[6]) {
+        cx<T> w[12];
+        load_spinor(base, V, s, w);
+#pragma unroll
+        for (int k = 0; k < 6; k++) v[k] = h ? w[6 + k] : w[k];
+    }
+    static __device__ __forceinline__ void store_spinor(void *base, int V, int s, const cx<T> v[12]) {
+        half8 *p = static_cast<half8 *>(base);
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].r), fabsf(v[k].i)));
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            half8 a;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                a[2 * j] = m > 0.f ? (_Float16)(v[4 * k + j].r / m) : (_Float16)0.f;
+                a[2 * j + 1] = m > 0.f ? (_Float16)(v[4 * k + j].i / m) : (_Float16)0.f;
+            }
+            __builtin_nontemporal_store(a, &p[(size_t)k * V + s]);
+        }
+        float *sp = reinterpret_cast<float *>(static_cast<char *>(base) + (size_t)48 * V);
+        __builtin_nontemporal_store(m, &sp[s]);
+    }
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+        const half2v *p = static_cast<const half2v *>(base);
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            half2v a = p[(size_t)(mu * 9 + e) * V + s];
+            U[e] = {(float)a[0], (float)a[1]};
+        }
+    }
+    static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
+                                                       cx<T> u[15]) {
+        const half4 *p = static_cast<const half4 *>(base) + (size_t)b * 9 * V;
+        float r[36];
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            half4 a = p[(size_t)e * V + s];
+            r[4 * e] = (float)a[0]; r[4 * e + 1] = (float)a[1];
+            r[4 * e + 2] = (float)a[2]; r[4 * e + 3] = (float)a[3];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) d[k] = r[k];
+#pragma unroll
+        for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    }
+};
+
+}  // namespace wd

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point that include/*.h
+declares; argument checks that need no device run on the CPU."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2407_00041_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\([^;{]*\)\s*;", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ["dirac_create", "dirac_destroy", "dirac_apply", "dirac_apply_adjoint", "dirac_apply_batched",
+              "dirac_pack", "dirac_unpack", "fgmres_solve", "fgmres_workspace_bytes", "dirac_force",
+              "dirac_clover_term", "dirac_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(_lib.SIGNATURES) >= declared_functions()
+
+
+def test_argument_errors_without_device():
+    lib = _lib.load()
+    assert lib.dirac_apply(None, None, None, 1, 0, None) == _lib.EINVAL
+    assert b"null" in lib.dirac_last_error()
+    assert lib.dirac_apply_adjoint(None, None, None, 1, 0, None) == _lib.EINVAL
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int * 4)(4, 4, 1, 4)
+    assert lib.dirac_create(ctypes.byref(h), bad, ctypes.c_void_p(1), None, 0.0, 0.0, 0) == _lib.EINVAL
+    assert h.value is None
+    assert lib.dirac_create(None, bad, None, None, 0.0, 0.0, 0) == _lib.EINVAL
+    assert lib.dirac_destroy(None) == 0
+    assert lib.dirac_volume(None) == 0
+    assert lib.dirac_field_bytes(None, 0, 1) == 0
+    assert lib.dirac_pack(None, None, None, 1, 0, None) == _lib.EINVAL
+    assert lib.dirac_clover_term(None, None, None, None) == _lib.EINVAL
+
+
+def test_product_path_has_no_fallback(monkeypatch, tmp_path):
+    """Without the shared object the binding raises instead of computing."""
+    monkeypatch.setattr(_lib, "SO_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.load()
