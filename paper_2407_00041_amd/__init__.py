@@ -139,6 +139,30 @@ class DiracOp:
         self.apply_native(b, a, nrhs, prec, dagger)
         return self.unpack(b, prec, nrhs).reshape(shape)
 
+    def solve(self, b: torch.Tensor, nrhs: int = 1, x0: torch.Tensor | None = None, restart: int = 20,
+              tol: float = 1e-10, maxit: int = 10000, mode="f64", inner_restart: int = 30,
+              inner_tol: float = 1e-2, inner_maxit: int = 30, stream=None):
+        """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
+        "mixed_f16s".  Returns (x native FP64, list of per-RHS stats dicts, status)."""
+        modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S}
+        p = _lib.FgmresParams(int(restart), float(tol), int(maxit), modes[mode] if isinstance(mode, str) else int(mode),
+                              int(inner_restart), float(inner_tol), int(inner_maxit))
+        nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
+        if nbytes == 0:
+            raise WdiracError(-1, "fgmres_workspace_bytes")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        stats = (_lib.FgmresStats * int(nrhs))()
+        rc = check(self.lib.fgmres_solve(self.handle, _ptr(x), _ptr(b), int(nrhs), ctypes.byref(p), stats,
+                                         _ptr(work), nbytes, _stream(stream)), "fgmres_solve")
+        out = []
+        for s in stats:
+            out.append({"applies": s.applies, "inner_applies": s.inner_applies, "restarts": s.restarts,
+                        "converged": bool(s.converged), "breakdown": bool(s.breakdown),
+                        "true_residual": s.true_residual, "seconds": s.seconds,
+                        "hist": [s.hist[i] for i in range(s.nhist)]})
+        return x, out, rc
+
     def force(self, eta: torch.Tensor, x: torch.Tensor, nrhs: int = 1, raw: bool = False,
               stream=None) -> torch.Tensor:
         """dL/dU for L = Re sum <eta, D x>; eta, x native FP64.  [V, 4, 3, 3] c128."""

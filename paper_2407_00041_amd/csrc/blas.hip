@@ -1,0 +1,344 @@
+// Vector kernels of the Krylov solvers (the non-operator work of Algorithm 2:
+// inner products, norms, orthogonalisation updates, scaling, the solution
+// update and precision conversion).
+//
+// A field is treated as a flat array of N = 12 V complex numbers (the native
+// FP64 and FP32 layouts are dense arrays of complex128 / complex64, so the
+// order does not matter for these operations).  Storage is complex128
+// (double2) or complex64 (float2); every sum is accumulated in FP64.
+//
+// Reductions are deterministic: a fixed grid of kRedBlocks work-groups, each
+// thread summing a fixed strided subset, a fixed LDS tree per work-group,
+// then one work-group per output summing the per-group partials in order.
+// No floating-point atomics.
+#include "blas.h"
+
+namespace wd {
+
+template <typename S> struct Elem;
+template <> struct Elem<double2> {
+    static __device__ __forceinline__ double2 ld(const double2 *p, long long i) { return p[i]; }
+    static __device__ __forceinline__ void st(double2 *p, long long i, double2 v) { p[i] = v; }
+};
+template <> struct Elem<float2> {
+    static __device__ __forceinline__ double2 ld(const float2 *p, long long i) {
+        float2 a = p[i];
+        return make_double2(a.x, a.y);
+    }
+    static __device__ __forceinline__ void st(float2 *p, long long i, double2 v) {
+        p[i] = make_float2((float)v.x, (float)v.y);
+    }
+};
+
+__device__ __forceinline__ double2 cj_mul(double2 a, double2 b) {  // conj(a) b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// LDS tree reduction of NV complex values per thread; thread 0 gets the sums
+template <int NV>
+__device__ __forceinline__ void block_reduce(double2 (&v)[NV], double2 *lds) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; i++) lds[i * kRedThreads + t] = v[i];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                double2 a = lds[i * kRedThreads + t], b = lds[i * kRedThreads + t + s];
+                lds[i * kRedThreads + t] = make_double2(a.x + b.x, a.y + b.y);
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; i++) v[i] = lds[i * kRedThreads];
+    }
+}
+
+// partial[blk][i] = sum conj(v_i) w over the group's elements (i < nv),
+// partial[blk][kGS] = sum |w|^2 (real part)
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__restrict__ w,
+                                                       double2 *__restrict__ partial, long long N) {
+    __shared__ double2 lds[(kGS + 1) * kRedThreads];
+    double2 acc[kGS + 1];
+#pragma unroll
+    for (int i = 0; i <= kGS; i++) acc[i] = make_double2(0, 0);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double2 we = Elem<S>::ld(w, e);
+        acc[kGS].x += we.x * we.x + we.y * we.y;
+#pragma unroll
+        for (int i = 0; i < kGS; i++) {
+            if (i < vl.n) {
+                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
+                const double2 p = cj_mul(vi, we);
+                acc[i].x += p.x;
+                acc[i].y += p.y;
+            }
+        }
+    }
+    block_reduce<kGS + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i <= kGS; i++) partial[(size_t)blockIdx.x * (kGS + 1) + i] = acc[i];
+    }
+}
+
+// out[i] = sum over groups of partial[g][i], i < ncols (one work-group per i);
+// stride = number of columns per partial row
+__global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
+                                                        double2 *__restrict__ out) {
+    __shared__ double2 lds[kRedThreads];
+    double2 a[1] = {make_double2(0, 0)};
+    for (int g = threadIdx.x; g < ngroups; g += blockDim.x) {
+        double2 p = partial[(size_t)g * stride + blockIdx.x];
+        a[0].x += p.x;
+        a[0].y += p.y;
+    }
+    block_reduce<1>(a, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = a[0];
+}
+
+// w -= sum_i coef[i] v_i (i < nv); partial[blk] = sum |w_new|^2 if partial
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void k_axpy_multi(VecList vl, const double2 *__restrict__ coef,
+                                                             S *__restrict__ w, double2 *__restrict__ partial,
+                                                             long long N) {
+    __shared__ double2 lds[kRedThreads];
+    double2 c[kGS];
+#pragma unroll
+    for (int i = 0; i < kGS; i++) c[i] = i < vl.n ? coef[i] : make_double2(0, 0);
+    double2 nrm[1] = {make_double2(0, 0)};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double2 we = Elem<S>::ld(w, e);
+#pragma unroll
+        for (int i = 0; i < kGS; i++) {
+            if (i < vl.n) {
+                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
+                we.x -= c[i].x * vi.x - c[i].y * vi.y;
+                we.y -= c[i].x * vi.y + c[i].y * vi.x;
+            }
+        }
+        Elem<S>::st(w, e, we);
+        nrm[0].x += we.x * we.x + we.y * we.y;
+    }
+    if (partial) {
+        block_reduce<1>(nrm, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = nrm[0];
+    }
+}
+
+// out = in * s * mult, s = sc[0].x, 1/sqrt(sc[0].x) when inv_sqrt, or 1 when sc is null
+template <typename SI, typename SO>
+__global__ __launch_bounds__(kRedThreads) void k_scale(const SI *__restrict__ in, SO *__restrict__ out,
+                                                        const double2 *__restrict__ sc, int inv_sqrt, double mult,
+                                                        long long N) {
+    const double s = (sc ? (inv_sqrt ? 1.0 / sqrt(sc[0].x) : sc[0].x) : 1.0) * mult;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double2 a = Elem<SI>::ld(in, e);
+        Elem<SO>::st(out, e, make_double2(a.x * s, a.y * s));
+    }
+}
+
+// r = b - w, partial[blk] = sum |r|^2
+__global__ __launch_bounds__(kRedThreads) void k_residual(const double2 *__restrict__ b, const double2 *__restrict__ w,
+                                                           double2 *__restrict__ r, double2 *__restrict__ partial,
+                                                           long long N) {
+    __shared__ double2 lds[kRedThreads];
+    double2 nrm[1] = {make_double2(0, 0)};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double2 a = b[e], c = w[e];
+        double2 d = make_double2(a.x - c.x, a.y - c.y);
+        r[e] = d;
+        nrm[0].x += d.x * d.x + d.y * d.y;
+    }
+    block_reduce<1>(nrm, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = nrm[0];
+}
+
+// x += sum_i c_i z_i (x FP64, z of storage S; coefficients passed by value)
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void k_update(VecList vl, CoefList cl, double2 *__restrict__ x,
+                                                         long long N) {
+    const double2 *c = cl.c;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double2 xe = x[e];
+#pragma unroll
+        for (int i = 0; i < kGS; i++) {
+            if (i < vl.n) {
+                const double2 zi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
+                xe.x += c[i].x * zi.x - c[i].y * zi.y;
+                xe.y += c[i].x * zi.y + c[i].y * zi.x;
+            }
+        }
+        x[e] = xe;
+    }
+}
+
+// Cross-precision operations must respect the two native layouts: FP64 is
+// [12][V] complex128, FP32 is [6][V] x (2 complex64), so component k of site
+// s sits at complex index k V + s in one and 2 ((k/2) V + s) + k%2 in the
+// other.  One thread per site.
+
+// dst (FP32 native) = src (FP64 native) * mult
+__global__ __launch_bounds__(kRedThreads) void k_f64_to_f32(const double2 *__restrict__ src, float4 *__restrict__ dst,
+                                                             double mult, int V) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int kp = 0; kp < 6; kp++) {
+        const double2 a = src[(size_t)(2 * kp) * V + s], b = src[(size_t)(2 * kp + 1) * V + s];
+        dst[(size_t)kp * V + s] = make_float4((float)(a.x * mult), (float)(a.y * mult), (float)(b.x * mult),
+                                              (float)(b.y * mult));
+    }
+}
+
+// x (FP64 native) = keep * x + sum_i c_i z_i (z_i FP32 native); keep = 0 or 1
+__global__ __launch_bounds__(kRedThreads) void k_update_f32_to_f64(VecList vl, CoefList cl, double2 *__restrict__ x,
+                                                                    int keep, int V) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *c = cl.c;
+#pragma unroll
+    for (int kp = 0; kp < 6; kp++) {
+        double2 a = keep ? x[(size_t)(2 * kp) * V + s] : make_double2(0, 0);
+        double2 b = keep ? x[(size_t)(2 * kp + 1) * V + s] : make_double2(0, 0);
+#pragma unroll
+        for (int i = 0; i < kGS; i++) {
+            if (i < vl.n) {
+                const float4 z = static_cast<const float4 *>(vl.v[i])[(size_t)kp * V + s];
+                a.x += c[i].x * z.x - c[i].y * z.y;
+                a.y += c[i].x * z.y + c[i].y * z.x;
+                b.x += c[i].x * z.z - c[i].y * z.w;
+                b.y += c[i].x * z.w + c[i].y * z.z;
+            }
+        }
+        x[(size_t)(2 * kp) * V + s] = a;
+        x[(size_t)(2 * kp + 1) * V + s] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+hipError_t f64_to_f32(const void *src, void *dst, double mult, int V, hipStream_t st) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((V + kRedThreads - 1) / kRedThreads), dim3(kRedThreads), 0, st,
+                       static_cast<const double2 *>(src), static_cast<float4 *>(dst), mult, V);
+    return hipGetLastError();
+}
+
+hipError_t combine_f32_into_f64(const void *const *z, int nz, const double2 *coef, double2 *x, int V, hipStream_t st) {
+    for (int i0 = 0; i0 < nz || i0 == 0; i0 += kGS) {
+        VecList vl;
+        CoefList cl;
+        vl.n = nz - i0 < kGS ? nz - i0 : kGS;
+        if (vl.n < 0) vl.n = 0;
+        for (int i = 0; i < kGS; i++) {
+            vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
+            cl.c[i] = i < vl.n ? coef[i0 + i] : make_double2(0, 0);
+        }
+        hipLaunchKernelGGL(k_update_f32_to_f64, dim3((V + kRedThreads - 1) / kRedThreads), dim3(kRedThreads), 0, st,
+                           vl, cl, x, i0 > 0 ? 1 : 0, V);
+        if (i0 + kGS >= nz) break;
+    }
+    return hipGetLastError();
+}
+
+static int red_grid(long long N) {
+    long long g = (N + kRedThreads - 1) / kRedThreads;
+    return (int)(g < kRedBlocks ? g : kRedBlocks);
+}
+
+template <typename S>
+hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
+                hipStream_t st) {
+    // out[0..nv) = <v_i, w>, out[nv] = |w|^2 (real part), in passes of kGS vectors
+    const int G = red_grid(N);
+    for (int i0 = 0; i0 < nv || i0 == 0; i0 += kGS) {
+        VecList vl;
+        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
+        if (vl.n < 0) vl.n = 0;
+        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        hipLaunchKernelGGL(k_mdot<S>, dim3(G), dim3(kRedThreads), 0, st, vl, static_cast<const S *>(w), partial, N);
+        if (vl.n > 0)
+            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kGS + 1, out + i0);
+        if (i0 + kGS >= nv) {
+            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kGS, G, kGS + 1, out + nv);
+            break;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, void *w, long long N, double2 *partial,
+                      double2 *norm_out, hipStream_t st) {
+    const int G = red_grid(N);
+    for (int i0 = 0; i0 < nv; i0 += kGS) {
+        VecList vl;
+        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
+        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        const bool last = i0 + kGS >= nv;
+        hipLaunchKernelGGL(k_axpy_multi<S>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, static_cast<S *>(w),
+                           (last && norm_out) ? partial : (double2 *)nullptr, N);
+        if (last && norm_out)
+            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial, G, 1, norm_out);
+    }
+    return hipGetLastError();
+}
+
+template <typename SI, typename SO>
+hipError_t scale(const void *in, void *out, const double2 *sc, bool inv_sqrt, double mult, long long N,
+                 hipStream_t st) {
+    hipLaunchKernelGGL((k_scale<SI, SO>), dim3(red_grid(N)), dim3(kRedThreads), 0, st, static_cast<const SI *>(in),
+                       static_cast<SO *>(out), sc, inv_sqrt ? 1 : 0, mult, N);
+    return hipGetLastError();
+}
+
+hipError_t residual(const double2 *b, const double2 *w, double2 *r, long long N, double2 *partial, double2 *norm_out,
+                    hipStream_t st) {
+    const int G = red_grid(N);
+    hipLaunchKernelGGL(k_residual, dim3(G), dim3(kRedThreads), 0, st, b, w, r, partial, N);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial, G, 1, norm_out);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x, long long N, hipStream_t st) {
+    for (int i0 = 0; i0 < nz; i0 += kGS) {
+        VecList vl;
+        CoefList cl;
+        vl.n = nz - i0 < kGS ? nz - i0 : kGS;
+        for (int i = 0; i < kGS; i++) {
+            vl.v[i] = i < vl.n ? z[i0 + i] : x;
+            cl.c[i] = i < vl.n ? coef[i0 + i] : make_double2(0, 0);
+        }
+        hipLaunchKernelGGL(k_update<S>, dim3(red_grid(N)), dim3(kRedThreads), 0, st, vl, cl, x, N);
+    }
+    return hipGetLastError();
+}
+
+hipError_t norm2(const void *w, bool f32, long long N, double2 *partial, double2 *out, hipStream_t st) {
+    return f32 ? mdot<float2>(nullptr, 0, w, N, partial, out, st) : mdot<double2>(nullptr, 0, w, N, partial, out, st);
+}
+
+template hipError_t mdot<double2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
+template hipError_t mdot<float2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
+template hipError_t axpy_multi<double2>(const void *const *, int, const double2 *, void *, long long, double2 *,
+                                        double2 *, hipStream_t);
+template hipError_t axpy_multi<float2>(const void *const *, int, const double2 *, void *, long long, double2 *,
+                                       double2 *, hipStream_t);
+template hipError_t scale<double2, double2>(const void *, void *, const double2 *, bool, double, long long,
+                                            hipStream_t);
+template hipError_t scale<float2, float2>(const void *, void *, const double2 *, bool, double, long long,
+                                          hipStream_t);
+template hipError_t update<double2>(const void *const *, int, const double2 *, double2 *, long long, hipStream_t);
+
+}  // namespace wd

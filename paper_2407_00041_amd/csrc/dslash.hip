@@ -324,25 +324,27 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
     return hipSuccess;
 }
 
-// Split batches into register blocks of at most NR right-hand sides.
+// Group the right-hand sides of all batches, in order, into register blocks
+// of at most NR (a block may span batches).
 template <int P, bool DAG, int NR>
 static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
                             bool persistent, hipStream_t st) {
     const size_t rb = field_rhs_bytes(P, g.V);
+    std::vector<std::pair<const void *, void *>> rhs;
+    for (int b = 0; b < nbatch; b++)
+        for (int r = 0; r < batches[b].nrhs; r++)
+            rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
+                             static_cast<char *>(batches[b].out) + r * rb);
     std::vector<Chunk<NR>> chunks;
-    for (int b = 0; b < nbatch; b++) {
-        const char *in = static_cast<const char *>(batches[b].in);
-        char *out = static_cast<char *>(batches[b].out);
-        for (int r0 = 0; r0 < batches[b].nrhs; r0 += NR) {
-            Chunk<NR> c;
-            c.nr = std::min(NR, batches[b].nrhs - r0);
-            for (int r = 0; r < NR; r++) {
-                const int rr = r0 + std::min(r, c.nr - 1);
-                c.in[r] = in + rr * rb;
-                c.out[r] = out + rr * rb;
-            }
-            chunks.push_back(c);
+    for (size_t r0 = 0; r0 < rhs.size(); r0 += NR) {
+        Chunk<NR> c;
+        c.nr = (int)std::min<size_t>(NR, rhs.size() - r0);
+        for (int r = 0; r < NR; r++) {
+            const size_t rr = r0 + std::min(r, c.nr - 1);
+            c.in[r] = rhs[rr].first;
+            c.out[r] = rhs[rr].second;
         }
+        chunks.push_back(c);
     }
     return launch_chunks<P, DAG, NR>(chunks, d, g, apbc, persistent, st);
 }
