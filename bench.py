@@ -1,31 +1,50 @@
 #!/usr/bin/env python3
-"""Benchmark of the Wilson-clover Dirac operator on one MI355X.
+"""Benchmark of the Wilson-clover Dirac operator and FGMRES on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--dims T Z Y X] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--dims T Z Y X] [--fgmres-rhs N]
+                    [--no-fgmres] [--no-batched] [--no-cpu-baseline]
+
+Workload: the 48^3 x 96 lattice (T = 96) with smoothed random SU(3) links
+exp(0.3 i H), c_sw = 1, m0 = -0.35, Gaussian right-hand sides; every input is
+seeded and synthetic and resident in HBM before any timed region.
 
 A step is one FP64 application of D (Eq. (1.13) with the clover term) to one
-Gaussian right-hand side on the 48^3 x 96 lattice (T = 96) with smoothed
-random SU(3) links exp(0.3 i H), c_sw = 1, m0 = -0.35; inputs are resident in
-HBM before the timed region.  Prints ONE JSON line.  The FP32 and FP16S
-applies on the same lattice are timed after the main measurement and reported
-in "extra".  The CPU oracle is timed on a bounded contiguous slab of sites
-("cpu_baseline").
+right-hand side: `value` is applications per second, `roofline` relates the
+stencil kernel's algorithmic bytes per launch to the HBM peak.  After the
+timed steps (reported under "extra"):
+  * single FP32 and FP16S applies;
+  * one persistent FP32 launch over uneven batches {1, 4, 12, 24};
+  * 12 right-hand sides solved to 1e-10 by plain FP64 FGMRES(30) and by the
+    mixed solver (FP64 outer FGMRES(16) whose preconditioner is an inner
+    GMRES(10) on the FP16S operator, relative tolerance 0.1), in memory-sized
+    waves: wall time, applications and the difference between the two
+    solutions.
+The CPU oracle's apply is timed on a bounded slab of sites ("cpu_baseline").
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FLOP_HOP = 1320                # flop/site, hopping term (the paper's convention)
 FLOP_FULL = 1872               # flop/site, with clover (504) and combine (48)
 # algorithmic bytes per site and right-hand side: in + out spinor + links + clover
 BYTES_SITE = {"f64": 192 + 192 + 576 + 576, "f32": 96 + 96 + 288 + 288, "f16s": 52 + 52 + 144 + 144}
+KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/csrc/dslash.h",
+                  "paper_2407_00041_amd/csrc/spinor_io.h", "paper_2407_00041_amd/csrc/common.h"]
+TRAFFIC_PROFILE = "profiles/dslash_f64_48x96_hbm_traffic.md"
+# mixed solver: FP64 outer FGMRES, inner GMRES on the reduced-precision operator
+MIXED = {"mode": "mixed_f16s", "restart": 16, "inner_restart": 10, "inner_tol": 0.1}
 
 
 def parse():
@@ -36,10 +55,13 @@ def parse():
     ap.add_argument("--dims", type=int, nargs=4, default=[96, 48, 48, 48])
     ap.add_argument("--m0", type=float, default=-0.35)
     ap.add_argument("--csw", type=float, default=1.0)
+    ap.add_argument("--fgmres-rhs", type=int, default=12)
+    ap.add_argument("--no-fgmres", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip every measurement after the main one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration)")
+                    help="also run a plain 1 GiB elementwise copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -47,101 +69,117 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_applies(torch, op, out, inp, prec, steps, warmup, stream):
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def time_launches(torch, fn, steps, warmup, stream):
     for _ in range(warmup):
-        op.apply_native(out, inp, 1, prec, stream=stream)
+        fn()
     stream.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        op.apply_native(out, inp, 1, prec, stream=stream)
+        fn()
     e1.record(stream)
     e1.synchronize()
-    return e0.elapsed_time(e1) / steps        # ms per apply
+    return e0.elapsed_time(e1) / steps        # ms per launch
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   "multi-GPU halo exchange is not part of this build"}))
-        sys.exit(2)
-    import torch
-
-    import paper_2407_00041_amd as wd
+def batched_run(torch, op, dims, stream, steps):
     from paper_2407_00041_amd import synth
+    sizes = [1, 4, 12, 24]
+    n = sum(sizes)
+    psi = synth.gaussian_spinor(dims, 2100, nrhs=n, device="cuda")
+    nat = op.pack(psi, "f32")
+    del psi
+    rb = op.field_bytes("f32", 1)
+    outs, batches, r0 = [], [], 0
+    for s in sizes:
+        o = op.empty("f32", s)
+        outs.append(o)
+        batches.append((o, nat[r0 * rb:(r0 + s) * rb], s))
+        r0 += s
+    ms = time_launches(torch, lambda: op.apply_batched(batches, "f32", stream=stream), steps, 3, stream)
+    res = {"batches": sizes, "prec": "f32", "ms_per_launch": ms, "rhs_applies_per_s": n * 1000.0 / ms,
+           "alg_GBps": (576 + 192 * n) * op.V / (ms * 1e-3) / 1e9}
+    del outs, batches, nat
+    torch.cuda.empty_cache()
+    return res
 
-    dims = tuple(a.dims)
-    V = int(np.prod(dims))
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    log(f"[bench] generating inputs {dims} V={V}")
-    t0 = time.time()
-    Ud = synth.smooth_links(dims, 1003, device=dev)
-    psid = synth.gaussian_spinor(dims, 2000, nrhs=1, device=dev)
-    U = Ud.cpu().numpy()
-    del Ud
-    log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
-    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"))
-    stream = torch.cuda.current_stream()
-    inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
-    out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}
-    torch.cuda.synchronize()
 
-    log(f"[bench] timing FP64 apply: {a.warmup} warmup + {a.steps} steps")
-    ms = time_applies(torch, op, out["f64"], inp["f64"], "f64", a.steps, a.warmup, stream)
-    apps = 1000.0 / ms
-    gbs = BYTES_SITE["f64"] * V / (ms * 1e-3) / 1e9
-    log(f"[bench] FP64: {ms:.4f} ms/apply, {apps:.1f} apps/s, {gbs:.0f} GB/s")
-
-    extra = {"f64": {"ms": ms, "apps_per_s": apps, "alg_GBps": gbs,
-                     "GFLOPs_1320": FLOP_HOP * V / (ms * 1e-3) / 1e9,
-                     "GFLOPs_1872": FLOP_FULL * V / (ms * 1e-3) / 1e9}}
-    if not a.no_extra:
-        for p in ("f32", "f16s"):
-            m = time_applies(torch, op, out[p], inp[p], p, max(10, a.steps // 2), a.warmup, stream)
-            extra[p] = {"ms": m, "apps_per_s": 1000.0 / m,
-                        "alg_GBps": BYTES_SITE[p] * V / (m * 1e-3) / 1e9,
-                        "GFLOPs_1320": FLOP_HOP * V / (m * 1e-3) / 1e9}
-            log(f"[bench] {p}: {m:.4f} ms/apply")
-    if a.copy_probe:
-        n = 1 << 30
-        src = torch.empty(n, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
+def fgmres_run(torch, op, dims, nrhs_total):
+    """Plain FP64 FGMRES(30) vs the mixed FP16S-preconditioned FGMRES on the
+    same right-hand sides, in waves sized to the free HBM."""
+    from paper_2407_00041_amd import synth
+    p64 = dict(restart=30, tol=1e-10, maxit=5000, mode="f64")
+    pmx = dict(restart=MIXED["restart"], tol=1e-10, maxit=500, mode=MIXED["mode"],
+               inner_restart=MIXED["inner_restart"], inner_tol=MIXED["inner_tol"], inner_maxit=MIXED["inner_restart"])
+    fb = op.field_bytes("f64", 1)
+    free, _ = torch.cuda.mem_get_info()
+    per = max(op.workspace_bytes(1, 30, "f64"),
+              op.workspace_bytes(1, pmx["restart"], pmx["mode"], pmx["inner_restart"])) + 3 * fb
+    wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
+    log(f"[bench] fgmres: {nrhs_total} RHS in waves of {wave} "
+        f"(free {free / 2**30:.0f} GiB, {per / 2**30:.1f} GiB per RHS)")
+    # one workspace for every wave and both solvers (allocation is not timed)
+    wbytes = max(op.workspace_bytes(wave, 30, "f64"),
+                 op.workspace_bytes(wave, pmx["restart"], pmx["mode"], pmx["inner_restart"]))
+    work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    t64 = tmx = 0.0
+    a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
+    for w0 in range(0, nrhs_total, wave):
+        nw = min(wave, nrhs_total - w0)
+        b = op.pack(synth.gaussian_spinor(dims, 3000 + w0, nrhs=nw, device="cuda"), "f64")
         torch.cuda.synchronize()
-        log("[bench] copy probe done (1 GiB x 5)")
-
-    res = {
-        "metric": "Dirac apps/s & HBM GB/s; mixed vs FP64 FGMRES time to 1e-10 at 48^3x96",
-        "value": apps,
-        "unit": "Dirac apps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded exp(0.3iH) SU(3) links, Gaussian spinor)",
-        "config": {"workload": f"Wilson-clover D apply, {dims[1]}^3x{dims[0]} (T,Z,Y,X = {dims}), "
-                               f"FP64, 1 RHS, csw={a.csw}, m0={a.m0}, periodic",
-                   "lattice": list(dims), "sites": V, "nrhs": 1, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "wd::dslash_kernel<0,false>",
-                     "alg_bytes_per_site": BYTES_SITE["f64"]},
-        "extra": extra,
-    }
-    if not a.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        psi = psid.reshape(V, 12).cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline_run(dims, U, psi, a.m0, a.csw)
-        log(f"[bench] cpu baseline {res['cpu_baseline']['value']:.4f} apps/s")
-    print(json.dumps(res), flush=True)
+        t = time.perf_counter()
+        x64, st64, _ = op.solve(b, nrhs=nw, work=work, **p64)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t
+        t = time.perf_counter()
+        xmx, stmx, _ = op.solve(b, nrhs=nw, work=work, **pmx)
+        torch.cuda.synchronize()
+        tmx += time.perf_counter() - t
+        for r in range(nw):
+            u = x64[r * fb:(r + 1) * fb].view(torch.float64)
+            v = xmx[r * fb:(r + 1) * fb].view(torch.float64)
+            errs.append(float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(u)))
+            a64.append(st64[r]["applies"])
+            amx.append(stmx[r]["applies"])
+            ainner.append(stmx[r]["inner_applies"])
+            res64.append(st64[r]["true_residual"])
+            resmx.append(stmx[r]["true_residual"])
+        log(f"[bench] fgmres after RHS {w0 + nw}: fp64 {t64:.2f}s mixed {tmx:.2f}s")
+        del b, x64, xmx
+        torch.cuda.empty_cache()
+    return {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
+            "fp64": {"solver": "FGMRES(30), FP64", "seconds": t64, "applies": a64,
+                     "true_residual_max": max(res64), "converged": all(r < 1e-10 for r in res64)},
+            "mixed": {"solver": f"FP64 FGMRES({pmx['restart']}), preconditioner inner GMRES({pmx['inner_restart']}) "
+                                f"on the {pmx['mode'][6:].upper()} operator (relative tol {pmx['inner_tol']})",
+                      "seconds": tmx, "fp64_applies": amx, "fp16s_applies": ainner,
+                      "true_residual_max": max(resmx), "converged": all(r < 1e-10 for r in resmx)},
+            "speedup_mixed_vs_fp64": t64 / tmx if tmx > 0 else None,
+            "error_vs_fp64_max": max(errs)}
 
 
 def cpu_baseline_run(dims, U, psi, m0, csw, target_s=3.0):
@@ -177,6 +215,101 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU halo exchange "
+                                   "is not part of this build"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2407_00041_amd as wd
+    from paper_2407_00041_amd import synth
+
+    dims = tuple(a.dims)
+    V = int(np.prod(dims))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] generating inputs {dims} V={V}")
+    t0 = time.time()
+    Ud = synth.smooth_links(dims, 1003, device=dev)
+    psid = synth.gaussian_spinor(dims, 2000, nrhs=1, device=dev)
+    U = Ud.cpu().numpy()
+    del Ud
+    log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
+    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"))
+    stream = torch.cuda.current_stream()
+    inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
+    out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing FP64 apply: {a.warmup} warmup + {a.steps} steps")
+    ms = time_launches(torch, lambda: op.apply_native(out["f64"], inp["f64"], 1, "f64", stream=stream),
+                       a.steps, a.warmup, stream)
+    apps = 1000.0 / ms
+    gbs = BYTES_SITE["f64"] * V / (ms * 1e-3) / 1e9
+    log(f"[bench] FP64: {ms:.4f} ms/apply, {apps:.1f} apps/s, {gbs:.0f} GB/s")
+
+    extra = {"f64": {"ms": ms, "apps_per_s": apps, "alg_GBps": gbs,
+                     "GFLOPs_1320": FLOP_HOP * V / (ms * 1e-3) / 1e9,
+                     "GFLOPs_1872": FLOP_FULL * V / (ms * 1e-3) / 1e9}}
+    if not a.no_extra:
+        for p in ("f32", "f16s"):
+            m = time_launches(torch, lambda: op.apply_native(out[p], inp[p], 1, p, stream=stream),
+                              max(10, a.steps // 2), a.warmup, stream)
+            extra[p] = {"ms": m, "apps_per_s": 1000.0 / m, "alg_GBps": BYTES_SITE[p] * V / (m * 1e-3) / 1e9,
+                        "GFLOPs_1320": FLOP_HOP * V / (m * 1e-3) / 1e9}
+            log(f"[bench] {p}: {m:.4f} ms/apply")
+    if a.copy_probe:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy probe done (1 GiB read + 1 GiB write, x5)")
+    del inp, out
+    torch.cuda.empty_cache()
+    if not a.no_extra and not a.no_batched:
+        log("[bench] persistent batched FP32 launch {1,4,12,24}")
+        extra["batched"] = batched_run(torch, op, dims, stream, 10)
+        extra["batched"]["per_rhs_rate_vs_fp64_single"] = extra["batched"]["rhs_applies_per_s"] / apps
+        log(f"[bench] batched: {extra['batched']['rhs_applies_per_s']:.0f} RHS-applies/s")
+    if not a.no_extra and not a.no_fgmres and a.fgmres_rhs > 0:
+        extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs)
+
+    res = {
+        "metric": "Dirac apps/s & HBM GB/s; mixed vs FP64 FGMRES time to 1e-10 at 48^3x96",
+        "value": apps,
+        "unit": "Dirac apps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded exp(0.3iH) SU(3) links, Gaussian spinors)",
+        "config": {"workload": f"Wilson-clover D apply, {dims[1]}^3x{dims[0]} (T,Z,Y,X = {list(dims)}), "
+                               f"FP64, 1 RHS, csw={a.csw}, m0={a.m0}, periodic",
+                   "lattice": list(dims), "sites": V, "nrhs": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
+                     "kernel": "wd::dslash_kernel<0, false, 1>",
+                     "alg_bytes_per_site": BYTES_SITE["f64"], "alg_bytes_per_launch": BYTES_SITE["f64"] * V,
+                     "kernel_source_sha256_16": kernel_hash()},
+        "extra": extra,
+    }
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        psi = psid.reshape(V, 12).cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline_run(dims, U, psi, a.m0, a.csw)
+        log(f"[bench] cpu baseline {res['cpu_baseline']['value']:.4f} apps/s")
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

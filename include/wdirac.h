@@ -152,8 +152,11 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * Process-wide launch parameters of the stencil kernels (the autotuner's
  * knobs).  Keys: "block" (threads per work-group: 64, 128, 192, 256),
  * "order" (0 linear, 1 one contiguous 1/8 of the lattice per XCD, 2 every
- * XCD takes 1/8 of each T-slice and the slices are swept in order),
- * "persistent_blocks" (work-groups of a dirac_apply_batched launch, >= 8),
+ * XCD takes 1/8 of each T-slice and the slices are swept in order, 3 lanes
+ * walk columns along T carrying the T neighbours in registers), "tchunk"
+ * (order 3: sites per lane along T, >= 1),
+ * "persistent_blocks" (cap on the work-groups of a dirac_apply_batched launch;
+ * 0, the default, means all work-groups that fit on the device at once),
  * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
  * or 4).  Not synchronised with launches in flight; set before applying.
  * Errors: EINVAL (unknown key or value out of range).

@@ -139,18 +139,36 @@ class DiracOp:
         self.apply_native(b, a, nrhs, prec, dagger)
         return self.unpack(b, prec, nrhs).reshape(shape)
 
+    @staticmethod
+    def _params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit):
+        modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S}
+        return _lib.FgmresParams(int(restart), float(tol), int(maxit),
+                                 modes[mode] if isinstance(mode, str) else int(mode),
+                                 int(inner_restart), float(inner_tol), int(inner_maxit))
+
+    def workspace_bytes(self, nrhs: int = 1, restart: int = 20, mode="f64", inner_restart: int = 30) -> int:
+        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1)
+        n = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
+        if n == 0:
+            raise WdiracError(-1, "fgmres_workspace_bytes")
+        return n
+
     def solve(self, b: torch.Tensor, nrhs: int = 1, x0: torch.Tensor | None = None, restart: int = 20,
               tol: float = 1e-10, maxit: int = 10000, mode="f64", inner_restart: int = 30,
-              inner_tol: float = 1e-2, inner_maxit: int = 30, stream=None):
+              inner_tol: float = 1e-2, inner_maxit: int = 30, work: torch.Tensor | None = None, stream=None):
         """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
-        "mixed_f16s".  Returns (x native FP64, list of per-RHS stats dicts, status)."""
-        modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S}
-        p = _lib.FgmresParams(int(restart), float(tol), int(maxit), modes[mode] if isinstance(mode, str) else int(mode),
-                              int(inner_restart), float(inner_tol), int(inner_maxit))
+        "mixed_f16s".  ``work`` may be a reusable device buffer of at least
+        workspace_bytes(...) bytes.  Returns (x native FP64, per-RHS stats dicts, status)."""
+        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit)
         nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if nbytes == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
-        work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+        if work is None:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+        elif work.numel() * work.element_size() < nbytes:
+            raise ValueError(f"workspace of {work.numel()} bytes is smaller than {nbytes}")
+        else:
+            nbytes = work.numel() * work.element_size()
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         stats = (_lib.FgmresStats * int(nrhs))()
         rc = check(self.lib.fgmres_solve(self.handle, _ptr(x), _ptr(b), int(nrhs), ctypes.byref(p), stats,
@@ -183,7 +201,7 @@ def tune_get(key: str) -> int:
     return int(v.value)
 
 
-TUNE_KEYS = ("block", "order", "persistent_blocks", "nr_f64", "nr_f32", "nr_f16s")
+TUNE_KEYS = ("block", "order", "tchunk", "persistent_blocks", "nr_f64", "nr_f32", "nr_f16s")
 
 
 def clover_term(dims, links_dev: torch.Tensor, stream=None) -> torch.Tensor:

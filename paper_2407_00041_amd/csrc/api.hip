@@ -204,10 +204,13 @@ int dirac_tune_set(const char *key, int value) {
         if (value < 64 || value > 256 || value % 64) return fail(WDIRAC_EINVAL, "block must be 64, 128, 192 or 256");
         t.block = value;
     } else if (k == "order") {
-        if (value < 0 || value > 2) return fail(WDIRAC_EINVAL, "order must be 0, 1 or 2");
+        if (value < 0 || value > 3) return fail(WDIRAC_EINVAL, "order must be 0, 1, 2 or 3");
         t.order = value;
+    } else if (k == "tchunk") {
+        if (value < 1 || value > 4096) return fail(WDIRAC_EINVAL, "tchunk must be in [1, 4096]");
+        t.tchunk = value;
     } else if (k == "persistent_blocks") {
-        if (value < 8) return fail(WDIRAC_EINVAL, "persistent_blocks must be >= 8");
+        if (value != 0 && value < 8) return fail(WDIRAC_EINVAL, "persistent_blocks must be 0 or >= 8");
         t.persistent_blocks = value;
     } else if (k == "nr_f64" || k == "nr_f32" || k == "nr_f16s") {
         if (value != 1 && value != 2 && value != 4) return fail(WDIRAC_EINVAL, "register block must be 1, 2 or 4");
@@ -224,6 +227,7 @@ int dirac_tune_get(const char *key, int *value) {
     std::string k(key);
     if (k == "block") *value = t.block;
     else if (k == "order") *value = t.order;
+    else if (k == "tchunk") *value = t.tchunk;
     else if (k == "persistent_blocks") *value = t.persistent_blocks;
     else if (k == "nr_f64") *value = t.nr[0];
     else if (k == "nr_f32") *value = t.nr[1];

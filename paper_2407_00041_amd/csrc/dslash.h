@@ -25,24 +25,27 @@ template <int NR> struct ChunkTable {
 constexpr int kOrderLinear = 0;    // tile slot = tile, lexicographic
 constexpr int kOrderXcdChunk = 1;  // each XCD gets a contiguous 1/8 of the lattice
 constexpr int kOrderTSweep = 2;    // each XCD gets 1/8 of every T-slice; slices in order
+constexpr int kOrderColumn = 3;    // lanes walk columns along T (register-carried T neighbours)
 
 struct TileMap {
     int order;
     int block;            // sites per tile = threads per work-group
     int V;
     int slice;            // sites per T-slice
-    int tiles_per_range;  // kOrderTSweep: tiles per (slice, XCD) range
+    int tiles_per_range;  // kOrderTSweep / kOrderColumn: tiles per (slice, XCD) range
+    int tchunk;           // kOrderColumn: sites per lane along T
     int ntiles;           // tile slots holding sites
     int nslots;           // ntiles rounded up to a multiple of 8
 };
 
-TileMap make_tilemap(const Geom &g, int order, int block);
+TileMap make_tilemap(const Geom &g, int order, int block, int tchunk);
 
 // Process-wide launch parameters (set through dirac_tune_set).
 struct Tuning {
     int block = 256;             // threads per work-group: 64, 128, 192 or 256
     int order = kOrderTSweep;    // tile order
-    int persistent_blocks = 2048;  // grid of persistent (batched) launches
+    int tchunk = 8;              // kOrderColumn: T sites per lane
+    int persistent_blocks = 0;   // cap on the persistent grid (0: all co-resident work-groups)
     int nr[3] = {2, 2, 2};       // register block size per precision (1, 2 or 4)
 };
 

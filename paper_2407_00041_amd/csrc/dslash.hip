@@ -201,6 +201,117 @@ __device__ __forceinline__ void site_apply(const Chunk<NR> &ch, const OpData &d,
         if (r < ch.nr) Store<P>::store_spinor(ch.out[r], V, s, acc[r]);
 }
 
+// Register T-sweep (tile order 3): one lane walks the sites t0..t1-1 of one
+// column (z, y, x).  psi(t+1) is loaded once as the forward T neighbour and
+// kept as the next step's own spinor, and the backward T hop of site t+1,
+// -1/2 (I + SB gamma_T) (x) U_T(t)^H psi(t), is formed at step t and carried
+// in registers, so no T-neighbour spinor or backward T link is re-read.
+template <int P, bool DAG, int NR>
+__device__ __forceinline__ void column_sweep(const Chunk<NR> &ch, const OpData &d, const Geom &g, int c, int t0,
+                                             int t1, bool apbc) {
+    using T = typename Store<P>::T;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const int V = g.V, S = g.stride[0], nT = g.n[0];
+    // neighbour columns in Z, Y, X
+    int cf[4], cb[4];
+    {
+        int r = c, q[4];
+        q[3] = r % g.n[3]; r /= g.n[3];
+        q[2] = r % g.n[2];
+        q[1] = r / g.n[2];
+#pragma unroll
+        for (int mu = 1; mu < 4; mu++) {
+            const int st = g.stride[mu], L = g.n[mu];
+            cf[mu] = (q[mu] == L - 1) ? c - (L - 1) * st : c + st;
+            cb[mu] = (q[mu] == 0) ? c + (L - 1) * st : c - st;
+        }
+    }
+    cx<T> self[NR][12], chiT[NR][6];
+    {
+        const int tm = (t0 == 0) ? nT - 1 : t0 - 1;
+        const T f = (apbc && t0 == 0) ? T(0.5) : T(-0.5);
+        cx<T> U[9];
+        Store<P>::load_link(d.links, V, 0, tm * S + c, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < ch.nr) {
+                cx<T> p[12], h[6];
+                Store<P>::load_spinor(ch.in[r], V, tm * S + c, p);
+                project<0, SB>(p, h, f);
+                su3_mul<true>(U, h, chiT[r]);
+                Store<P>::load_spinor(ch.in[r], V, t0 * S + c, self[r]);
+            }
+        }
+    }
+    for (int t = t0; t < t1; t++) {
+        const int s = t * S + c;
+        cx<T> acc[NR][12];
+        // self coupling
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            T dd[6];
+            cx<T> uu[15];
+            Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                if (r < ch.nr) clover_block(dd, uu, &self[r][6 * b], &acc[r][6 * b]);
+        }
+        // backward T hop (carried), then the one for site t+1
+        const bool last = (t == nT - 1);
+        {
+            const T f = (apbc && last) ? T(0.5) : T(-0.5);
+            cx<T> U[9];
+            Store<P>::load_link(d.links, V, 0, s, U);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r < ch.nr) {
+                    reconstruct<0, SB>(acc[r], chiT[r]);
+                    cx<T> h[6];
+                    project<0, SB>(self[r], h, f);
+                    su3_mul<true>(U, h, chiT[r]);
+                }
+            }
+        }
+        hop_fence(1);
+        Nbr nb;
+#pragma unroll
+        for (int mu = 1; mu < 4; mu++) {
+            nb.fwd[mu] = t * S + cf[mu];
+            nb.bwd[mu] = t * S + cb[mu];
+        }
+        nb.fwd[0] = nb.bwd[0] = s;
+        nb.fwd_wrapT = nb.bwd_wrapT = false;
+        hop_pair<P, 1, DAG, NR>(ch, d, V, s, nb, false, acc);
+        hop_fence(1);
+        hop_pair<P, 2, DAG, NR>(ch, d, V, s, nb, false, acc);
+        hop_fence(1);
+        hop_pair<P, 3, DAG, NR>(ch, d, V, s, nb, false, acc);
+        hop_fence(1);
+        // forward T hop; psi(t+1) becomes the next step's own spinor
+        {
+            const int sp = (last ? 0 : t + 1) * S + c;
+            const T f = (apbc && last) ? T(0.5) : T(-0.5);
+            cx<T> U[9];
+            Store<P>::load_link(d.links, V, 0, s, U);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r < ch.nr) {
+                    cx<T> h[6], chi[6];
+                    Store<P>::load_spinor(ch.in[r], V, sp, self[r]);
+                    project<0, SF>(self[r], h, f);
+                    su3_mul<false>(U, h, chi);
+                    reconstruct<0, SF>(acc[r], chi);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            if (r < ch.nr) Store<P>::store_spinor(ch.out[r], V, s, acc[r]);
+        hop_fence(1);
+    }
+}
+
 // site range [lo, hi) of tile slot vb (see TileMap in dslash.h)
 __device__ __forceinline__ void tile_range(const TileMap &m, int vb, int &lo, int &hi) {
     if (m.order == kOrderTSweep) {
@@ -277,16 +388,45 @@ void dslash_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int apbc) {
     }
 }
 
+// the column sweep carries psi(t+1) and the T half-spinors: fewer waves
+template <int P, int NR> constexpr int occupancy_col() {
+    return P == WDIRAC_F64 ? (NR == 1 ? 2 : 1) : P == WDIRAC_F32 ? (NR == 1 ? 3 : NR == 2 ? 2 : 1)
+                                                                 : (NR == 1 ? 4 : NR == 2 ? 2 : 1);
+}
+
+template <int P, bool DAG, int NR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(occupancy_col<P, NR>())))
+void dslash_column_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int apbc) {
+    const int nitems = m.nslots * tab.nchunks;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const int xcd = w & 7, q = w >> 3;
+        const int vb = (q / tab.nchunks) * 8 + xcd;
+        const int c = q - (q / tab.nchunks) * tab.nchunks;
+        // columns of XCD k's 1/8 of a slice, T-chunk tc
+        const int k = vb & 7, j = vb >> 3;
+        const int tc = j / m.tiles_per_range, tile = j - tc * m.tiles_per_range;
+        const int r0 = (int)(((long long)k * m.slice) >> 3), r1 = (int)(((long long)(k + 1) * m.slice) >> 3);
+        const int col = r0 + tile * m.block + (int)threadIdx.x;
+        const int t0 = tc * m.tchunk, t1 = min(t0 + m.tchunk, g.n[0]);
+        if (col < r1 && t0 < t1) column_sweep<P, DAG, NR>(tab.c[c], d, g, col, t0, t1, apbc != 0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
-TileMap make_tilemap(const Geom &g, int order, int block) {
+TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     TileMap m;
     m.order = order;
     m.block = block;
     m.V = g.V;
     m.slice = g.V / g.n[0];
-    if (order == kOrderTSweep) {
+    m.tchunk = tchunk < 1 ? 1 : (tchunk > g.n[0] ? g.n[0] : tchunk);
+    if (order == kOrderColumn) {
+        const int per_range = (m.slice + 7) / 8;
+        m.tiles_per_range = (per_range + block - 1) / block;
+        m.ntiles = (g.n[0] + m.tchunk - 1) / m.tchunk * 8 * m.tiles_per_range;
+    } else if (order == kOrderTSweep) {
         const int per_range = (m.slice + 7) / 8;
         m.tiles_per_range = (per_range + block - 1) / block;
         m.ntiles = g.n[0] * 8 * m.tiles_per_range;
@@ -302,22 +442,51 @@ static Tuning g_tuning;
 
 Tuning &tuning() { return g_tuning; }
 
+// Work-groups of one kernel instance that fit on the device at once.
+template <int P, bool DAG, int NR>
+static int resident_blocks(int block) {
+    static int cached[5] = {0, 0, 0, 0, 0};
+    const int slot = block / 64;
+    if (!cached[slot]) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dslash_kernel<P, DAG, NR>, block, 0) != hipSuccess ||
+            cus * per_cu < 8) {
+            (void)hipGetLastError();
+            return 8;
+        }
+        cached[slot] = cus * per_cu / 8 * 8;
+    }
+    return cached[slot];
+}
+
 template <int P, bool DAG, int NR>
 static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpData &d, const Geom &g, int apbc,
                                 bool persistent, hipStream_t st) {
     const Tuning &tu = g_tuning;
-    const TileMap m = make_tilemap(g, tu.order, tu.block);
+    const TileMap m = make_tilemap(g, tu.order, tu.block, tu.tchunk);
     for (size_t c0 = 0; c0 < chunks.size(); c0 += kMaxChunks) {
         ChunkTable<NR> tab;
         tab.nchunks = (int)std::min(chunks.size() - c0, (size_t)kMaxChunks);
         for (int i = 0; i < tab.nchunks; i++) tab.c[i] = chunks[c0 + i];
-        long long items = (long long)m.nslots * tab.nchunks;
+        const long long items = (long long)m.nslots * tab.nchunks;
         long long grid = items;
-        if (persistent && tu.persistent_blocks > 0 && grid > tu.persistent_blocks)
-            grid = (tu.persistent_blocks + 7) / 8 * 8;
+        if (persistent) {
+            // every work-group must be resident, so that the work-groups of an
+            // XCD walk through its items together (in order)
+            long long cap = resident_blocks<P, DAG, NR>(tu.block);
+            if (tu.persistent_blocks > 0 && tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
+            if (cap < 8) cap = 8;
+            if (grid > cap) grid = cap;
+        }
         if (grid > (1LL << 30)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((dslash_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d, g, m,
-                           apbc);
+        if (m.order == kOrderColumn)
+            hipLaunchKernelGGL((dslash_column_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d,
+                               g, m, apbc);
+        else
+            hipLaunchKernelGGL((dslash_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d, g, m,
+                               apbc);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -356,6 +525,7 @@ static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData 
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
     int nr = g_tuning.nr[P];
     if (total == 1) nr = 1;
+    if (g_tuning.order == kOrderColumn && P == WDIRAC_F64 && nr > 2) nr = 2;  // register budget
     if (nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, st);
     if (nr >= 2) return launch_nr<P, DAG, 2>(batches, nbatch, d, g, apbc, persistent, st);
     return launch_nr<P, DAG, 1>(batches, nbatch, d, g, apbc, persistent, st);

@@ -168,7 +168,7 @@ struct Ctx {
 
 hipError_t apply_many(const Ctx &c, int prec, const std::vector<dirac_batch> &b) {
     if (b.empty()) return hipSuccess;
-    return dslash_launch_batches(b.data(), (int)b.size(), prec, false, c.op->data(prec), c.op->g, c.apbc, true, c.st);
+    return dslash_launch_batches(b.data(), (int)b.size(), prec, false, c.op->data(prec), c.op->g, c.apbc, false, c.st);
 }
 
 #define WD_TRY(expr)                                                                              \

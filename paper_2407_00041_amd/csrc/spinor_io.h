@@ -15,6 +15,16 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
+// Read-once data (the self-coupling matrices) may be loaded non-temporally so
+// that it does not displace reusable neighbour spinors from the L2.
+#ifndef WD_CLOVER_NT
+#define WD_CLOVER_NT 1
+#endif
+template <typename V> __device__ __forceinline__ V ld_once(const V *p) {
+    if (WD_CLOVER_NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 template <int P> struct Store;
 
 // ---------------------------------------------------------------- FP64
@@ -56,16 +66,16 @@ template <> struct Store<WDIRAC_F64> {
     // block b of A(x): 6 real diagonal entries and 15 complex strict-upper entries
     static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
                                                        cx<T> u[15]) {
-        const double2 *p = static_cast<const double2 *>(base) + (size_t)b * 18 * V;
+        const d2v *p = static_cast<const d2v *>(base) + (size_t)b * 18 * V;
 #pragma unroll
         for (int e = 0; e < 3; e++) {
-            double2 a = p[(size_t)e * V + s];
+            d2v a = ld_once(&p[(size_t)e * V + s]);
             d[2 * e] = a.x;
             d[2 * e + 1] = a.y;
         }
 #pragma unroll
         for (int e = 0; e < 15; e++) {
-            double2 a = p[(size_t)(3 + e) * V + s];
+            d2v a = ld_once(&p[(size_t)(3 + e) * V + s]);
             u[e] = {a.x, a.y};
         }
     }
@@ -110,11 +120,11 @@ template <> struct Store<WDIRAC_F32> {
     }
     static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
                                                        cx<T> u[15]) {
-        const float4 *p = static_cast<const float4 *>(base) + (size_t)b * 9 * V;
+        const f4v *p = static_cast<const f4v *>(base) + (size_t)b * 9 * V;
         float r[36];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            float4 a = p[(size_t)e * V + s];
+            f4v a = ld_once(&p[(size_t)e * V + s]);
             r[4 * e] = a.x; r[4 * e + 1] = a.y; r[4 * e + 2] = a.z; r[4 * e + 3] = a.w;
         }
 #pragma unroll
@@ -178,7 +188,7 @@ template <> struct Store<WDIRAC_F16S> {
         float r[36];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            half4 a = p[(size_t)e * V + s];
+            half4 a = ld_once(&p[(size_t)e * V + s]);
             r[4 * e] = (float)a[0]; r[4 * e + 1] = (float)a[1];
             r[4 * e + 2] = (float)a[2]; r[4 * e + 3] = (float)a[3];
         }

@@ -108,6 +108,23 @@ def test_tile_orders_and_blocks(order, block, restore_tuning):
     assert rel_l2(op.unpack(out, "f64").cpu().numpy(), want) < 1e-13
 
 
+@pytest.mark.parametrize("tchunk", [1, 3, 8])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_column_sweep_order(tchunk, prec, dagger, restore_tuning):
+    """Tile order 3 (lanes walk columns along T with register-carried T
+    neighbours): ragged T-chunks, anti-periodic T, several right-hand sides."""
+    dims = (5, 3, 7, 4)
+    U, psi = fields(dims, 31, nrhs=3)
+    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True)
+    tune_set("order", 3)
+    tune_set("tchunk", tchunk)
+    got = op.apply(to_dev(psi), prec, dagger=dagger).cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, -0.3, 1.0, antiperiodic_t=True, dagger=dagger)
+    for r in range(3):
+        assert rel_l2(got[r], want[r]) < TOL[prec], (r, rel_l2(got[r], want[r]))
+
+
 def test_batched_argument_errors(restore_tuning):
     dims = (2, 2, 2, 4)
     U, psi = fields(dims, 1, nrhs=2)
