@@ -38,9 +38,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FLOP_HOP = 1320                # flop/site, hopping term (the paper's convention)
 FLOP_FULL = 1872               # flop/site, with clover (504) and combine (48)
-# algorithmic bytes per site and right-hand side: in + out spinor + links + clover
-BYTES_SITE = {"f64": 192 + 192 + 576 + 576, "f32": 96 + 96 + 288 + 288, "f16s": 52 + 52 + 144 + 144}
+# algorithmic bytes per site and right-hand side: in + out spinor + links + clover;
+# the links are stored as two rows (4 directions x 6 complex per site; the
+# third row is rebuilt in the kernel)
+BYTES_SITE = {"f64": 192 + 192 + 384 + 576, "f32": 96 + 96 + 192 + 288, "f16s": 52 + 52 + 96 + 144}
+LINK_BYTES = {"f64": 384, "f32": 192, "f16s": 96}
 KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/csrc/dslash.h",
+                  "paper_2407_00041_amd/csrc/tune.hip",
                   "paper_2407_00041_amd/csrc/spinor_io.h", "paper_2407_00041_amd/csrc/common.h"]
 TRAFFIC_PROFILE = "profiles/dslash_f64_48x96_hbm_traffic.md"
 # mixed solver: FP64 outer FGMRES, inner GMRES on the reduced-precision operator
@@ -119,9 +123,10 @@ def batched_run(torch, op, dims, stream, steps):
         outs.append(o)
         batches.append((o, nat[r0 * rb:(r0 + s) * rb], s))
         r0 += s
+    tuned = op.autotune("f32", n)
     ms = time_launches(torch, lambda: op.apply_batched(batches, "f32", stream=stream), steps, 3, stream)
     res = {"batches": sizes, "prec": "f32", "ms_per_launch": ms, "rhs_applies_per_s": n * 1000.0 / ms,
-           "alg_GBps": (576 + 192 * n) * op.V / (ms * 1e-3) / 1e9}
+           "alg_GBps": (LINK_BYTES["f32"] + 288 + 192 * n) * op.V / (ms * 1e-3) / 1e9, "launch": tuned}
     del outs, batches, nat
     torch.cuda.empty_cache()
     return res
@@ -145,6 +150,10 @@ def fgmres_run(torch, op, dims, nrhs_total):
     wbytes = max(op.workspace_bytes(wave, 30, "f64"),
                  op.workspace_bytes(wave, pmx["restart"], pmx["mode"], pmx["inner_restart"]))
     work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    inner = "f16s" if pmx["mode"].endswith("f16s") else "f32"
+    for n in sorted({1, wave, nrhs_total % wave or wave}):     # the solvers' batched applies
+        op.autotune("f64", n)
+        op.autotune(inner, n)
     t64 = tmx = 0.0
     a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
     for w0 in range(0, nrhs_total, wave):
@@ -239,12 +248,14 @@ def main():
     U = Ud.cpu().numpy()
     del Ud
     log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
-    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"))
+    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"), compress_links=True)
     stream = torch.cuda.current_stream()
     inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
     out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}
     torch.cuda.synchronize()
 
+    tuned = {p: op.autotune(p, 1) for p in ("f64", "f32", "f16s")}
+    log(f"[bench] autotuned launches: {tuned}")
     log(f"[bench] timing FP64 apply: {a.warmup} warmup + {a.steps} steps")
     ms = time_launches(torch, lambda: op.apply_native(out["f64"], inp["f64"], 1, "f64", stream=stream),
                        a.steps, a.warmup, stream)
@@ -252,7 +263,7 @@ def main():
     gbs = BYTES_SITE["f64"] * V / (ms * 1e-3) / 1e9
     log(f"[bench] FP64: {ms:.4f} ms/apply, {apps:.1f} apps/s, {gbs:.0f} GB/s")
 
-    extra = {"f64": {"ms": ms, "apps_per_s": apps, "alg_GBps": gbs,
+    extra = {"f64": {"ms": ms, "apps_per_s": apps, "alg_GBps": gbs, "launch": tuned["f64"],
                      "GFLOPs_1320": FLOP_HOP * V / (ms * 1e-3) / 1e9,
                      "GFLOPs_1872": FLOP_FULL * V / (ms * 1e-3) / 1e9}}
     if not a.no_extra:
@@ -260,6 +271,7 @@ def main():
             m = time_launches(torch, lambda: op.apply_native(out[p], inp[p], 1, p, stream=stream),
                               max(10, a.steps // 2), a.warmup, stream)
             extra[p] = {"ms": m, "apps_per_s": 1000.0 / m, "alg_GBps": BYTES_SITE[p] * V / (m * 1e-3) / 1e9,
+                        "launch": tuned[p],
                         "GFLOPs_1320": FLOP_HOP * V / (m * 1e-3) / 1e9}
             log(f"[bench] {p}: {m:.4f} ms/apply")
     if a.copy_probe:
@@ -296,10 +308,12 @@ def main():
         "data": "synthetic (seeded exp(0.3iH) SU(3) links, Gaussian spinors)",
         "config": {"workload": f"Wilson-clover D apply, {dims[1]}^3x{dims[0]} (T,Z,Y,X = {list(dims)}), "
                                f"FP64, 1 RHS, csw={a.csw}, m0={a.m0}, periodic",
-                   "lattice": list(dims), "sites": V, "nrhs": 1, "parallelism": "single GPU"},
+                   "lattice": list(dims), "sites": V, "nrhs": 1, "parallelism": "single GPU",
+                   "link_storage": "two rows per SU(3) link (third rebuilt in the kernel)"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
-                     "kernel": "wd::dslash_kernel<0, false, 1>",
+                     "kernel": ("wd::dslash_column_kernel<0, false, 1>" if tuned["f64"]["order"] == 3
+                                else "wd::dslash_kernel<0, false, 1>"),
                      "alg_bytes_per_site": BYTES_SITE["f64"], "alg_bytes_per_launch": BYTES_SITE["f64"] * V,
                      "kernel_source_sha256_16": kernel_hash()},
         "extra": extra,

@@ -78,6 +78,8 @@ extern "C" {
 #define WDIRAC_ANTIPERIODIC_T 1u /* hops across the T boundary get sign -1 */
 #define WDIRAC_WITH_F32 2u       /* also materialise FP32 links + clover    */
 #define WDIRAC_WITH_F16 4u       /* also materialise FP16 links + clover    */
+#define WDIRAC_COMPRESS_LINKS 8u /* store two rows per link; the third is
+                                    rebuilt as conj(row0 x row1) (SU(3) only) */
 
 typedef struct dirac_op dirac_op;
 
@@ -97,9 +99,13 @@ const char *dirac_version(void);
  *            from the links on the device (Eqs. (1.11)-(1.12)).
  *   m0,csw : mass and clover coefficient; A(x) = (4 + m0) I + csw C(x).
  *   flags  : WDIRAC_* flags above.  FP64 data are always materialised.
+ *            WDIRAC_COMPRESS_LINKS keeps 2 of the 3 rows of every link (the
+ *            third row of an SU(3) matrix is conj(row0 x row1)); it needs
+ *            |U U^H - 1| and |det U - 1| <= 1e-12 for every link.
  * Synchronous.  Copies everything into device memory owned by the handle;
  * the caller may free its arrays on return.  Errors: EINVAL (null pointer,
- * dims < 2), ENOMEM, EHIP, EUNSUPPORTED (no HIP device).
+ * dims < 2, non-SU(3) links with WDIRAC_COMPRESS_LINKS), ENOMEM, EHIP,
+ * EUNSUPPORTED (no HIP device).
  */
 int dirac_create(dirac_op **op, const int dims[4], const double *links, const double *clover,
                  double m0, double csw, unsigned flags);
@@ -158,11 +164,31 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * "persistent_blocks" (cap on the work-groups of a dirac_apply_batched launch;
  * 0, the default, means all work-groups that fit on the device at once),
  * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
- * or 4).  Not synchronised with launches in flight; set before applying.
+ * or 4).  Setting any of these launch knobs makes them override autotuned
+ * choices; "explicit" = 0 returns to the autotuned ones (1 forces the knobs).
+ * Not synchronised with launches in flight; set before applying.
  * Errors: EINVAL (unknown key or value out of range).
  */
 int dirac_tune_set(const char *key, int value);
 int dirac_tune_get(const char *key, int *value);
+
+/*
+ * Autotuner: time candidate launch configurations of the stencil (tile order,
+ * work-group size, T-chunk, register block) for this operator, precision and
+ * nrhs right-hand sides in one launch, on temporary device buffers, and keep
+ * the fastest for every later launch with the same lattice extents,
+ * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...) and link format.
+ * The choice is appended to the JSON-lines file named by the environment
+ * variable WDIRAC_TUNE_CACHE when it is set; that file is read back the first
+ * time a configuration is looked up.  Synchronous; allocates.
+ *   cfg_out (optional): {order, block, tchunk, nr} chosen; us_out (optional):
+ *   its time per launch in microseconds.
+ * Errors: EINVAL, EUNSUPPORTED (precision not materialised), ENOMEM, EHIP.
+ */
+int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_out[4], double *us_out, void *stream);
+
+/* Forget every autotuned configuration of this process. */
+int dirac_tune_clear(void);
 
 /*
  * Canonical <-> native conversion of device fields.

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ANTIPERIODIC_T, EUNSUPPORTED, F16S, F32, F64, FGMRES_F64,  # noqa: F401
+from ._lib import (ANTIPERIODIC_T, COMPRESS_LINKS, EUNSUPPORTED, F16S, F32, F64, FGMRES_F64,  # noqa: F401
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
 PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
@@ -50,13 +50,17 @@ class DiracOp:
     """
 
     def __init__(self, dims, links, m0: float, csw: float = 0.0, clover=None,
-                 antiperiodic_t: bool = False, precisions=("f64", "f32", "f16s")):
+                 antiperiodic_t: bool = False, precisions=("f64", "f32", "f16s"),
+                 compress_links: bool = False):
         self.lib = _lib.load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(np.prod(self.dims))
         self.m0, self.csw = float(m0), float(csw)
         self.antiperiodic_t = bool(antiperiodic_t)
         flags = ANTIPERIODIC_T if antiperiodic_t else 0
+        if compress_links:
+            flags |= COMPRESS_LINKS
+        self.compress_links = bool(compress_links)
         if "f32" in precisions:
             flags |= WITH_F32
         if "f16s" in precisions:
@@ -181,6 +185,14 @@ class DiracOp:
                         "hist": [s.hist[i] for i in range(s.nhist)]})
         return x, out, rc
 
+    def autotune(self, prec="f64", nrhs: int = 1, stream=None) -> dict:
+        """Time candidate launch configurations and keep the fastest (dirac_autotune)."""
+        cfg = (ctypes.c_int * 4)()
+        us = ctypes.c_double()
+        check(self.lib.dirac_autotune(self.handle, _prec(prec), int(nrhs), cfg, ctypes.byref(us), _stream(stream)),
+              "dirac_autotune")
+        return {"order": cfg[0], "block": cfg[1], "tchunk": cfg[2], "nr": cfg[3], "us": us.value}
+
     def force(self, eta: torch.Tensor, x: torch.Tensor, nrhs: int = 1, raw: bool = False,
               stream=None) -> torch.Tensor:
         """dL/dU for L = Re sum <eta, D x>; eta, x native FP64.  [V, 4, 3, 3] c128."""
@@ -201,7 +213,7 @@ def tune_get(key: str) -> int:
     return int(v.value)
 
 
-TUNE_KEYS = ("block", "order", "tchunk", "persistent_blocks", "nr_f64", "nr_f32", "nr_f16s")
+TUNE_KEYS = ("block", "order", "tchunk", "persistent_blocks", "nr_f64", "nr_f32", "nr_f16s", "explicit")
 
 
 def clover_term(dims, links_dev: torch.Tensor, stream=None) -> torch.Tensor:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libwdirac.so")
 
 F64, F32, F16S = 0, 1, 2
-ANTIPERIODIC_T, WITH_F32, WITH_F16 = 1, 2, 4
+ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS = 1, 2, 4, 8
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV = 0, -1, -2, -3, -4, 1
 FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S = 0, 1, 2
 FGMRES_HIST_MAX = 4096
@@ -52,6 +52,8 @@ SIGNATURES = {
     "dirac_apply_batched": (_I, [_P, ctypes.POINTER(DiracBatch), _I, _I, _I, _P]),
     "dirac_tune_set": (_I, [ctypes.c_char_p, _I]),
     "dirac_tune_get": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
+    "dirac_autotune": (_I, [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double), _P]),
+    "dirac_tune_clear": (_I, []),
     "dirac_pack": (_I, [_P, _P, _P, _I, _I, _P]),
     "dirac_unpack": (_I, [_P, _P, _P, _I, _I, _P]),
     "dirac_clover_term": (_I, [_P, _P, _P, _P]),

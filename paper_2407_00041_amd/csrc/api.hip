@@ -12,8 +12,10 @@ hipError_t unpack_launch(double *can, const void *nat, int nrhs, int prec, int V
 hipError_t clover_build_launch(double *out, const double *links, const Geom &g, hipStream_t st);
 hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const double *clover_can_dev,
                               hipStream_t st);
+hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStream_t st);
 
 static thread_local std::string g_err;
+constexpr double kSu3Tol = 1e-12;  // largest |U U^H - 1|, |det U - 1| accepted for two-row storage
 
 void set_error(const std::string &msg) { g_err = msg; }
 
@@ -104,6 +106,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     op->csw = csw;
     op->flags = flags;
     (void)hipGetDevice(&op->device);
+    op->link_rows = (flags & WDIRAC_COMPRESS_LINKS) ? 2 : 3;
+    const size_t lr = (size_t)op->link_rows * 3;  // stored complex entries per link
     const size_t nl = (size_t)V * 36 * 16, nc = (size_t)V * 42 * 16;
     double *lc = nullptr, *cc = nullptr;
     int rc = WDIRAC_OK;
@@ -117,18 +121,31 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     };
     hipStream_t st = nullptr;
     do {
-        if (!alloc((void **)&op->links64, nl) || !alloc((void **)&op->clover64, (size_t)V * 36 * 16)) break;
-        if ((flags & WDIRAC_WITH_F32) &&
-            (!alloc((void **)&op->links32, (size_t)V * 36 * 8) || !alloc((void **)&op->clover32, (size_t)V * 72 * 4)))
+        if (!alloc((void **)&op->links64, (size_t)V * 4 * lr * 16) || !alloc((void **)&op->clover64, (size_t)V * 36 * 16))
             break;
-        if ((flags & WDIRAC_WITH_F16) &&
-            (!alloc((void **)&op->links16, (size_t)V * 36 * 4) || !alloc((void **)&op->clover16, (size_t)V * 72 * 2)))
+        if ((flags & WDIRAC_WITH_F32) && (!alloc((void **)&op->links32, (size_t)V * 4 * lr * 8) ||
+                                          !alloc((void **)&op->clover32, (size_t)V * 72 * 4)))
+            break;
+        if ((flags & WDIRAC_WITH_F16) && (!alloc((void **)&op->links16, (size_t)V * 4 * lr * 4) ||
+                                          !alloc((void **)&op->clover16, (size_t)V * 72 * 2)))
             break;
         if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
         lc = op->links_canon;
         if (hipMemcpy(lc, links, nl, hipMemcpyHostToDevice) != hipSuccess) {
             rc = fail(WDIRAC_EHIP, "copy of links to the device failed");
             break;
+        }
+        if (op->link_rows == 2) {
+            double dev = 0;
+            if (su3_deviation(lc, (int)V, &dev, st) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "SU(3) check failed to run");
+                break;
+            }
+            if (!(dev <= kSu3Tol)) {
+                rc = fail(WDIRAC_EINVAL, "two-row link storage needs SU(3) links; largest deviation " +
+                                             std::to_string(dev) + " exceeds 1e-12");
+                break;
+            }
         }
         if (clover) {
             if (hipMemcpy(cc, clover, nc, hipMemcpyHostToDevice) != hipSuccess) {
@@ -200,6 +217,11 @@ int dirac_tune_set(const char *key, int value) {
     if (!key) return fail(WDIRAC_EINVAL, "null key");
     Tuning &t = tuning();
     std::string k(key);
+    if (k == "explicit") {
+        t.explicit_launch = value != 0;
+        return WDIRAC_OK;
+    }
+    if (k != "persistent_blocks") t.explicit_launch = true;  // a launch knob set by hand wins over tuned ones
     if (k == "block") {
         if (value < 64 || value > 256 || value % 64) return fail(WDIRAC_EINVAL, "block must be 64, 128, 192 or 256");
         t.block = value;
@@ -226,6 +248,7 @@ int dirac_tune_get(const char *key, int *value) {
     const Tuning &t = tuning();
     std::string k(key);
     if (k == "block") *value = t.block;
+    else if (k == "explicit") *value = t.explicit_launch ? 1 : 0;
     else if (k == "order") *value = t.order;
     else if (k == "tchunk") *value = t.tchunk;
     else if (k == "persistent_blocks") *value = t.persistent_blocks;

@@ -40,18 +40,31 @@ struct TileMap {
 
 TileMap make_tilemap(const Geom &g, int order, int block, int tchunk);
 
+// One launch configuration of the stencil.
+struct LaunchCfg {
+    int order, block, tchunk, nr;
+};
+
+// Autotuned configurations, keyed by lattice, precision, right-hand-side
+// bucket and link format (see tune.hip); returns false when none is stored.
+bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, LaunchCfg &out);
+
 // Process-wide launch parameters (set through dirac_tune_set).
 struct Tuning {
     int block = 256;             // threads per work-group: 64, 128, 192 or 256
     int order = kOrderTSweep;    // tile order
-    int tchunk = 8;              // kOrderColumn: T sites per lane
+    int tchunk = 4;              // kOrderColumn: T sites per lane
     int persistent_blocks = 0;   // cap on the persistent grid (0: all co-resident work-groups)
     int nr[3] = {2, 2, 2};       // register block size per precision (1, 2 or 4)
+    bool explicit_launch = false;  // set by dirac_tune_set: use these values, ignore autotuned ones
 };
 
 Tuning &tuning();
 
 hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
                                  const Geom &g, int apbc, bool persistent, hipStream_t st);
+// same, with an explicit launch configuration (the autotuner's timing runs)
+hipError_t dslash_launch_cfg(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
+                             const Geom &g, int apbc, bool persistent, const LaunchCfg &cfg, hipStream_t st);
 
 }  // namespace wd

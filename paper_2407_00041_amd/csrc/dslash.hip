@@ -137,7 +137,7 @@ __device__ __forceinline__ void hop_pair(const Chunk<NR> &ch, const OpData &d, i
     // forward: -1/2 (I + SF gamma) (x) U_mu(x) psi(x+mu)
     {
         const T f = (MU == 0 && apbc && nb.fwd_wrapT) ? T(0.5) : T(-0.5);
-        Store<P>::load_link(d.links, V, MU, s, U);
+        Store<P>::load_link(d.links, V, MU, s, U, d.rows);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (r < ch.nr) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ void hop_pair(const Chunk<NR> &ch, const OpData &d, i
     // backward: -1/2 (I + SB gamma) (x) U_mu(x-mu)^H psi(x-mu)
     {
         const T f = (MU == 0 && apbc && nb.bwd_wrapT) ? T(0.5) : T(-0.5);
-        Store<P>::load_link(d.links, V, MU, nb.bwd[MU], U);
+        Store<P>::load_link(d.links, V, MU, nb.bwd[MU], U, d.rows);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (r < ch.nr) {
@@ -232,7 +232,7 @@ __device__ __forceinline__ void column_sweep(const Chunk<NR> &ch, const OpData &
         const int tm = (t0 == 0) ? nT - 1 : t0 - 1;
         const T f = (apbc && t0 == 0) ? T(0.5) : T(-0.5);
         cx<T> U[9];
-        Store<P>::load_link(d.links, V, 0, tm * S + c, U);
+        Store<P>::load_link(d.links, V, 0, tm * S + c, U, d.rows);
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (r < ch.nr) {
@@ -262,7 +262,7 @@ __device__ __forceinline__ void column_sweep(const Chunk<NR> &ch, const OpData &
         {
             const T f = (apbc && last) ? T(0.5) : T(-0.5);
             cx<T> U[9];
-            Store<P>::load_link(d.links, V, 0, s, U);
+            Store<P>::load_link(d.links, V, 0, s, U, d.rows);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 if (r < ch.nr) {
@@ -293,7 +293,7 @@ __device__ __forceinline__ void column_sweep(const Chunk<NR> &ch, const OpData &
             const int sp = (last ? 0 : t + 1) * S + c;
             const T f = (apbc && last) ? T(0.5) : T(-0.5);
             cx<T> U[9];
-            Store<P>::load_link(d.links, V, 0, s, U);
+            Store<P>::load_link(d.links, V, 0, s, U, d.rows);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 if (r < ch.nr) {
@@ -462,10 +462,29 @@ static int resident_blocks(int block) {
 }
 
 template <int P, bool DAG, int NR>
+static int resident_blocks_col(int block) {
+    static int cached[5] = {0, 0, 0, 0, 0};
+    const int slot = block / 64;
+    if (!cached[slot]) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dslash_column_kernel<P, DAG, NR>, block, 0) !=
+                hipSuccess ||
+            cus * per_cu < 8) {
+            (void)hipGetLastError();
+            return 8;
+        }
+        cached[slot] = cus * per_cu / 8 * 8;
+    }
+    return cached[slot];
+}
+
+template <int P, bool DAG, int NR>
 static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpData &d, const Geom &g, int apbc,
-                                bool persistent, hipStream_t st) {
+                                bool persistent, const LaunchCfg &cfg, hipStream_t st) {
     const Tuning &tu = g_tuning;
-    const TileMap m = make_tilemap(g, tu.order, tu.block, tu.tchunk);
+    const TileMap m = make_tilemap(g, cfg.order, cfg.block, cfg.tchunk);
     for (size_t c0 = 0; c0 < chunks.size(); c0 += kMaxChunks) {
         ChunkTable<NR> tab;
         tab.nchunks = (int)std::min(chunks.size() - c0, (size_t)kMaxChunks);
@@ -475,18 +494,19 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
         if (persistent) {
             // every work-group must be resident, so that the work-groups of an
             // XCD walk through its items together (in order)
-            long long cap = resident_blocks<P, DAG, NR>(tu.block);
+            long long cap = m.order == kOrderColumn ? resident_blocks_col<P, DAG, NR>(cfg.block)
+                                                    : resident_blocks<P, DAG, NR>(cfg.block);
             if (tu.persistent_blocks > 0 && tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
             if (cap < 8) cap = 8;
             if (grid > cap) grid = cap;
         }
         if (grid > (1LL << 30)) return hipErrorInvalidValue;
         if (m.order == kOrderColumn)
-            hipLaunchKernelGGL((dslash_column_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d,
-                               g, m, apbc);
+            hipLaunchKernelGGL((dslash_column_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(cfg.block), 0, st, tab,
+                               d, g, m, apbc);
         else
-            hipLaunchKernelGGL((dslash_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(tu.block), 0, st, tab, d, g, m,
-                               apbc);
+            hipLaunchKernelGGL((dslash_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(cfg.block), 0, st, tab, d, g,
+                               m, apbc);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -497,7 +517,7 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
 // of at most NR (a block may span batches).
 template <int P, bool DAG, int NR>
 static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
-                            bool persistent, hipStream_t st) {
+                            bool persistent, const LaunchCfg &cfg, hipStream_t st) {
     const size_t rb = field_rhs_bytes(P, g.V);
     std::vector<std::pair<const void *, void *>> rhs;
     for (int b = 0; b < nbatch; b++)
@@ -515,36 +535,48 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
         }
         chunks.push_back(c);
     }
-    return launch_chunks<P, DAG, NR>(chunks, d, g, apbc, persistent, st);
+    return launch_chunks<P, DAG, NR>(chunks, d, g, apbc, persistent, cfg, st);
 }
 
 template <int P, bool DAG>
 static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
-                           bool persistent, hipStream_t st) {
+                           bool persistent, LaunchCfg cfg, hipStream_t st) {
     int total = 0;
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
-    int nr = g_tuning.nr[P];
-    if (total == 1) nr = 1;
-    if (g_tuning.order == kOrderColumn && P == WDIRAC_F64 && nr > 2) nr = 2;  // register budget
-    if (nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, st);
-    if (nr >= 2) return launch_nr<P, DAG, 2>(batches, nbatch, d, g, apbc, persistent, st);
-    return launch_nr<P, DAG, 1>(batches, nbatch, d, g, apbc, persistent, st);
+    if (total == 1) cfg.nr = 1;
+    if (cfg.order == kOrderColumn && P == WDIRAC_F64 && cfg.nr > 2) cfg.nr = 2;  // register budget
+    if (cfg.nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, cfg, st);
+    if (cfg.nr >= 2) return launch_nr<P, DAG, 2>(batches, nbatch, d, g, apbc, persistent, cfg, st);
+    return launch_nr<P, DAG, 1>(batches, nbatch, d, g, apbc, persistent, cfg, st);
 }
 
-hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
-                                 const Geom &g, int apbc, bool persistent, hipStream_t st) {
+hipError_t dslash_launch_cfg(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
+                             const Geom &g, int apbc, bool persistent, const LaunchCfg &cfg, hipStream_t st) {
     switch (prec) {
     case WDIRAC_F64:
-        return dagger ? launch_p<WDIRAC_F64, true>(batches, nbatch, d, g, apbc, persistent, st)
-                      : launch_p<WDIRAC_F64, false>(batches, nbatch, d, g, apbc, persistent, st);
+        return dagger ? launch_p<WDIRAC_F64, true>(batches, nbatch, d, g, apbc, persistent, cfg, st)
+                      : launch_p<WDIRAC_F64, false>(batches, nbatch, d, g, apbc, persistent, cfg, st);
     case WDIRAC_F32:
-        return dagger ? launch_p<WDIRAC_F32, true>(batches, nbatch, d, g, apbc, persistent, st)
-                      : launch_p<WDIRAC_F32, false>(batches, nbatch, d, g, apbc, persistent, st);
+        return dagger ? launch_p<WDIRAC_F32, true>(batches, nbatch, d, g, apbc, persistent, cfg, st)
+                      : launch_p<WDIRAC_F32, false>(batches, nbatch, d, g, apbc, persistent, cfg, st);
     case WDIRAC_F16S:
-        return dagger ? launch_p<WDIRAC_F16S, true>(batches, nbatch, d, g, apbc, persistent, st)
-                      : launch_p<WDIRAC_F16S, false>(batches, nbatch, d, g, apbc, persistent, st);
+        return dagger ? launch_p<WDIRAC_F16S, true>(batches, nbatch, d, g, apbc, persistent, cfg, st)
+                      : launch_p<WDIRAC_F16S, false>(batches, nbatch, d, g, apbc, persistent, cfg, st);
     }
     return hipErrorInvalidValue;
+}
+
+// The configuration of a launch: the autotuned one for this lattice,
+// precision, right-hand-side count and link format if there is one, else
+// the process-wide defaults.
+hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
+                                 const Geom &g, int apbc, bool persistent, hipStream_t st) {
+    int total = 0;
+    for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
+    const Tuning &tu = g_tuning;
+    LaunchCfg cfg{tu.order, tu.block, tu.tchunk, (prec >= 0 && prec < 3) ? tu.nr[prec] : 1};
+    if (!tu.explicit_launch) tuned_cfg(g, prec, total, d.rows, cfg);
+    return dslash_launch_cfg(batches, nbatch, prec, dagger, d, g, apbc, persistent, cfg, st);
 }
 
 }  // namespace wd

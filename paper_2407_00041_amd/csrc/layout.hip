@@ -6,6 +6,8 @@
 // Each thread owns one site: it reads the site's contiguous canonical record
 // (whole cache lines per wavefront) and writes each native component at
 // consecutive sites across the wavefront.
+#include <cstring>
+
 #include "spinor_io.h"
 
 namespace wd {
@@ -113,13 +115,68 @@ hipError_t unpack_launch(double *can, const void *nat, int nrhs, int prec, int V
 // ---------------------------------------------------------------------------
 // operator data
 
-// canonical links [V][4][3][3] c128 -> native FP64 [4][9][V] double2
+// canonical links [V][4][3][3] c128 -> native FP64 [4][rows*3][V] double2
+// (rows = 2 keeps the first two rows of every link)
 __global__ __launch_bounds__(256) void links_to_native(double2 *__restrict__ nat, const double2 *__restrict__ can,
-                                                       int V) {
+                                                       int V, int rows) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
-#pragma unroll
-    for (int e = 0; e < 36; e++) nat[(size_t)e * V + s] = can[(size_t)36 * s + e];
+    const int ne = 3 * rows;
+    for (int mu = 0; mu < 4; mu++)
+        for (int e = 0; e < ne; e++) nat[(size_t)(mu * ne + e) * V + s] = can[(size_t)36 * s + 9 * mu + e];
+}
+
+// largest deviation of a link from SU(3): max |U U^H - 1| and |det U - 1|,
+// folded into *worst with an integer max on the bits of a non-negative double
+__global__ __launch_bounds__(256) void su3_check(const double2 *__restrict__ can, int n,
+                                                 unsigned long long *__restrict__ worst) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const double2 *u = can + (size_t)9 * l;
+    double dev = 0.0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double re = 0, im = 0;
+            for (int k = 0; k < 3; k++) {  // (U U^H)_ij = sum_k U_ik conj(U_jk)
+                double2 a = u[3 * i + k], b = u[3 * j + k];
+                re += a.x * b.x + a.y * b.y;
+                im += a.y * b.x - a.x * b.y;
+            }
+            if (i == j) re -= 1.0;
+            dev = fmax(dev, sqrt(re * re + im * im));
+        }
+    // det by the first row's cofactors
+    auto mul = [](double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+    double2 c0 = mul(u[4], u[8]), c0b = mul(u[5], u[7]);
+    double2 c1 = mul(u[5], u[6]), c1b = mul(u[3], u[8]);
+    double2 c2 = mul(u[3], u[7]), c2b = mul(u[4], u[6]);
+    double2 m0 = make_double2(c0.x - c0b.x, c0.y - c0b.y), m1 = make_double2(c1.x - c1b.x, c1.y - c1b.y),
+            m2 = make_double2(c2.x - c2b.x, c2.y - c2b.y);
+    double2 d0 = mul(u[0], m0), d1 = mul(u[1], m1), d2 = mul(u[2], m2);
+    double dr = d0.x + d1.x + d2.x - 1.0, di = d0.y + d1.y + d2.y;
+    dev = fmax(dev, sqrt(dr * dr + di * di));
+    if (!(dev == dev)) dev = 1e300;  // NaN
+    atomicMax(worst, (unsigned long long)__double_as_longlong(dev));
+}
+
+hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStream_t st) {
+    unsigned long long *w = nullptr;
+    hipError_t e = hipMalloc(&w, sizeof(*w));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(w, 0, sizeof(*w), st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(su3_check, dim3((4 * V + 255) / 256), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(links_can_dev), 4 * V, w);
+        e = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, w, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(w);
+    double d;
+    memcpy(&d, &h, sizeof(d));
+    *out = d;
+    return e;
 }
 
 // canonical unit clover [V][42] c128 -> native FP64 A(x) = (4+m0) I + csw C(x):
@@ -140,6 +197,22 @@ __global__ __launch_bounds__(256) void clover_to_native(double2 *__restrict__ na
         for (int e = 0; e < 15; e++) {
             double2 u = c[21 * b + 6 + e];
             o[(size_t)(3 + e) * V + s] = make_double2(csw * u.x, csw * u.y);
+        }
+    }
+}
+
+// native FP64 links (two stored rows) -> FP32 [4][3][V] float4 / FP16 [4][3][V] 4 x half
+__global__ __launch_bounds__(256) void links_narrow2(float4 *__restrict__ o32, half4 *__restrict__ o16,
+                                                     const double2 *__restrict__ nat, int V) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    for (int q = 0; q < 12; q++) {  // (mu, pair) pairs of the [4][6] entries
+        double2 a = nat[(size_t)(2 * q) * V + s], b = nat[(size_t)(2 * q + 1) * V + s];
+        if (o32) o32[(size_t)q * V + s] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        if (o16) {
+            half4 h;
+            h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)b.x; h[3] = (_Float16)b.y;
+            o16[(size_t)q * V + s] = h;
         }
     }
 }
@@ -185,13 +258,18 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
     int V = op->g.V;
     dim3 grid((V + 255) / 256);
     hipLaunchKernelGGL(links_to_native, grid, dim3(256), 0, st, (double2 *)op->links64,
-                       (const double2 *)links_can_dev, V);
+                       (const double2 *)links_can_dev, V, op->link_rows);
     hipLaunchKernelGGL(clover_to_native, grid, dim3(256), 0, st, (double2 *)op->clover64,
                        (const double2 *)clover_can_dev, V, 4.0 + op->m0, op->csw);
     if (op->links32 || op->links16) {
-        size_t n = (size_t)36 * V;
-        hipLaunchKernelGGL(links_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                           (float2 *)op->links32, (half2v *)op->links16, (const double2 *)op->links64, n);
+        if (op->link_rows == 2) {
+            hipLaunchKernelGGL(links_narrow2, grid, dim3(256), 0, st, (float4 *)op->links32, (half4 *)op->links16,
+                               (const double2 *)op->links64, V);
+        } else {
+            size_t n = (size_t)36 * V;
+            hipLaunchKernelGGL(links_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                               (float2 *)op->links32, (half2v *)op->links16, (const double2 *)op->links64, n);
+        }
         hipLaunchKernelGGL(clover_narrow, grid, dim3(256), 0, st, (float4 *)op->clover32, (half4 *)op->clover16,
                            (const double2 *)op->clover64, V);
     }

@@ -25,6 +25,17 @@ template <typename V> __device__ __forceinline__ V ld_once(const V *p) {
     return *p;
 }
 
+// third row of an SU(3) matrix from the first two: conj(row0 x row1)
+template <typename T> __device__ __forceinline__ void third_row(cx<T> U[9]) {
+    const cx<T> a0 = U[0], a1 = U[1], a2 = U[2], b0 = U[3], b1 = U[4], b2 = U[5];
+    const cx<T> c0 = cmul(a1, b2) - cmul(a2, b1);
+    const cx<T> c1 = cmul(a2, b0) - cmul(a0, b2);
+    const cx<T> c2 = cmul(a0, b1) - cmul(a1, b0);
+    U[6] = {c0.r, -c0.i};
+    U[7] = {c1.r, -c1.i};
+    U[8] = {c2.r, -c2.i};
+}
+
 template <int P> struct Store;
 
 // ---------------------------------------------------------------- FP64
@@ -55,8 +66,18 @@ template <> struct Store<WDIRAC_F64> {
             __builtin_nontemporal_store(a, &p[(size_t)k * V + s]);
         }
     }
-    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9],
+                                                     int rows = 3) {
         const double2 *p = static_cast<const double2 *>(base);
+        if (rows == 2) {
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                double2 a = p[(size_t)(mu * 6 + e) * V + s];
+                U[e] = {a.x, a.y};
+            }
+            third_row(U);
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 9; e++) {
             double2 a = p[(size_t)(mu * 9 + e) * V + s];
@@ -110,7 +131,19 @@ template <> struct Store<WDIRAC_F32> {
             __builtin_nontemporal_store(a, &p[(size_t)k * V + s]);
         }
     }
-    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9],
+                                                     int rows = 3) {
+        if (rows == 2) {
+            const float4 *q = static_cast<const float4 *>(base);
+#pragma unroll
+            for (int e = 0; e < 3; e++) {
+                float4 a = q[(size_t)(mu * 3 + e) * V + s];
+                U[2 * e] = {a.x, a.y};
+                U[2 * e + 1] = {a.z, a.w};
+            }
+            third_row(U);
+            return;
+        }
         const float2 *p = static_cast<const float2 *>(base);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
@@ -174,7 +207,19 @@ template <> struct Store<WDIRAC_F16S> {
         float *sp = reinterpret_cast<float *>(static_cast<char *>(base) + (size_t)48 * V);
         __builtin_nontemporal_store(m, &sp[s]);
     }
-    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9]) {
+    static __device__ __forceinline__ void load_link(const void *base, int V, int mu, int s, cx<T> U[9],
+                                                     int rows = 3) {
+        if (rows == 2) {
+            const half4 *q = static_cast<const half4 *>(base);
+#pragma unroll
+            for (int e = 0; e < 3; e++) {
+                half4 a = q[(size_t)(mu * 3 + e) * V + s];
+                U[2 * e] = {(float)a[0], (float)a[1]};
+                U[2 * e + 1] = {(float)a[2], (float)a[3]};
+            }
+            third_row(U);
+            return;
+        }
         const half2v *p = static_cast<const half2v *>(base);
 #pragma unroll
         for (int e = 0; e < 9; e++) {

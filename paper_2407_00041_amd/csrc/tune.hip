@@ -1,0 +1,172 @@
+// Autotuner of the stencil's launch configuration.
+//
+// For one operator, precision and number of right-hand sides the tuner times
+// a small set of candidate configurations (tile order, work-group size,
+// T-chunk of the column sweep, register block) with HIP events on temporary
+// buffers and keeps the fastest.  Choices are stored per (lattice extents,
+// precision, right-hand-side bucket, link format) and used by every later
+// launch with that key; they can be appended to a JSON-lines cache file
+// (environment variable WDIRAC_TUNE_CACHE) and are read back from it the first
+// time a key is looked up in a new process.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dslash.h"
+
+namespace wd {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, LaunchCfg> g_table;
+bool g_loaded = false;
+
+int bucket(int nrhs) {
+    int b = 0;
+    while ((1 << b) < nrhs && b < 6) b++;
+    return b;  // 1 -> 0, 2 -> 1, 3..4 -> 2, 5..8 -> 3, ..., > 32 -> 6
+}
+
+std::string key_of(const Geom &g, int prec, int nrhs, int rows) {
+    char buf[128];
+    snprintf(buf, sizeof(buf), "gfx950|%dx%dx%dx%d|p%d|b%d|r%d", g.n[0], g.n[1], g.n[2], g.n[3], prec, bucket(nrhs),
+             rows);
+    return buf;
+}
+
+void load_cache_locked() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = getenv("WDIRAC_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512], key[256];
+    while (fgets(line, sizeof(line), f)) {
+        LaunchCfg c;
+        double us;
+        if (sscanf(line, "{\"key\": \"%255[^\"]\", \"order\": %d, \"block\": %d, \"tchunk\": %d, \"nr\": %d, \"us\": %lf",
+                   key, &c.order, &c.block, &c.tchunk, &c.nr, &us) == 6) {
+            if (c.order >= 0 && c.order <= 3 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
+                c.tchunk >= 1 && (c.nr == 1 || c.nr == 2 || c.nr == 4))
+                g_table[key] = c;
+        }
+    }
+    fclose(f);
+}
+
+}  // namespace
+
+bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, LaunchCfg &out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    auto it = g_table.find(key_of(g, prec, nrhs, rows));
+    if (it == g_table.end()) return false;
+    out = it->second;
+    return true;
+}
+
+int check_apply(const dirac_op *op, const void *out, const void *in, int nrhs, int prec);
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_out[4], double *us_out,
+                              void *stream) {
+    if (!op) return fail(WDIRAC_EINVAL, "null operator");
+    if (nrhs < 1 || nrhs > 256) return fail(WDIRAC_EINVAL, "nrhs must be in [1, 256]");
+    if (prec != WDIRAC_F64 && prec != WDIRAC_F32 && prec != WDIRAC_F16S) return fail(WDIRAC_EINVAL, "unknown precision");
+    if (!op->data(prec).links) return fail(WDIRAC_EUNSUPPORTED, "precision not materialised at create");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = field_rhs_bytes(prec, op->g.V) * (size_t)nrhs;
+    void *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, bytes) != hipSuccess || hipMalloc(&out, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (in) (void)hipFree(in);
+        return fail(WDIRAC_ENOMEM, "autotune buffers");
+    }
+    int rc = WDIRAC_OK;
+    std::vector<LaunchCfg> cands;
+    const int nrs[3] = {1, 2, 4};
+    for (int order : {2, 3})
+        for (int block : {128, 256})
+            for (int tchunk : {2, 4, 8}) {
+                if (order != 3 && tchunk != 4) continue;
+                for (int nr : nrs) {
+                    if (nr > 1 && nr > nrhs) continue;
+                    if (nrhs == 1 && nr > 1) continue;
+                    if (order == 3 && prec == WDIRAC_F64 && nr > 2) continue;
+                    cands.push_back({order, block, tchunk, nr});
+                }
+            }
+    const dirac_batch b{out, in, nrhs};
+    const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LaunchCfg best{};
+    float best_ms = 1e30f;
+    do {
+        if (hipMemsetAsync(in, 0, bytes, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            rc = fail(WDIRAC_EHIP, "autotune setup");
+            break;
+        }
+        const int reps = nrhs > 8 ? 2 : 3;
+        for (const LaunchCfg &c : cands) {
+            hipError_t e = dslash_launch_cfg(&b, 1, prec, false, op->data(prec), op->g, apbc, false, c, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; r++)
+                e = dslash_launch_cfg(&b, 1, prec, false, op->data(prec), op->g, apbc, false, c, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, std::string("autotune launch: ") + hipGetErrorString(e));
+                break;
+            }
+            ms /= reps;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    if (rc) return rc;
+    const std::string key = key_of(op->g, prec, nrhs, op->link_rows);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_cache_locked();
+        g_table[key] = best;
+        if (const char *path = getenv("WDIRAC_TUNE_CACHE")) {
+            if (FILE *f = fopen(path, "a")) {
+                fprintf(f, "{\"key\": \"%s\", \"order\": %d, \"block\": %d, \"tchunk\": %d, \"nr\": %d, \"us\": %.1f}\n",
+                        key.c_str(), best.order, best.block, best.tchunk, best.nr, best_ms * 1000.0);
+                fclose(f);
+            }
+        }
+    }
+    if (cfg_out) {
+        cfg_out[0] = best.order;
+        cfg_out[1] = best.block;
+        cfg_out[2] = best.tchunk;
+        cfg_out[3] = best.nr;
+    }
+    if (us_out) *us_out = best_ms * 1000.0;
+    return WDIRAC_OK;
+}
+
+extern "C" int dirac_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+    g_loaded = true;  // do not re-read the cache file
+    return WDIRAC_OK;
+}

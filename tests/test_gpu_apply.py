@@ -147,3 +147,28 @@ def test_full_size_sampled_sites(dims):
         assert rel_l2(got, want) < TOL[prec], prec
     del op
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dims,kind,m0,csw,ap", CASES[1:4])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_two_row_links_match_oracle(dims, kind, m0, csw, ap, prec, dagger):
+    """Two stored rows per link, third rebuilt as conj(row0 x row1)."""
+    need_gpu()
+    U, psi = fields(dims, 17, kind, nrhs=3)
+    op = DiracOp(dims, U, m0, csw, antiperiodic_t=ap, compress_links=True)
+    got = op.apply(to_dev(psi), prec, dagger=dagger).cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, m0, csw, antiperiodic_t=ap, dagger=dagger)
+    for r in range(3):
+        assert rel_l2(got[r], want[r]) < TOL[prec], (r, rel_l2(got[r], want[r]))
+
+
+def test_two_row_links_reject_non_su3():
+    need_gpu()
+    dims = (2, 2, 2, 4)
+    U, _ = fields(dims, 3, "haar")
+    U[5, 2] *= 1.0 + 1e-9                 # no longer unitary
+    with pytest.raises(WdiracError) as e:
+        DiracOp(dims, U, -0.3, 1.0, compress_links=True)
+    assert e.value.code == -1
+    DiracOp(dims, U, -0.3, 1.0)            # full storage accepts any links

@@ -138,3 +138,16 @@ def test_batched_argument_errors(restore_tuning):
         tune_set("block", 100)
     with pytest.raises(WdiracError):
         tune_set("nosuchkey", 1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_column_sweep_two_row_links(prec, restore_tuning):
+    dims = (6, 4, 3, 4)
+    U, psi = fields(dims, 41, nrhs=3)
+    op = DiracOp(dims, U, -0.25, 1.0, antiperiodic_t=True, compress_links=True)
+    tune_set("order", 3)
+    tune_set("tchunk", 4)
+    got = op.apply(to_dev(psi), prec).cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, -0.25, 1.0, antiperiodic_t=True)
+    for r in range(3):
+        assert rel_l2(got[r], want[r]) < TOL[prec]

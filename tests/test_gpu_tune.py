@@ -1,0 +1,68 @@
+"""The autotuner: its choices are valid configurations, launches that use them
+still match the oracle, the cache file records them, and the full-size
+lattice in the benchmark's configuration (two-row links, autotuned launch)
+agrees with the oracle at sampled sites."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2407_00041_amd import DiracOp, _lib, synth, tune_get, tune_set
+from util import TOL, fields, need_gpu, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def clean_table():
+    need_gpu()
+    explicit = tune_get("explicit")
+    tune_set("explicit", 0)
+    yield
+    _lib.load().dirac_tune_clear()
+    tune_set("explicit", explicit)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_autotuned_launch_matches_oracle(prec, nrhs, clean_table, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("WDIRAC_TUNE_CACHE", str(cache))
+    dims = (6, 4, 6, 4)
+    U, psi = fields(dims, 12, nrhs=nrhs)
+    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_links=True)
+    cfg = op.autotune(prec, nrhs)
+    assert cfg["order"] in (2, 3) and cfg["block"] in (128, 256) and cfg["nr"] in (1, 2, 4)
+    assert cfg["us"] > 0
+    got = op.apply(to_dev(psi), prec).cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, -0.3, 1.0, antiperiodic_t=True)
+    for r in range(nrhs):
+        assert rel_l2(got[r], want[r]) < TOL[prec]
+    lines = [json.loads(x) for x in cache.read_text().splitlines()]
+    assert lines[-1]["order"] == cfg["order"] and lines[-1]["nr"] == cfg["nr"]
+    assert lines[-1]["key"].startswith("gfx950|6x4x6x4|")
+
+
+def test_full_size_bench_configuration(clean_table):
+    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links, autotuned FP64 and
+    FP32 launches (as bench.py times them): 1500 sampled sites vs the oracle."""
+    dims = (96, 48, 48, 48)
+    V = synth.volume(dims)
+    m0, csw = -0.35, 1.0
+    Ud = synth.smooth_links(dims, 1003, device="cuda")
+    psid = synth.gaussian_spinor(dims, 2000, nrhs=1, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    psi = psid.cpu().numpy()[0]
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32", "f16s"), compress_links=True)
+    sites = synth.random_sites(dims, 1500, 9)
+    want = oracle.dirac_apply_sites(dims, U, psi, sites, m0, csw)
+    st = torch.from_numpy(sites).cuda()
+    for prec in ("f64", "f32", "f16s"):
+        op.autotune(prec, 1)
+        got = op.apply(psid, prec).reshape(V, 12)[st].cpu().numpy()
+        assert rel_l2(got, want) < TOL[prec], prec
+    del op
+    torch.cuda.empty_cache()
