@@ -49,6 +49,7 @@ KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/
 TRAFFIC_PROFILE = "profiles/dslash_f64_48x96_hbm_traffic.md"
 # mixed solver: FP64 outer FGMRES, inner GMRES on the reduced-precision operator
 MIXED = {"mode": "mixed_f16s", "restart": 16, "inner_restart": 10, "inner_tol": 0.1}
+TUNE_FIXED = False
 
 
 def parse():
@@ -64,6 +65,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip every measurement after the main one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fixed-launch", type=int, nargs=4, metavar=("ORDER", "BLOCK", "TCHUNK", "NR"),
+                    help="use this launch configuration for every stencil launch instead of autotuning "
+                         "(reproducible profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (counter calibration)")
     return ap.parse_args()
@@ -123,7 +127,7 @@ def batched_run(torch, op, dims, stream, steps):
         outs.append(o)
         batches.append((o, nat[r0 * rb:(r0 + s) * rb], s))
         r0 += s
-    tuned = op.autotune("f32", n)
+    tuned = {"fixed": True} if TUNE_FIXED else op.autotune("f32", n)
     ms = time_launches(torch, lambda: op.apply_batched(batches, "f32", stream=stream), steps, 3, stream)
     res = {"batches": sizes, "prec": "f32", "ms_per_launch": ms, "rhs_applies_per_s": n * 1000.0 / ms,
            "alg_GBps": (LINK_BYTES["f32"] + 288 + 192 * n) * op.V / (ms * 1e-3) / 1e9, "launch": tuned}
@@ -152,8 +156,9 @@ def fgmres_run(torch, op, dims, nrhs_total):
     work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
     inner = "f16s" if pmx["mode"].endswith("f16s") else "f32"
     for n in sorted({1, wave, nrhs_total % wave or wave}):     # the solvers' batched applies
-        op.autotune("f64", n)
-        op.autotune(inner, n)
+        if not TUNE_FIXED:
+            op.autotune("f64", n)
+            op.autotune(inner, n)
     t64 = tmx = 0.0
     a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
     for w0 in range(0, nrhs_total, wave):
@@ -227,7 +232,9 @@ def _cpu_model():
 
 
 def main():
+    global TUNE_FIXED
     a = parse()
+    TUNE_FIXED = bool(a.fixed_launch)
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU halo exchange "
                                    "is not part of this build"}))
@@ -254,8 +261,14 @@ def main():
     out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}
     torch.cuda.synchronize()
 
-    tuned = {p: op.autotune(p, 1) for p in ("f64", "f32", "f16s")}
-    log(f"[bench] autotuned launches: {tuned}")
+    if a.fixed_launch:
+        o, blk, tch, nr = a.fixed_launch
+        for k, v in (("order", o), ("block", blk), ("tchunk", tch), ("nr_f64", nr), ("nr_f32", nr), ("nr_f16s", nr)):
+            wd.tune_set(k, v)
+        tuned = {p: {"order": o, "block": blk, "tchunk": tch, "nr": nr, "fixed": True} for p in ("f64", "f32", "f16s")}
+    else:
+        tuned = {p: op.autotune(p, 1) for p in ("f64", "f32", "f16s")}
+    log(f"[bench] launches: {tuned}")
     log(f"[bench] timing FP64 apply: {a.warmup} warmup + {a.steps} steps")
     ms = time_launches(torch, lambda: op.apply_native(out["f64"], inp["f64"], 1, "f64", stream=stream),
                        a.steps, a.warmup, stream)
