@@ -18,9 +18,16 @@ struct VecList {
 struct CoefList {
     double2 c[kGS];
 };
+struct MultList {
+    double m[kGS];
+};
+
+// out[i] = sum over groups of partial[g][i], i < gridDim.x; stride = columns per partial row
+__global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
+                                                        double2 *__restrict__ out);
 
 // out[i] = <v_i, w> = v_i^H w for i < nv, out[nv].x = |w|^2; partial needs
-// kRedBlocks * (kGS + 1) entries.  S = double2 (FP64) or float2 (FP32 storage).
+// kRedBlocks * (kGS + 1) entries.  S = double2 (FP64 storage).
 template <typename S>
 hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
                 hipStream_t st);
@@ -29,7 +36,7 @@ template <typename S>
 hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, void *w, long long N, double2 *partial,
                       double2 *norm_out, hipStream_t st);
 // out = in * s * mult, s = sc[0].x or 1/sqrt(sc[0].x) (1 for null sc);
-// SI == SO only (flat element order)
+// SI == SO == double2 (flat element order)
 template <typename SI, typename SO>
 hipError_t scale(const void *in, void *out, const double2 *sc, bool inv_sqrt, double mult, long long N,
                  hipStream_t st);
@@ -39,18 +46,21 @@ hipError_t residual(const double2 *b, const double2 *w, double2 *r, long long N,
 // x += sum_i coef[i] z_i (same precision: S = double2); coef is HOST memory
 template <typename S>
 hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x, long long N, hipStream_t st);
-hipError_t norm2(const void *w, bool f32, long long N, double2 *partial, double2 *out, hipStream_t st);
 
-// Same-precision flat operations above; the two cross-precision ones below
-// follow the native layouts (component order differs between FP64 and FP32).
-// dst (native FP32) = src (native FP64) * mult
-hipError_t f64_to_f32(const void *src, void *dst, double mult, int V, hipStream_t st);
-// x (native FP64) = sum_i coef[i] z_i, z_i native FP32 (x overwritten); coef HOST
-hipError_t combine_f32_into_f64(const void *const *z, int nz, const double2 *coef, double2 *x, int V,
-                                hipStream_t st);
-
-// native FP32 field <-> native FP16S field (per-site scale), nrhs = 1
-hipError_t f32_to_f16s(void *dst, const void *src, int V, hipStream_t st);
-hipError_t f16s_to_f32(void *dst, const void *src, int V, hipStream_t st);
+// Per-site operations on native fields of precision prec (WDIRAC_F64, _F32 or
+// _F16S), nrhs = 1, FP64 accumulation; results re-encoded in the field's
+// precision.  partial needs kRedBlocks * (kGS + 1) entries.
+// out[i] = v_i^H w (i < nv), out[nv].x = |w|^2
+hipError_t site_mdot(int prec, const void *const *v, int nv, const void *w, int V, double2 *partial, double2 *out,
+                     hipStream_t st);
+// w -= sum_i mult[i] coef[i] v_i (coef on the device, mult HOST memory or null
+// for all ones); norm_out[0].x = |w_new|^2 (before re-encoding) when non-null
+hipError_t site_axpy(int prec, const void *const *v, int nv, const double2 *coef, const double *mult, void *w, int V,
+                     double2 *partial, double2 *norm_out, hipStream_t st);
+// out (precision pout) = in (precision pin) * mult; pin == pout or pin = F64
+hipError_t site_scale(int pin, int pout, const void *in, void *out, double mult, int V, hipStream_t st);
+// x (native FP64) = sum_i coef[i] z_i, z_i of precision prec (x overwritten); coef HOST
+hipError_t site_combine(int prec, const void *const *z, int nz, const double2 *coef, double2 *x, int V,
+                        hipStream_t st);
 
 }  // namespace wd

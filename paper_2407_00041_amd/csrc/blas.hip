@@ -1,11 +1,11 @@
-// Vector kernels of the Krylov solvers (the non-operator work of Algorithm 2:
-// inner products, norms, orthogonalisation updates, scaling, the solution
-// update and precision conversion).
+// Vector kernels of the outer FP64 Krylov solver (the non-operator work of
+// Algorithm 2: inner products, norms, orthogonalisation updates, scaling and
+// the solution update).
 //
-// A field is treated as a flat array of N = 12 V complex numbers (the native
-// FP64 and FP32 layouts are dense arrays of complex128 / complex64, so the
-// order does not matter for these operations).  Storage is complex128
-// (double2) or complex64 (float2); every sum is accumulated in FP64.
+// A field is treated as a flat array of N = 12 V complex128 numbers (the
+// native FP64 layout is a dense array, so the order does not matter for these
+// operations); every sum is accumulated in FP64.  The low-precision inner
+// solver uses the per-site kernels of blas_site.hip instead.
 //
 // Reductions are deterministic: a fixed grid of kRedBlocks work-groups, each
 // thread summing a fixed strided subset, a fixed LDS tree per work-group,
@@ -19,15 +19,6 @@ template <typename S> struct Elem;
 template <> struct Elem<double2> {
     static __device__ __forceinline__ double2 ld(const double2 *p, long long i) { return p[i]; }
     static __device__ __forceinline__ void st(double2 *p, long long i, double2 v) { p[i] = v; }
-};
-template <> struct Elem<float2> {
-    static __device__ __forceinline__ double2 ld(const float2 *p, long long i) {
-        float2 a = p[i];
-        return make_double2(a.x, a.y);
-    }
-    static __device__ __forceinline__ void st(float2 *p, long long i, double2 v) {
-        p[i] = make_float2((float)v.x, (float)v.y);
-    }
 };
 
 __device__ __forceinline__ double2 cj_mul(double2 a, double2 b) {  // conj(a) b
@@ -182,74 +173,8 @@ __global__ __launch_bounds__(kRedThreads) void k_update(VecList vl, CoefList cl,
     }
 }
 
-// Cross-precision operations must respect the two native layouts: FP64 is
-// [12][V] complex128, FP32 is [6][V] x (2 complex64), so component k of site
-// s sits at complex index k V + s in one and 2 ((k/2) V + s) + k%2 in the
-// other.  One thread per site.
-
-// dst (FP32 native) = src (FP64 native) * mult
-__global__ __launch_bounds__(kRedThreads) void k_f64_to_f32(const double2 *__restrict__ src, float4 *__restrict__ dst,
-                                                             double mult, int V) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-#pragma unroll
-    for (int kp = 0; kp < 6; kp++) {
-        const double2 a = src[(size_t)(2 * kp) * V + s], b = src[(size_t)(2 * kp + 1) * V + s];
-        dst[(size_t)kp * V + s] = make_float4((float)(a.x * mult), (float)(a.y * mult), (float)(b.x * mult),
-                                              (float)(b.y * mult));
-    }
-}
-
-// x (FP64 native) = keep * x + sum_i c_i z_i (z_i FP32 native); keep = 0 or 1
-__global__ __launch_bounds__(kRedThreads) void k_update_f32_to_f64(VecList vl, CoefList cl, double2 *__restrict__ x,
-                                                                    int keep, int V) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    const double2 *c = cl.c;
-#pragma unroll
-    for (int kp = 0; kp < 6; kp++) {
-        double2 a = keep ? x[(size_t)(2 * kp) * V + s] : make_double2(0, 0);
-        double2 b = keep ? x[(size_t)(2 * kp + 1) * V + s] : make_double2(0, 0);
-#pragma unroll
-        for (int i = 0; i < kGS; i++) {
-            if (i < vl.n) {
-                const float4 z = static_cast<const float4 *>(vl.v[i])[(size_t)kp * V + s];
-                a.x += c[i].x * z.x - c[i].y * z.y;
-                a.y += c[i].x * z.y + c[i].y * z.x;
-                b.x += c[i].x * z.z - c[i].y * z.w;
-                b.y += c[i].x * z.w + c[i].y * z.z;
-            }
-        }
-        x[(size_t)(2 * kp) * V + s] = a;
-        x[(size_t)(2 * kp + 1) * V + s] = b;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // launchers
-
-hipError_t f64_to_f32(const void *src, void *dst, double mult, int V, hipStream_t st) {
-    hipLaunchKernelGGL(k_f64_to_f32, dim3((V + kRedThreads - 1) / kRedThreads), dim3(kRedThreads), 0, st,
-                       static_cast<const double2 *>(src), static_cast<float4 *>(dst), mult, V);
-    return hipGetLastError();
-}
-
-hipError_t combine_f32_into_f64(const void *const *z, int nz, const double2 *coef, double2 *x, int V, hipStream_t st) {
-    for (int i0 = 0; i0 < nz || i0 == 0; i0 += kGS) {
-        VecList vl;
-        CoefList cl;
-        vl.n = nz - i0 < kGS ? nz - i0 : kGS;
-        if (vl.n < 0) vl.n = 0;
-        for (int i = 0; i < kGS; i++) {
-            vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
-            cl.c[i] = i < vl.n ? coef[i0 + i] : make_double2(0, 0);
-        }
-        hipLaunchKernelGGL(k_update_f32_to_f64, dim3((V + kRedThreads - 1) / kRedThreads), dim3(kRedThreads), 0, st,
-                           vl, cl, x, i0 > 0 ? 1 : 0, V);
-        if (i0 + kGS >= nz) break;
-    }
-    return hipGetLastError();
-}
 
 static int red_grid(long long N) {
     long long g = (N + kRedThreads - 1) / kRedThreads;
@@ -325,20 +250,11 @@ hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x,
     return hipGetLastError();
 }
 
-hipError_t norm2(const void *w, bool f32, long long N, double2 *partial, double2 *out, hipStream_t st) {
-    return f32 ? mdot<float2>(nullptr, 0, w, N, partial, out, st) : mdot<double2>(nullptr, 0, w, N, partial, out, st);
-}
-
 template hipError_t mdot<double2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
-template hipError_t mdot<float2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
 template hipError_t axpy_multi<double2>(const void *const *, int, const double2 *, void *, long long, double2 *,
                                         double2 *, hipStream_t);
-template hipError_t axpy_multi<float2>(const void *const *, int, const double2 *, void *, long long, double2 *,
-                                       double2 *, hipStream_t);
 template hipError_t scale<double2, double2>(const void *, void *, const double2 *, bool, double, long long,
                                             hipStream_t);
-template hipError_t scale<float2, float2>(const void *, void *, const double2 *, bool, double, long long,
-                                          hipStream_t);
 template hipError_t update<double2>(const void *const *, int, const double2 *, double2 *, long long, hipStream_t);
 
 }  // namespace wd

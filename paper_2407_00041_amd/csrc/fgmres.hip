@@ -22,8 +22,15 @@
 //
 // Preconditioner M_j^{-1}: the identity (FGMRES_F64), or for the mixed
 // modes an inner GMRES solve of D z = v_j with the FP32 or FP16S operator,
-// an FP32 basis and FP64-accumulated inner products, stopped at the relative
-// residual inner_tol or after inner_maxit applications.  The outer residual,
+// stopped at the relative residual inner_tol or after inner_maxit
+// applications.  The inner Krylov basis is stored in the inner operator's own
+// native layout (FP32, or FP16 with per-site scales) and all its inner
+// products accumulate in FP64.  Inner basis vectors are normalised lazily:
+// the operator writes D W_k straight into the next basis slot, which is
+// orthogonalised in place and kept unnormalised; the host tracks the stored
+// norms c_k (W_k = c_k v_k) and folds them into the Hessenberg entries, the
+// update coefficients and the final combination, so no separate scaling or
+// conversion pass runs per inner step.  The outer residual,
 // orthogonalisation and update stay FP64, so the outer loop is an iterative
 // refinement of the low-precision solves.
 //
@@ -71,9 +78,8 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kGS + 1) + 3 * (size_t)kmax + 8));
     L.per_rhs = (size_t)(m + 2) * L.f64 + L.scal;  // V[0..m], w
     if (p->mode != FGMRES_F64) {
-        L.per_rhs += (size_t)m * L.f64;              // Z[0..m)
-        L.per_rhs += (size_t)(mi + 2) * L.f32;       // inner V[0..mi], inner w
-        if (p->mode == FGMRES_MIXED_F16S) L.per_rhs += 2 * L.f16;
+        L.per_rhs += (size_t)m * L.f64;                                          // Z[0..m)
+        L.per_rhs += (size_t)(mi + 1) * (p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16);  // inner W[0..mi]
     }
     return L;
 }
@@ -143,8 +149,8 @@ struct Rhs {
     const double2 *b = nullptr;
     std::vector<void *> V, Z;  // outer basis (F64), preconditioned vectors (F64)
     double2 *w = nullptr;
-    std::vector<void *> Vi;    // inner basis (F32)
-    void *wi = nullptr, *h16a = nullptr, *h16b = nullptr;
+    std::vector<void *> Vi;    // inner basis, inner operator precision, unnormalised
+    std::vector<double> ic;    // stored norms of the inner basis vectors (host)
     double2 *partial = nullptr, *hcol = nullptr, *coef = nullptr, *hcol2 = nullptr, *nrm = nullptr;
     // host
     Phase phase = Phase::Residual;
@@ -211,30 +217,27 @@ int inner_solve(const Ctx &c, std::vector<Rhs *> &list) {
     const int mi = p.inner_restart;
     const int maxit = p.inner_maxit < mi ? p.inner_maxit : mi;
     for (Rhs *r : list) {
-        const int j = r->outer.j;
-        WD_TRY(f64_to_f32(r->V[j], r->Vi[0], 1.0, c.V, c.st));
+        WD_TRY(site_scale(WDIRAC_F64, prec, r->V[r->outer.j], r->Vi[0], 1.0, c.V, c.st));
         r->inner.reset(mi, 1.0);
+        r->ic.assign(1, 1.0);
         r->inner_done = false;
     }
     std::vector<Rhs *> act = list;
+    std::vector<double> mult;
     while (!act.empty()) {
+        // W_{k+1} = D W_k for every active right-hand side, one batched launch
         std::vector<dirac_batch> b;
-        for (Rhs *r : act) {
-            const int ji = r->inner.j;
-            if (prec == WDIRAC_F16S) {
-                WD_TRY(f32_to_f16s(r->h16a, r->Vi[ji], c.V, c.st));
-                b.push_back({r->h16b, r->h16a, 1});
-            } else {
-                b.push_back({r->wi, r->Vi[ji], 1});
-            }
-        }
+        for (Rhs *r : act) b.push_back({r->Vi[r->inner.j + 1], r->Vi[r->inner.j], 1});
         WD_TRY(apply_many(c, prec, b));
         for (Rhs *r : act) {
-            const int ji = r->inner.j;
-            if (prec == WDIRAC_F16S) WD_TRY(f16s_to_f32(r->wi, r->h16b, c.V, c.st));
+            const int k = r->inner.j;
             r->inner_applies++;
-            WD_TRY(mdot<float2>(r->Vi.data(), ji + 1, r->wi, c.N, r->partial, r->hcol, c.st));
-            WD_TRY(axpy_multi<float2>(r->Vi.data(), ji + 1, r->hcol, r->wi, c.N, r->partial, r->hcol + ji + 1, c.st));
+            // dots d_i = W_i^H W_{k+1} = c_i c_k h_ik; then W_{k+1} -= sum_i d_i / c_i^2 W_i
+            WD_TRY(site_mdot(prec, r->Vi.data(), k + 1, r->Vi[k + 1], c.V, r->partial, r->hcol, c.st));
+            mult.resize(k + 1);
+            for (int i = 0; i <= k; i++) mult[i] = 1.0 / (r->ic[i] * r->ic[i]);
+            WD_TRY(site_axpy(prec, r->Vi.data(), k + 1, r->hcol, mult.data(), r->Vi[k + 1], c.V, r->partial,
+                             r->hcol + k + 1, c.st));
         }
         std::vector<std::pair<const double2 *, int>> src;
         for (Rhs *r : act) src.emplace_back(r->hcol, r->inner.j + 2);
@@ -242,29 +245,38 @@ int inner_solve(const Ctx &c, std::vector<Rhs *> &list) {
         int rc = fetch(c, src, h);
         if (rc) return rc;
         std::vector<Rhs *> next;
-        for (size_t k = 0; k < act.size(); k++) {
-            Rhs *r = act[k];
-            const int ji = r->inner.j;
-            std::vector<zc> col(ji + 2);
-            for (int i = 0; i <= ji; i++) col[i] = h[k][i];
-            const double hn = std::sqrt(std::max(h[k][ji + 1].real(), 0.0));
-            col[ji + 1] = hn;
+        for (size_t q = 0; q < act.size(); q++) {
+            Rhs *r = act[q];
+            const int k = r->inner.j;
+            const double ck = r->ic[k];
+            std::vector<zc> col(k + 2);
+            for (int i = 0; i <= k; i++) col[i] = h[q][i] / (r->ic[i] * ck);
+            const double nrm = std::sqrt(std::max(h[q][k + 1].real(), 0.0));  // |W_{k+1}| = c_k h_{k+1,k}
+            const double hn = nrm / ck;
+            col[k + 1] = hn;
             const double est = r->inner.add_column(col.data());
             const bool stop = est < p.inner_tol || r->inner.j >= maxit || hn == 0.0;
-            if (!stop) {
-                WD_TRY((scale<float2, float2>(r->wi, r->Vi[r->inner.j], nullptr, false, 1.0 / hn, c.N, c.st)));
-                next.push_back(r);
-            } else {
+            if (stop) {
                 r->inner_done = true;
+                continue;
             }
+            if (nrm > 1e-20 && nrm < 1e20) {
+                r->ic.push_back(nrm);
+            } else {  // keep stored magnitudes well inside the FP32 range
+                WD_TRY(site_scale(prec, prec, r->Vi[k + 1], r->Vi[k + 1], 1.0 / nrm, c.V, c.st));
+                r->ic.push_back(1.0);
+            }
+            next.push_back(r);
         }
         act.swap(next);
     }
-    // z_j = sum_i y_i Vi[i] in FP64
+    // z_j = sum_i y_i v_i = sum_i (y_i / c_i) W_i, accumulated in FP64
     for (Rhs *r : list) {
-        const int j = r->outer.j;
-        const std::vector<double2> y = to_d2(r->inner.solve());
-        WD_TRY(combine_f32_into_f64(r->Vi.data(), (int)y.size(), y.data(), static_cast<double2 *>(r->Z[j]), c.V, c.st));
+        std::vector<zc> y = r->inner.solve();
+        for (size_t i = 0; i < y.size(); i++) y[i] /= r->ic[i];
+        const std::vector<double2> yd = to_d2(y);
+        WD_TRY(site_combine(prec, r->Vi.data(), (int)yd.size(), yd.data(), static_cast<double2 *>(r->Z[r->outer.j]),
+                            c.V, c.st));
     }
     return WDIRAC_OK;
 }
@@ -309,12 +321,8 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         r.w = reinterpret_cast<double2 *>(take(L.f64));
         if (mixed) {
             for (int i = 0; i < m; i++) r.Z.push_back(take(L.f64));
-            for (int i = 0; i <= p->inner_restart; i++) r.Vi.push_back(take(L.f32));
-            r.wi = take(L.f32);
-            if (p->mode == FGMRES_MIXED_F16S) {
-                r.h16a = take(L.f16);
-                r.h16b = take(L.f16);
-            }
+            const size_t fi = p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;
+            for (int i = 0; i <= p->inner_restart; i++) r.Vi.push_back(take(fi));
         } else {
             r.Z = std::vector<void *>(r.V.begin(), r.V.begin() + m);  // M = I: z_j = v_j
         }

@@ -277,59 +277,3 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
 }
 
 }  // namespace wd
-
-namespace wd {
-
-// native FP32 [6][V] float4 -> native FP16S (same encoding as pack_kernel)
-__global__ __launch_bounds__(256) void k_f32_to_f16s(char *__restrict__ dst, const float4 *__restrict__ src, int V) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    float v[24];
-    float m = 0.f;
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        float4 a = src[(size_t)k * V + s];
-        v[4 * k] = a.x; v[4 * k + 1] = a.y; v[4 * k + 2] = a.z; v[4 * k + 3] = a.w;
-    }
-#pragma unroll
-    for (int k = 0; k < 24; k++) m = fmaxf(m, fabsf(v[k]));
-    half8 *o = reinterpret_cast<half8 *>(dst);
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        half8 q;
-#pragma unroll
-        for (int j = 0; j < 8; j++) q[j] = m > 0.f ? (_Float16)(v[8 * k + j] / m) : (_Float16)0.f;
-        o[(size_t)k * V + s] = q;
-    }
-    reinterpret_cast<float *>(dst + (size_t)48 * V)[s] = m;
-}
-
-__global__ __launch_bounds__(256) void k_f16s_to_f32(float4 *__restrict__ dst, const char *__restrict__ src, int V) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    const half8 *i = reinterpret_cast<const half8 *>(src);
-    const float m = reinterpret_cast<const float *>(src + (size_t)48 * V)[s];
-    float v[24];
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        half8 q = i[(size_t)k * V + s];
-#pragma unroll
-        for (int j = 0; j < 8; j++) v[8 * k + j] = m * (float)q[j];
-    }
-#pragma unroll
-    for (int k = 0; k < 6; k++) dst[(size_t)k * V + s] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-}
-
-hipError_t f32_to_f16s(void *dst, const void *src, int V, hipStream_t st) {
-    hipLaunchKernelGGL(k_f32_to_f16s, dim3((V + 255) / 256), dim3(256), 0, st, static_cast<char *>(dst),
-                       static_cast<const float4 *>(src), V);
-    return hipGetLastError();
-}
-
-hipError_t f16s_to_f32(void *dst, const void *src, int V, hipStream_t st) {
-    hipLaunchKernelGGL(k_f16s_to_f32, dim3((V + 255) / 256), dim3(256), 0, st, static_cast<float4 *>(dst),
-                       static_cast<const char *>(src), V);
-    return hipGetLastError();
-}
-
-}  // namespace wd
