@@ -159,8 +159,9 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * knobs).  Keys: "block" (threads per work-group: 64, 128, 192, 256),
  * "order" (0 linear, 1 one contiguous 1/8 of the lattice per XCD, 2 every
  * XCD takes 1/8 of each T-slice and the slices are swept in order, 3 lanes
- * walk columns along T carrying the T neighbours in registers), "tchunk"
- * (order 3: sites per lane along T, >= 1),
+ * walk columns along T carrying the T neighbours in registers, 4 as 3 with
+ * each work-group's columns forming a 16 (X) x 4 (Y) x block/64 (Z) patch),
+ * "tchunk" (orders 3 and 4: sites per lane along T, >= 1),
  * "persistent_blocks" (cap on the work-groups of a dirac_apply_batched launch;
  * 0, the default, means all work-groups that fit on the device at once),
  * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
@@ -225,6 +226,10 @@ typedef struct {
     int inner_restart;  /* inner GMRES dimension (mixed modes)               */
     double inner_tol;   /* inner relative residual target (mixed modes)      */
     int inner_maxit;    /* inner operator applications per outer step        */
+    int graph;          /* mixed modes: 1 = run each inner cycle as a HIP     */
+                        /* graph, captured once per set of right-hand sides  */
+                        /* and replayed (no host step per inner iteration);  */
+                        /* 0 = issue it step by step                         */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096
@@ -253,8 +258,8 @@ size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nr
  *          entry (x0) and the solution on return.
  *   st   : host array of nrhs stats records (may be NULL).
  *   work : device workspace of at least fgmres_workspace_bytes(op, p, nrhs).
- * Blocks until done (one host synchronisation per Arnoldi step to read the
- * residual estimates).  Returns WDIRAC_ENOTCONV (> 0) when some right-hand
+ * Blocks until done (one host synchronisation per outer Arnoldi step to read
+ * the residual estimates, plus one per inner step unless p->graph is set).  Returns WDIRAC_ENOTCONV (> 0) when some right-hand
  * side reached maxit (x still holds its last iterate); errors: EINVAL,
  * EUNSUPPORTED (mixed-mode precision not materialised), EHIP.
  */

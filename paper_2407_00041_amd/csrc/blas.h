@@ -18,9 +18,6 @@ struct VecList {
 struct CoefList {
     double2 c[kGS];
 };
-struct MultList {
-    double m[kGS];
-};
 
 // out[i] = sum over groups of partial[g][i], i < gridDim.x; stride = columns per partial row
 __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
@@ -49,18 +46,22 @@ hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x,
 
 // Per-site operations on native fields of precision prec (WDIRAC_F64, _F32 or
 // _F16S), nrhs = 1, FP64 accumulation; results re-encoded in the field's
-// precision.  partial needs kRedBlocks * (kGS + 1) entries.
+// precision.  partial needs kRedBlocks * (kGS + 1) entries.  hdr (nullable) is
+// the device header of an inner cycle: hdr[0] = (completed steps, active
+// flag), hdr[1].x = normalisation factor; with hdr[0].y == 0 the kernels of
+// mdot and axpy do nothing.
 // out[i] = v_i^H w (i < nv), out[nv].x = |w|^2
 hipError_t site_mdot(int prec, const void *const *v, int nv, const void *w, int V, double2 *partial, double2 *out,
-                     hipStream_t st);
-// w -= sum_i mult[i] coef[i] v_i (coef on the device, mult HOST memory or null
-// for all ones); norm_out[0].x = |w_new|^2 (before re-encoding) when non-null
-hipError_t site_axpy(int prec, const void *const *v, int nv, const double2 *coef, const double *mult, void *w, int V,
-                     double2 *partial, double2 *norm_out, hipStream_t st);
+                     const double2 *hdr, hipStream_t st);
+// w = f (w - sum_i coef[i] v_i), coef on the device, f = hdr[1].x (1 without
+// hdr); norm_out[0].x = |w_new|^2 (before re-encoding) when non-null
+hipError_t site_axpy(int prec, const void *const *v, int nv, const double2 *coef, void *w, int V, double2 *partial,
+                     double2 *norm_out, const double2 *hdr, hipStream_t st);
 // out (precision pout) = in (precision pin) * mult; pin == pout or pin = F64
 hipError_t site_scale(int pin, int pout, const void *in, void *out, double mult, int V, hipStream_t st);
-// x (native FP64) = sum_i coef[i] z_i, z_i of precision prec (x overwritten); coef HOST
-hipError_t site_combine(int prec, const void *const *z, int nz, const double2 *coef, double2 *x, int V,
-                        hipStream_t st);
+// x (native FP64) = sum_{i < n} coef[i] z_i with n = hdr[0].x <= nmax, z_i of
+// precision prec, coef on the device (x overwritten; n = 0 gives x = 0)
+hipError_t site_combine(int prec, const void *const *z, int nmax, const double2 *coef, const double2 *hdr, double2 *x,
+                        int V, hipStream_t st);
 
 }  // namespace wd

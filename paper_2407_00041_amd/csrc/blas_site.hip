@@ -6,6 +6,12 @@
 // mixed solver keeps its Krylov basis in the low-precision operator's layout,
 // so the operator reads and writes basis vectors directly.
 //
+// The kernels can follow a device-side state header hdr of the inner cycle
+// (hdr[0] = (completed steps, active flag), hdr[1].x = normalisation factor):
+// they return at once for a right-hand side whose cycle has ended, and take
+// their coefficients from device memory, so a whole cycle can be issued
+// without host decisions (and captured as a graph).
+//
 // Reductions are deterministic: a fixed grid of kRedBlocks work-groups, each
 // thread summing a fixed strided subset of sites, a fixed LDS tree per
 // work-group, then k_colsum adding the per-group partials in order.
@@ -59,7 +65,8 @@ __device__ __forceinline__ void reduce_block(double2 (&v)[NV], double2 *lds) {
 // partial[blk][i] = sum over the group's sites of v_i^H w (i < n), [kGS] = |w|^2
 template <int P>
 __global__ __launch_bounds__(kRedThreads) void k_site_mdot(VecList vl, const void *__restrict__ w,
-                                                            double2 *__restrict__ partial, int V) {
+                                                            double2 *__restrict__ partial, const double2 *hdr, int V) {
+    if (hdr && hdr[0].y == 0.0) return;
     __shared__ double2 lds[(kGS + 1) * kRedThreads];
     double2 acc[kGS + 1];
 #pragma unroll
@@ -89,19 +96,20 @@ __global__ __launch_bounds__(kRedThreads) void k_site_mdot(VecList vl, const voi
     }
 }
 
-// w -= sum_i ml.m[i] coef[i] v_i (coef on the device, real multipliers by
-// value); partial[blk] = |w_new|^2 when partial != null
+// w = f (w - sum_i coef[i] v_i), coefficients on the device; f = hdr[1].x when
+// apply_f (last pass) and hdr are set, else 1.  partial[blk] = |w_new|^2 of the
+// re-encoded values' source (before rounding) when partial != null.
 template <int P>
-__global__ __launch_bounds__(kRedThreads) void k_site_axpy(VecList vl, MultList ml, const double2 *__restrict__ coef,
-                                                            void *__restrict__ w, double2 *__restrict__ partial, int V) {
+__global__ __launch_bounds__(kRedThreads) void k_site_axpy(VecList vl, const double2 *__restrict__ coef,
+                                                            void *__restrict__ w, double2 *__restrict__ partial,
+                                                            const double2 *hdr, int apply_f, int V) {
+    if (hdr && hdr[0].y == 0.0) return;
     __shared__ double2 lds[kRedThreads];
+    const double f = (hdr && apply_f) ? hdr[1].x : 1.0;
     double2 nrm[1] = {make_double2(0, 0)};
     double2 c[kGS];
 #pragma unroll
-    for (int i = 0; i < kGS; i++) {
-        const double2 a = i < vl.n ? coef[i] : make_double2(0, 0);
-        c[i] = make_double2(a.x * ml.m[i], a.y * ml.m[i]);
-    }
+    for (int i = 0; i < kGS; i++) c[i] = i < vl.n ? coef[i] : make_double2(0, 0);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < V; s += gridDim.x * blockDim.x) {
         double2 wv[12];
         SiteIO<P>::load(w, V, s, wv);
@@ -117,6 +125,8 @@ __global__ __launch_bounds__(kRedThreads) void k_site_axpy(VecList vl, MultList 
                 }
             }
         }
+#pragma unroll
+        for (int k = 0; k < 12; k++) wv[k] = make_double2(wv[k].x * f, wv[k].y * f);
         SiteIO<P>::store(w, V, s, wv);
 #pragma unroll
         for (int k = 0; k < 12; k++) nrm[0].x += wv[k].x * wv[k].x + wv[k].y * wv[k].y;
@@ -140,13 +150,21 @@ __global__ __launch_bounds__(kRedThreads) void k_site_scale(const void *__restri
     }
 }
 
-// x (native FP64) = keep * x + sum_i c_i z_i, z_i of precision P (coefficients by value)
+// x (native FP64) = keep * x + sum_{i < n} coef[i] z_i, z_i of precision P,
+// n = min(kGS, count - i0) with count = hdr[0].x (device coefficients)
 template <int P>
-__global__ __launch_bounds__(kRedThreads) void k_site_combine(VecList vl, CoefList cl, double2 *__restrict__ x,
-                                                               int keep, int V) {
+__global__ __launch_bounds__(kRedThreads) void k_site_combine(VecList vl, const double2 *__restrict__ coef,
+                                                               const double2 *hdr, int i0, double2 *__restrict__ x,
+                                                               int V) {
+    const int count = (int)hdr[0].x;
+    const int n = count - i0 < kGS ? count - i0 : kGS;
+    if (i0 > 0 && n <= 0) return;
+    double2 c[kGS];
+#pragma unroll
+    for (int i = 0; i < kGS; i++) c[i] = i < n ? coef[i] : make_double2(0, 0);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < V; s += gridDim.x * blockDim.x) {
         double2 xv[12];
-        if (keep) {
+        if (i0 > 0) {
             SiteIO<WDIRAC_F64>::load(x, V, s, xv);
         } else {
 #pragma unroll
@@ -154,14 +172,13 @@ __global__ __launch_bounds__(kRedThreads) void k_site_combine(VecList vl, CoefLi
         }
 #pragma unroll
         for (int i = 0; i < kGS; i++) {
-            if (i < vl.n) {
+            if (i < n) {
                 double2 zv[12];
                 SiteIO<P>::load(vl.v[i], V, s, zv);
-                const double2 c = cl.c[i];
 #pragma unroll
                 for (int k = 0; k < 12; k++) {
-                    xv[k].x += c.x * zv[k].x - c.y * zv[k].y;
-                    xv[k].y += c.x * zv[k].y + c.y * zv[k].x;
+                    xv[k].x += c[i].x * zv[k].x - c[i].y * zv[k].y;
+                    xv[k].y += c[i].x * zv[k].y + c[i].y * zv[k].x;
                 }
             }
         }
@@ -178,14 +195,14 @@ static int site_grid(int V) {
 
 template <int P>
 static hipError_t site_mdot_p(const void *const *v, int nv, const void *w, int V, double2 *partial, double2 *out,
-                              hipStream_t st) {
+                              const double2 *hdr, hipStream_t st) {
     const int G = site_grid(V);
     for (int i0 = 0;; i0 += kGS) {
         VecList vl;
         vl.n = nv - i0 < kGS ? nv - i0 : kGS;
         if (vl.n < 0) vl.n = 0;
         for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
-        hipLaunchKernelGGL(k_site_mdot<P>, dim3(G), dim3(kRedThreads), 0, st, vl, w, partial, V);
+        hipLaunchKernelGGL(k_site_mdot<P>, dim3(G), dim3(kRedThreads), 0, st, vl, w, partial, hdr, V);
         if (vl.n > 0)
             hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kGS + 1, out + i0);
         if (i0 + kGS >= nv) {
@@ -197,20 +214,16 @@ static hipError_t site_mdot_p(const void *const *v, int nv, const void *w, int V
 }
 
 template <int P>
-static hipError_t site_axpy_p(const void *const *v, int nv, const double2 *coef, const double *mult, void *w, int V,
-                              double2 *partial, double2 *norm_out, hipStream_t st) {
+static hipError_t site_axpy_p(const void *const *v, int nv, const double2 *coef, void *w, int V, double2 *partial,
+                              double2 *norm_out, const double2 *hdr, hipStream_t st) {
     const int G = site_grid(V);
     for (int i0 = 0; i0 < nv; i0 += kGS) {
         VecList vl;
-        MultList ml;
         vl.n = nv - i0 < kGS ? nv - i0 : kGS;
-        for (int i = 0; i < kGS; i++) {
-            vl.v[i] = i < vl.n ? v[i0 + i] : w;
-            ml.m[i] = (i < vl.n && mult) ? mult[i0 + i] : 1.0;
-        }
+        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
         const bool last = i0 + kGS >= nv;
-        hipLaunchKernelGGL(k_site_axpy<P>, dim3(G), dim3(kRedThreads), 0, st, vl, ml, coef + i0, w,
-                           (last && norm_out) ? partial : (double2 *)nullptr, V);
+        hipLaunchKernelGGL(k_site_axpy<P>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, w,
+                           (last && norm_out) ? partial : (double2 *)nullptr, hdr, last ? 1 : 0, V);
         if (last && norm_out)
             hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial, G, 1, norm_out);
     }
@@ -218,40 +231,36 @@ static hipError_t site_axpy_p(const void *const *v, int nv, const double2 *coef,
 }
 
 template <int P>
-static hipError_t site_combine_p(const void *const *z, int nz, const double2 *coef, double2 *x, int V,
-                                 hipStream_t st) {
+static hipError_t site_combine_p(const void *const *z, int nmax, const double2 *coef, const double2 *hdr, double2 *x,
+                                 int V, hipStream_t st) {
     for (int i0 = 0;; i0 += kGS) {
         VecList vl;
-        CoefList cl;
-        vl.n = nz - i0 < kGS ? nz - i0 : kGS;
+        vl.n = nmax - i0 < kGS ? nmax - i0 : kGS;
         if (vl.n < 0) vl.n = 0;
-        for (int i = 0; i < kGS; i++) {
-            vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
-            cl.c[i] = i < vl.n ? coef[i0 + i] : make_double2(0, 0);
-        }
-        hipLaunchKernelGGL(k_site_combine<P>, dim3(site_grid(V)), dim3(kRedThreads), 0, st, vl, cl, x,
-                           i0 > 0 ? 1 : 0, V);
-        if (i0 + kGS >= nz) break;
+        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
+        hipLaunchKernelGGL(k_site_combine<P>, dim3(site_grid(V)), dim3(kRedThreads), 0, st, vl, coef + i0, hdr, i0,
+                           x, V);
+        if (i0 + kGS >= nmax) break;
     }
     return hipGetLastError();
 }
 
 hipError_t site_mdot(int prec, const void *const *v, int nv, const void *w, int V, double2 *partial, double2 *out,
-                     hipStream_t st) {
+                     const double2 *hdr, hipStream_t st) {
     switch (prec) {
-    case WDIRAC_F64: return site_mdot_p<WDIRAC_F64>(v, nv, w, V, partial, out, st);
-    case WDIRAC_F32: return site_mdot_p<WDIRAC_F32>(v, nv, w, V, partial, out, st);
-    case WDIRAC_F16S: return site_mdot_p<WDIRAC_F16S>(v, nv, w, V, partial, out, st);
+    case WDIRAC_F64: return site_mdot_p<WDIRAC_F64>(v, nv, w, V, partial, out, hdr, st);
+    case WDIRAC_F32: return site_mdot_p<WDIRAC_F32>(v, nv, w, V, partial, out, hdr, st);
+    case WDIRAC_F16S: return site_mdot_p<WDIRAC_F16S>(v, nv, w, V, partial, out, hdr, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t site_axpy(int prec, const void *const *v, int nv, const double2 *coef, const double *mult, void *w, int V,
-                     double2 *partial, double2 *norm_out, hipStream_t st) {
+hipError_t site_axpy(int prec, const void *const *v, int nv, const double2 *coef, void *w, int V, double2 *partial,
+                     double2 *norm_out, const double2 *hdr, hipStream_t st) {
     switch (prec) {
-    case WDIRAC_F64: return site_axpy_p<WDIRAC_F64>(v, nv, coef, mult, w, V, partial, norm_out, st);
-    case WDIRAC_F32: return site_axpy_p<WDIRAC_F32>(v, nv, coef, mult, w, V, partial, norm_out, st);
-    case WDIRAC_F16S: return site_axpy_p<WDIRAC_F16S>(v, nv, coef, mult, w, V, partial, norm_out, st);
+    case WDIRAC_F64: return site_axpy_p<WDIRAC_F64>(v, nv, coef, w, V, partial, norm_out, hdr, st);
+    case WDIRAC_F32: return site_axpy_p<WDIRAC_F32>(v, nv, coef, w, V, partial, norm_out, hdr, st);
+    case WDIRAC_F16S: return site_axpy_p<WDIRAC_F16S>(v, nv, coef, w, V, partial, norm_out, hdr, st);
     }
     return hipErrorInvalidValue;
 }
@@ -272,12 +281,12 @@ hipError_t site_scale(int pin, int pout, const void *in, void *out, double mult,
     return hipErrorInvalidValue;
 }
 
-hipError_t site_combine(int prec, const void *const *z, int nz, const double2 *coef, double2 *x, int V,
-                        hipStream_t st) {
+hipError_t site_combine(int prec, const void *const *z, int nmax, const double2 *coef, const double2 *hdr, double2 *x,
+                        int V, hipStream_t st) {
     switch (prec) {
-    case WDIRAC_F64: return site_combine_p<WDIRAC_F64>(z, nz, coef, x, V, st);
-    case WDIRAC_F32: return site_combine_p<WDIRAC_F32>(z, nz, coef, x, V, st);
-    case WDIRAC_F16S: return site_combine_p<WDIRAC_F16S>(z, nz, coef, x, V, st);
+    case WDIRAC_F64: return site_combine_p<WDIRAC_F64>(z, nmax, coef, hdr, x, V, st);
+    case WDIRAC_F32: return site_combine_p<WDIRAC_F32>(z, nmax, coef, hdr, x, V, st);
+    case WDIRAC_F16S: return site_combine_p<WDIRAC_F16S>(z, nmax, coef, hdr, x, V, st);
     }
     return hipErrorInvalidValue;
 }

@@ -26,6 +26,9 @@ constexpr int kOrderLinear = 0;    // tile slot = tile, lexicographic
 constexpr int kOrderXcdChunk = 1;  // each XCD gets a contiguous 1/8 of the lattice
 constexpr int kOrderTSweep = 2;    // each XCD gets 1/8 of every T-slice; slices in order
 constexpr int kOrderColumn = 3;    // lanes walk columns along T (register-carried T neighbours)
+constexpr int kOrderPatch = 4;     // as kOrderColumn, a work-group's columns form a z-y-x patch
+constexpr int kPatchX = 16, kPatchY = 4;  // patch extent in X and Y; Z extent = block / 64
+__host__ __device__ constexpr bool is_column_order(int order) { return order == kOrderColumn || order == kOrderPatch; }
 
 struct TileMap {
     int order;
@@ -33,9 +36,11 @@ struct TileMap {
     int V;
     int slice;            // sites per T-slice
     int tiles_per_range;  // kOrderTSweep / kOrderColumn: tiles per (slice, XCD) range
-    int tchunk;           // kOrderColumn: sites per lane along T
+    int tchunk;           // kOrderColumn / kOrderPatch: sites per lane along T
     int ntiles;           // tile slots holding sites
     int nslots;           // ntiles rounded up to a multiple of 8
+    int patches;          // kOrderPatch: patches per T-slice
+    int npx, npy, pz;     // kOrderPatch: patches along X and Y, patch extent in Z
 };
 
 TileMap make_tilemap(const Geom &g, int order, int block, int tchunk);
@@ -53,7 +58,7 @@ bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, LaunchCfg &out);
 struct Tuning {
     int block = 256;             // threads per work-group: 64, 128, 192 or 256
     int order = kOrderTSweep;    // tile order
-    int tchunk = 4;              // kOrderColumn: T sites per lane
+    int tchunk = 4;              // kOrderColumn / kOrderPatch: T sites per lane
     int persistent_blocks = 0;   // cap on the persistent grid (0: all co-resident work-groups)
     int nr[3] = {2, 2, 2};       // register block size per precision (1, 2 or 4)
     bool explicit_launch = false;  // set by dirac_tune_set: use these values, ignore autotuned ones

@@ -402,13 +402,25 @@ void dslash_column_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int a
         const int xcd = w & 7, q = w >> 3;
         const int vb = (q / tab.nchunks) * 8 + xcd;
         const int c = q - (q / tab.nchunks) * tab.nchunks;
-        // columns of XCD k's 1/8 of a slice, T-chunk tc
+        // columns of XCD k's 1/8 of a slice (or of its patches), T-chunk tc
         const int k = vb & 7, j = vb >> 3;
         const int tc = j / m.tiles_per_range, tile = j - tc * m.tiles_per_range;
-        const int r0 = (int)(((long long)k * m.slice) >> 3), r1 = (int)(((long long)(k + 1) * m.slice) >> 3);
-        const int col = r0 + tile * m.block + (int)threadIdx.x;
         const int t0 = tc * m.tchunk, t1 = min(t0 + m.tchunk, g.n[0]);
-        if (col < r1 && t0 < t1) column_sweep<P, DAG, NR>(tab.c[c], d, g, col, t0, t1, apbc != 0);
+        int col = -1;
+        if (m.order == kOrderPatch) {
+            const int p0 = (int)(((long long)k * m.patches) >> 3), p1 = (int)(((long long)(k + 1) * m.patches) >> 3);
+            const int pi = p0 + tile;
+            const int lx = (int)threadIdx.x % kPatchX, ly = ((int)threadIdx.x / kPatchX) % kPatchY,
+                      lz = (int)threadIdx.x / (kPatchX * kPatchY);
+            const int px = pi % m.npx, py = (pi / m.npx) % m.npy, pzi = pi / (m.npx * m.npy);
+            const int x = px * kPatchX + lx, y = py * kPatchY + ly, z = pzi * m.pz + lz;
+            if (pi < p1 && x < g.n[3] && y < g.n[2] && z < g.n[1]) col = (z * g.n[2] + y) * g.n[3] + x;
+        } else {
+            const int r0 = (int)(((long long)k * m.slice) >> 3), r1 = (int)(((long long)(k + 1) * m.slice) >> 3);
+            const int cc = r0 + tile * m.block + (int)threadIdx.x;
+            if (cc < r1) col = cc;
+        }
+        if (col >= 0 && t0 < t1) column_sweep<P, DAG, NR>(tab.c[c], d, g, col, t0, t1, apbc != 0);
     }
 }
 
@@ -422,9 +434,17 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     m.V = g.V;
     m.slice = g.V / g.n[0];
     m.tchunk = tchunk < 1 ? 1 : (tchunk > g.n[0] ? g.n[0] : tchunk);
+    m.patches = m.npx = m.npy = 0;
+    m.pz = block / (kPatchX * kPatchY);
     if (order == kOrderColumn) {
         const int per_range = (m.slice + 7) / 8;
         m.tiles_per_range = (per_range + block - 1) / block;
+        m.ntiles = (g.n[0] + m.tchunk - 1) / m.tchunk * 8 * m.tiles_per_range;
+    } else if (order == kOrderPatch) {
+        m.npx = (g.n[3] + kPatchX - 1) / kPatchX;
+        m.npy = (g.n[2] + kPatchY - 1) / kPatchY;
+        m.patches = m.npx * m.npy * ((g.n[1] + m.pz - 1) / m.pz);
+        m.tiles_per_range = (m.patches + 7) / 8;
         m.ntiles = (g.n[0] + m.tchunk - 1) / m.tchunk * 8 * m.tiles_per_range;
     } else if (order == kOrderTSweep) {
         const int per_range = (m.slice + 7) / 8;
@@ -494,14 +514,14 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
         if (persistent) {
             // every work-group must be resident, so that the work-groups of an
             // XCD walk through its items together (in order)
-            long long cap = m.order == kOrderColumn ? resident_blocks_col<P, DAG, NR>(cfg.block)
+            long long cap = is_column_order(m.order) ? resident_blocks_col<P, DAG, NR>(cfg.block)
                                                     : resident_blocks<P, DAG, NR>(cfg.block);
             if (tu.persistent_blocks > 0 && tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
             if (cap < 8) cap = 8;
             if (grid > cap) grid = cap;
         }
         if (grid > (1LL << 30)) return hipErrorInvalidValue;
-        if (m.order == kOrderColumn)
+        if (is_column_order(m.order))
             hipLaunchKernelGGL((dslash_column_kernel<P, DAG, NR>), dim3((unsigned)grid), dim3(cfg.block), 0, st, tab,
                                d, g, m, apbc);
         else
@@ -544,7 +564,7 @@ static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData 
     int total = 0;
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
     if (total == 1) cfg.nr = 1;
-    if (cfg.order == kOrderColumn && P == WDIRAC_F64 && cfg.nr > 2) cfg.nr = 2;  // register budget
+    if (is_column_order(cfg.order) && P == WDIRAC_F64 && cfg.nr > 2) cfg.nr = 2;  // register budget
     if (cfg.nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, cfg, st);
     if (cfg.nr >= 2) return launch_nr<P, DAG, 2>(batches, nbatch, d, g, apbc, persistent, cfg, st);
     return launch_nr<P, DAG, 1>(batches, nbatch, d, g, apbc, persistent, cfg, st);

@@ -25,19 +25,22 @@
 // stopped at the relative residual inner_tol or after inner_maxit
 // applications.  The inner Krylov basis is stored in the inner operator's own
 // native layout (FP32, or FP16 with per-site scales) and all its inner
-// products accumulate in FP64.  Inner basis vectors are normalised lazily:
-// the operator writes D W_k straight into the next basis slot, which is
-// orthogonalised in place and kept unnormalised; the host tracks the stored
-// norms c_k (W_k = c_k v_k) and folds them into the Hessenberg entries, the
-// update coefficients and the final combination, so no separate scaling or
-// conversion pass runs per inner step.  The outer residual,
-// orthogonalisation and update stay FP64, so the outer loop is an iterative
-// refinement of the low-precision solves.
-//
-// Host work per Arnoldi step: one stream synchronisation, to read the new
-// Hessenberg column (a few complex numbers) and decide how to continue.
+// products accumulate in FP64.  The operator writes D W_k straight into the
+// next basis slot, which is orthogonalised and normalised in place in one
+// pass: the normalisation factor comes from the Pythagorean estimate
+// |w|^2 - sum |h_ik|^2 (exact norms c_k of the stored vectors are measured
+// in the same pass and folded into the Hessenberg entries, so the estimate
+// only has to keep magnitudes near 1).  The inner cycle's Givens rotations,
+// termination test and triangular solve run on the device, so a cycle needs
+// no host decision: it is issued step by step with one host read of the
+// active flags per step, or (params.graph) captured once per outer slot as a
+// HIP graph and replayed.  The outer residual, orthogonalisation and update
+// stay FP64, so the outer loop is an iterative refinement of the
+// low-precision solves.
+
 #include <chrono>
 #include <complex>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -53,6 +56,160 @@ using zc = std::complex<double>;
 namespace {
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Device-side state of one right-hand side's inner GMRES cycle (carved from
+// its scalar block).
+struct InnerDev {
+    double2 *hdr;         // [0] = (completed steps j, active flag), [1] = (normalisation factor f, 0)
+    double *ic;           // [mi + 1] norms c_k of the stored basis vectors (W_k = c_k v_k)
+    double2 *H;           // [(mi + 1) mi] Hessenberg columns, column-major, Givens-rotated
+    double *cs;           // [mi] rotation cosines
+    double2 *sn;          // [mi] rotation sines
+    double2 *g;           // [mi + 1] rotated right-hand side beta e_1
+    double2 *coef;        // [mi + 1] update coefficients of a step; at the end y_i / c_i
+    const double2 *hcol;  // [mi + 2] inner products of the current step (mdot / axpy results)
+};
+
+size_t inner_state_bytes(int mi) {
+    const size_t n2 = 2 + (size_t)(mi + 1) * mi + mi + (mi + 1) + (mi + 1);  // double2 entries
+    const size_t n1 = (size_t)(mi + 1) + mi;                                // double entries
+    return n2 * sizeof(double2) + n1 * sizeof(double) + 64;
+}
+
+InnerDev carve_inner(char *base, int mi, const double2 *hcol) {
+    InnerDev d;
+    double2 *q = reinterpret_cast<double2 *>(base);
+    d.hdr = q;
+    q += 2;
+    d.H = q;
+    q += (size_t)(mi + 1) * mi;
+    d.sn = q;
+    q += mi;
+    d.g = q;
+    q += mi + 1;
+    d.coef = q;
+    q += mi + 1;
+    double *r = reinterpret_cast<double *>(q);
+    d.ic = r;
+    r += mi + 1;
+    d.cs = r;
+    d.hcol = hcol;
+    return d;
+}
+
+constexpr int kListMax = 16;  // right-hand sides per state-kernel launch
+struct InnerList {
+    InnerDev d[kListMax];
+    int n;
+    int mi;
+};
+
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 c_scale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double c_abs(double2 a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ double2 c_div(double2 a, double2 b) {  // a / b, b != 0
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// start of a cycle: v_0 = W_0 has unit norm, beta = 1
+__global__ void k_inner_init(InnerList L) {
+    const int t = threadIdx.x;
+    if (t >= L.n) return;
+    const InnerDev &d = L.d[t];
+    d.hdr[0] = make_double2(0.0, 1.0);
+    d.hdr[1] = make_double2(1.0, 0.0);
+    d.ic[0] = 1.0;
+    d.g[0] = make_double2(1.0, 0.0);
+    for (int i = 1; i <= L.mi; i++) d.g[i] = make_double2(0.0, 0.0);
+}
+
+// step k, after the inner products d_i = W_i^H w (i <= k) and |w|^2 of
+// w = D W_k: orthogonalisation coefficients d_i / c_i^2 and the factor f that
+// brings the orthogonalised vector near unit norm (Pythagorean estimate;
+// with severe cancellation f = 1/|w| instead)
+__global__ void k_inner_prep(InnerList L, int k) {
+    const int t = threadIdx.x;
+    if (t >= L.n) return;
+    const InnerDev &d = L.d[t];
+    if (d.hdr[0].y == 0.0) return;
+    const double w2 = d.hcol[k + 1].x;
+    double proj = 0.0;
+    for (int i = 0; i <= k; i++) {
+        const double m = 1.0 / (d.ic[i] * d.ic[i]);
+        const double2 h = d.hcol[i];
+        d.coef[i] = c_scale(m, h);
+        proj += (h.x * h.x + h.y * h.y) * m;
+    }
+    const double rem = w2 - proj;
+    d.hdr[1].x = rem > 1e-8 * w2 ? 1.0 / sqrt(rem) : (w2 > 0.0 ? 1.0 / sqrt(w2) : 1.0);
+}
+
+// step k, after the in-place orthogonalisation: Hessenberg column k, Givens
+// rotation, residual estimate |g_{k+1}|, termination test
+__global__ void k_inner_givens(InnerList L, int k, double tol, int maxit) {
+    const int t = threadIdx.x;
+    if (t >= L.n) return;
+    const InnerDev &d = L.d[t];
+    if (d.hdr[0].y == 0.0) return;
+    const int ld = L.mi + 1;
+    double2 *col = d.H + (size_t)k * ld;
+    const double ck = d.ic[k];
+    for (int i = 0; i <= k; i++) col[i] = c_scale(1.0 / (d.ic[i] * ck), d.hcol[i]);
+    const double nrm = sqrt(fmax(d.hcol[k + 1].x, 0.0));  // |W_{k+1}| = f c_k h_{k+1,k}
+    const double hn = nrm / (d.hdr[1].x * ck);
+    for (int i = 0; i < k; i++) {
+        const double2 a = col[i], b = col[i + 1];
+        col[i] = c_add(c_scale(d.cs[i], a), c_mul(d.sn[i], b));
+        col[i + 1] = c_sub(c_scale(d.cs[i], b), c_mul(c_conj(d.sn[i]), a));
+    }
+    const double2 a = col[k];
+    const double r = hypot(c_abs(a), hn);
+    double cs;
+    double2 sn;
+    if (r == 0.0) {
+        cs = 1.0;
+        sn = make_double2(0.0, 0.0);
+    } else if (c_abs(a) == 0.0) {
+        cs = 0.0;
+        sn = make_double2(1.0, 0.0);  // conj(b) / |b| with b = hn > 0 real
+    } else {
+        const double aa = c_abs(a);
+        cs = aa / r;
+        sn = c_scale(hn / (aa * r), a);  // (a / |a|) conj(b) / r with b = hn real
+    }
+    d.cs[k] = cs;
+    d.sn[k] = sn;
+    col[k] = c_add(c_scale(cs, a), c_scale(hn, sn));
+    col[k + 1] = make_double2(0.0, 0.0);
+    const double2 gk = d.g[k];
+    d.g[k + 1] = c_scale(-1.0, c_mul(c_conj(sn), gk));
+    d.g[k] = c_scale(cs, gk);
+    d.ic[k + 1] = nrm;
+    const int j = k + 1;
+    const bool stop = c_abs(d.g[k + 1]) < tol || j >= maxit || hn == 0.0;
+    d.hdr[0] = make_double2((double)j, stop ? 0.0 : 1.0);
+}
+
+// cycle end: y = R^{-1} g (leading j x j triangle), coef_i = y_i / c_i
+__global__ void k_inner_solve(InnerList L) {
+    const int t = threadIdx.x;
+    if (t >= L.n) return;
+    const InnerDev &d = L.d[t];
+    const int j = (int)d.hdr[0].x, ld = L.mi + 1;
+    for (int i = j - 1; i >= 0; i--) {
+        double2 s = d.g[i];
+        for (int q = i + 1; q < j; q++) s = c_sub(s, c_mul(d.H[(size_t)q * ld + i], d.coef[q]));
+        const double2 dg = d.H[(size_t)i * ld + i];
+        d.coef[i] = (dg.x == 0.0 && dg.y == 0.0) ? make_double2(0.0, 0.0) : c_div(s, dg);
+    }
+    for (int i = 0; i < j; i++) d.coef[i] = c_scale(1.0 / d.ic[i], d.coef[i]);
+}
 
 struct Layout {
     size_t f64, f32, f16, scal;  // bytes of one field / scalar block
@@ -76,6 +233,7 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     const int m = p->restart, mi = p->mode == FGMRES_F64 ? 0 : p->inner_restart;
     const int kmax = kmax_of(p);
     L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kGS + 1) + 3 * (size_t)kmax + 8));
+    if (p->mode != FGMRES_F64) L.scal += align256(inner_state_bytes(mi));
     L.per_rhs = (size_t)(m + 2) * L.f64 + L.scal;  // V[0..m], w
     if (p->mode != FGMRES_F64) {
         L.per_rhs += (size_t)m * L.f64;                                          // Z[0..m)
@@ -149,14 +307,14 @@ struct Rhs {
     const double2 *b = nullptr;
     std::vector<void *> V, Z;  // outer basis (F64), preconditioned vectors (F64)
     double2 *w = nullptr;
-    std::vector<void *> Vi;    // inner basis, inner operator precision, unnormalised
-    std::vector<double> ic;    // stored norms of the inner basis vectors (host)
+    std::vector<void *> Vi;    // inner basis, inner operator precision
+    InnerDev in;               // device state of the inner cycle
     double2 *partial = nullptr, *hcol = nullptr, *coef = nullptr, *hcol2 = nullptr, *nrm = nullptr;
     // host
     Phase phase = Phase::Residual;
-    Arnoldi outer, inner;
+    Arnoldi outer;
     double r0norm = -1, relres = 1;
-    bool breakdown = false, converged = false, inner_done = false;
+    bool breakdown = false, converged = false;
     long long applies = 0, inner_applies = 0, restarts = 0;
     std::vector<double> hist;
 };
@@ -172,9 +330,19 @@ struct Ctx {
     size_t pinned_n;
 };
 
-hipError_t apply_many(const Ctx &c, int prec, const std::vector<dirac_batch> &b) {
+// instantiated inner-cycle graphs of one solve, keyed by the right-hand sides they cover
+struct GraphCache {
+    hipStream_t cap = nullptr;  // private capture stream
+    std::map<std::vector<int>, hipGraphExec_t> exec;
+    ~GraphCache() {
+        for (auto &e : exec) (void)hipGraphExecDestroy(e.second);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+hipError_t apply_many(const Ctx &c, int prec, const std::vector<dirac_batch> &b, hipStream_t s) {
     if (b.empty()) return hipSuccess;
-    return dslash_launch_batches(b.data(), (int)b.size(), prec, false, c.op->data(prec), c.op->g, c.apbc, false, c.st);
+    return dslash_launch_batches(b.data(), (int)b.size(), prec, false, c.op->data(prec), c.op->g, c.apbc, false, s);
 }
 
 #define WD_TRY(expr)                                                                              \
@@ -209,75 +377,109 @@ std::vector<double2> to_d2(const std::vector<zc> &v) {
     return t;
 }
 
-// Inner GMRES on the low-precision operator for every listed right-hand
-// side: z = M^{-1} v with v = V[j] (unit norm) and z = Z[j].
-int inner_solve(const Ctx &c, std::vector<Rhs *> &list) {
+hipError_t launch_state(void (*kern)(InnerList), const std::vector<Rhs *> &rs, int mi, hipStream_t s) {
+    for (size_t a = 0; a < rs.size(); a += kListMax) {
+        InnerList L;
+        L.n = (int)std::min<size_t>(kListMax, rs.size() - a);
+        L.mi = mi;
+        for (int q = 0; q < L.n; q++) L.d[q] = rs[a + q]->in;
+        hipLaunchKernelGGL(kern, dim3(1), dim3(64), 0, s, L);
+    }
+    return hipGetLastError();
+}
+
+template <typename F> hipError_t launch_state_k(const std::vector<Rhs *> &rs, int mi, hipStream_t s, F launch) {
+    for (size_t a = 0; a < rs.size(); a += kListMax) {
+        InnerList L;
+        L.n = (int)std::min<size_t>(kListMax, rs.size() - a);
+        L.mi = mi;
+        for (int q = 0; q < L.n; q++) L.d[q] = rs[a + q]->in;
+        launch(L);
+    }
+    return hipGetLastError();
+}
+
+// Issue the body of one inner GMRES cycle (start, steps, triangular solve)
+// for every listed right-hand side on stream s; W_0 must hold v = V[j].
+// host_steps: read the active flags after every step (one synchronisation)
+// and drop finished right-hand sides from later launches; otherwise every
+// step is issued for all of them and finished ones are skipped on the device
+// (graph capture).  The body does not depend on the outer slot j.
+int issue_inner_body(const Ctx &c, const std::vector<Rhs *> &list, bool host_steps, hipStream_t s) {
     const fgmres_params &p = *c.p;
     const int prec = inner_prec(p.mode);
     const int mi = p.inner_restart;
     const int maxit = p.inner_maxit < mi ? p.inner_maxit : mi;
-    for (Rhs *r : list) {
-        WD_TRY(site_scale(WDIRAC_F64, prec, r->V[r->outer.j], r->Vi[0], 1.0, c.V, c.st));
-        r->inner.reset(mi, 1.0);
-        r->ic.assign(1, 1.0);
-        r->inner_done = false;
-    }
+    WD_TRY(launch_state(k_inner_init, list, mi, s));
     std::vector<Rhs *> act = list;
-    std::vector<double> mult;
-    while (!act.empty()) {
-        // W_{k+1} = D W_k for every active right-hand side, one batched launch
+    for (int k = 0; k < maxit && !act.empty(); k++) {
+        // W_{k+1} = D W_k, one batched launch for the right-hand sides still iterating
         std::vector<dirac_batch> b;
-        for (Rhs *r : act) b.push_back({r->Vi[r->inner.j + 1], r->Vi[r->inner.j], 1});
-        WD_TRY(apply_many(c, prec, b));
-        for (Rhs *r : act) {
-            const int k = r->inner.j;
-            r->inner_applies++;
-            // dots d_i = W_i^H W_{k+1} = c_i c_k h_ik; then W_{k+1} -= sum_i d_i / c_i^2 W_i
-            WD_TRY(site_mdot(prec, r->Vi.data(), k + 1, r->Vi[k + 1], c.V, r->partial, r->hcol, c.st));
-            mult.resize(k + 1);
-            for (int i = 0; i <= k; i++) mult[i] = 1.0 / (r->ic[i] * r->ic[i]);
-            WD_TRY(site_axpy(prec, r->Vi.data(), k + 1, r->hcol, mult.data(), r->Vi[k + 1], c.V, r->partial,
-                             r->hcol + k + 1, c.st));
-        }
+        for (Rhs *r : act) b.push_back({r->Vi[k + 1], r->Vi[k], 1});
+        WD_TRY(apply_many(c, prec, b, s));
+        for (Rhs *r : act)
+            WD_TRY(site_mdot(prec, r->Vi.data(), k + 1, r->Vi[k + 1], c.V, r->partial, r->hcol, r->in.hdr, s));
+        WD_TRY(launch_state_k(act, mi, s, [&](const InnerList &L) {
+            hipLaunchKernelGGL(k_inner_prep, dim3(1), dim3(64), 0, s, L, k);
+        }));
+        for (Rhs *r : act)
+            WD_TRY(site_axpy(prec, r->Vi.data(), k + 1, r->in.coef, r->Vi[k + 1], c.V, r->partial, r->hcol + k + 1,
+                             r->in.hdr, s));
+        WD_TRY(launch_state_k(act, mi, s, [&](const InnerList &L) {
+            hipLaunchKernelGGL(k_inner_givens, dim3(1), dim3(64), 0, s, L, k, p.inner_tol, maxit);
+        }));
+        if (!host_steps) continue;
         std::vector<std::pair<const double2 *, int>> src;
-        for (Rhs *r : act) src.emplace_back(r->hcol, r->inner.j + 2);
+        for (Rhs *r : act) src.emplace_back(r->in.hdr, 1);
         std::vector<std::vector<zc>> h;
         int rc = fetch(c, src, h);
         if (rc) return rc;
         std::vector<Rhs *> next;
-        for (size_t q = 0; q < act.size(); q++) {
-            Rhs *r = act[q];
-            const int k = r->inner.j;
-            const double ck = r->ic[k];
-            std::vector<zc> col(k + 2);
-            for (int i = 0; i <= k; i++) col[i] = h[q][i] / (r->ic[i] * ck);
-            const double nrm = std::sqrt(std::max(h[q][k + 1].real(), 0.0));  // |W_{k+1}| = c_k h_{k+1,k}
-            const double hn = nrm / ck;
-            col[k + 1] = hn;
-            const double est = r->inner.add_column(col.data());
-            const bool stop = est < p.inner_tol || r->inner.j >= maxit || hn == 0.0;
-            if (stop) {
-                r->inner_done = true;
-                continue;
-            }
-            if (nrm > 1e-20 && nrm < 1e20) {
-                r->ic.push_back(nrm);
-            } else {  // keep stored magnitudes well inside the FP32 range
-                WD_TRY(site_scale(prec, prec, r->Vi[k + 1], r->Vi[k + 1], 1.0 / nrm, c.V, c.st));
-                r->ic.push_back(1.0);
-            }
-            next.push_back(r);
-        }
+        for (size_t q = 0; q < act.size(); q++)
+            if (h[q][0].imag() != 0.0) next.push_back(act[q]);
         act.swap(next);
     }
-    // z_j = sum_i y_i v_i = sum_i (y_i / c_i) W_i, accumulated in FP64
-    for (Rhs *r : list) {
-        std::vector<zc> y = r->inner.solve();
-        for (size_t i = 0; i < y.size(); i++) y[i] /= r->ic[i];
-        const std::vector<double2> yd = to_d2(y);
-        WD_TRY(site_combine(prec, r->Vi.data(), (int)yd.size(), yd.data(), static_cast<double2 *>(r->Z[r->outer.j]),
-                            c.V, c.st));
+    WD_TRY(launch_state(k_inner_solve, list, mi, s));
+    return WDIRAC_OK;
+}
+
+// Inner solves z = M^{-1} v_j of the listed right-hand sides (v_j = V[j],
+// z = Z[j], j each one's outer step).  The cycle body runs step by step, or
+// as a graph captured on first use for this set of right-hand sides.
+int inner_solve(const Ctx &c, const std::vector<Rhs *> &list, GraphCache *gc, const std::vector<Rhs> &all) {
+    const int prec = inner_prec(c.p->mode);
+    const int mi = c.p->inner_restart;
+    const int maxit = c.p->inner_maxit < mi ? c.p->inner_maxit : mi;
+    for (Rhs *r : list) WD_TRY(site_scale(WDIRAC_F64, prec, r->V[r->outer.j], r->Vi[0], 1.0, c.V, c.st));
+    if (!gc) {
+        int rc = issue_inner_body(c, list, true, c.st);
+        if (rc) return rc;
+    } else {
+        std::vector<int> key;
+        for (Rhs *r : list) key.push_back((int)(r - all.data()));
+        auto it = gc->exec.find(key);
+        if (it == gc->exec.end()) {
+            if (!gc->cap) WD_TRY(hipStreamCreateWithFlags(&gc->cap, hipStreamNonBlocking));
+            WD_TRY(hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal));
+            const int rc = issue_inner_body(c, list, false, gc->cap);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(gc->cap, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("inner-cycle capture: ") + hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) return fail(WDIRAC_EHIP, std::string("inner-cycle graph: ") + hipGetErrorString(ei));
+            it = gc->exec.emplace(key, exec).first;
+        }
+        WD_TRY(hipGraphLaunch(it->second, c.st));
     }
+    for (Rhs *r : list)
+        WD_TRY(site_combine(prec, r->Vi.data(), maxit, r->in.coef, r->in.hdr, static_cast<double2 *>(r->Z[r->outer.j]),
+                            c.V, c.st));
     return WDIRAC_OK;
 }
 
@@ -305,6 +507,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     Ctx c{op, p, stream, 12LL * op->g.V, op->g.V, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, pinned, pinned_n};
     const bool mixed = p->mode != FGMRES_F64;
     const int m = p->restart;
+    GraphCache graphs;
     // carve the workspace
     std::vector<Rhs> R(nrhs);
     char *wp = static_cast<char *>(work);
@@ -332,7 +535,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         r.coef = r.hcol + kmax;
         r.hcol2 = r.coef + kmax;
         r.nrm = r.hcol2 + kmax;
-        if (reinterpret_cast<char *>(r.nrm + 1) > s + L.scal) return fail(WDIRAC_EINVAL, "internal: scalar block overflow");
+        char *end = reinterpret_cast<char *>(r.nrm + 1);
+        if (mixed) {
+            char *ib = s + align256(sizeof(double2) * ((size_t)kRedBlocks * (kGS + 1) + 3 * (size_t)kmax + 8));
+            r.in = carve_inner(ib, p->inner_restart, r.hcol);
+            end = ib + inner_state_bytes(p->inner_restart);
+        }
+        if (end > s + L.scal) return fail(WDIRAC_EINVAL, "internal: scalar block overflow");
     }
     if ((size_t)(wp - static_cast<char *>(work)) > work_bytes) return fail(WDIRAC_EINVAL, "workspace too small");
 
@@ -345,14 +554,14 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             if (r.phase == Phase::Residual) res.push_back(&r);
         }
         if (mixed && !arn.empty()) {
-            int rc = inner_solve(c, arn);
+            int rc = inner_solve(c, arn, p->graph ? &graphs : nullptr, R);
             if (rc) return rc;
         }
         // one batched FP64 application for all of them (lines 4 and 9)
         std::vector<dirac_batch> bat;
         for (Rhs *r : res) bat.push_back({r->w, r->x, 1});
         for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], 1});
-        WD_TRY(apply_many(c, WDIRAC_F64, bat));
+        WD_TRY(apply_many(c, WDIRAC_F64, bat, c.st));
         for (Rhs *r : res) {
             r->applies++;
             WD_TRY(residual(r->b, r->w, static_cast<double2 *>(r->V[0]), c.N, r->partial, r->nrm, c.st));
@@ -366,6 +575,8 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         std::vector<std::pair<const double2 *, int>> src;
         for (Rhs *r : res) src.emplace_back(r->nrm, 1);
         for (Rhs *r : arn) src.emplace_back(r->hcol, r->outer.j + 2);
+        if (mixed)
+            for (Rhs *r : arn) src.emplace_back(r->in.hdr, 1);  // inner steps taken
         std::vector<std::vector<zc>> got;
         if (!src.empty()) {
             int rc = fetch(c, src, got);
@@ -396,6 +607,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             Rhs &r = *arn[k];
             const int j = r.outer.j;
             const std::vector<zc> &hk = got[res.size() + k];
+            if (mixed) r.inner_applies += (long long)got[res.size() + arn.size() + k][0].real();
             std::vector<zc> col(j + 2);
             for (int i = 0; i <= j; i++) col[i] = hk[i];
             const double hn = std::sqrt(std::max(hk[j + 1].real(), 0.0));

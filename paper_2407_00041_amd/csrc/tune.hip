@@ -51,7 +51,7 @@ void load_cache_locked() {
         double us;
         if (sscanf(line, "{\"key\": \"%255[^\"]\", \"order\": %d, \"block\": %d, \"tchunk\": %d, \"nr\": %d, \"us\": %lf",
                    key, &c.order, &c.block, &c.tchunk, &c.nr, &us) == 6) {
-            if (c.order >= 0 && c.order <= 3 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
+            if (c.order >= 0 && c.order <= 4 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
                 c.tchunk >= 1 && (c.nr == 1 || c.nr == 2 || c.nr == 4))
                 g_table[key] = c;
         }
@@ -93,14 +93,14 @@ extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_ou
     int rc = WDIRAC_OK;
     std::vector<LaunchCfg> cands;
     const int nrs[3] = {1, 2, 4};
-    for (int order : {2, 3})
+    for (int order : {2, 3, 4})
         for (int block : {128, 256})
             for (int tchunk : {2, 4, 8}) {
-                if (order != 3 && tchunk != 4) continue;
+                if (!is_column_order(order) && tchunk != 4) continue;
                 for (int nr : nrs) {
                     if (nr > 1 && nr > nrhs) continue;
                     if (nrhs == 1 && nr > 1) continue;
-                    if (order == 3 && prec == WDIRAC_F64 && nr > 2) continue;
+                    if (is_column_order(order) && prec == WDIRAC_F64 && nr > 2) continue;
                     cands.push_back({order, block, tchunk, nr});
                 }
             }

@@ -77,6 +77,47 @@ def test_multi_rhs_equals_single_solves(mode):
         assert sr[0]["applies"] == st[r]["applies"]
 
 
+@pytest.mark.parametrize("mode", ["mixed_f32", "mixed_f16s"])
+def test_graph_inner_cycles_equal_stepwise(mode):
+    """Inner cycles replayed as captured graphs give bit-identical iterates to
+    the step-by-step issue, on every replay (graphs are replayed across outer
+    steps and restarts; eager solves run between the graph solves)."""
+    need_gpu()
+    dims = (4, 4, 6, 4)
+    U, b, op, bn = setup(dims, 7, -0.3, 1.0, nrhs=3)
+    kw = dict(nrhs=3, restart=6, tol=1e-10, maxit=500, mode=mode, inner_restart=12, inner_tol=0.05, inner_maxit=12)
+    xe, se, rc = op.solve(bn, **kw)
+    assert rc == 0
+    for rep in range(3):
+        xg, sg, rcg = op.solve(bn, graph=True, **kw)
+        assert rcg == 0
+        assert torch.equal(xg, xe), rep
+        for r in range(3):
+            assert sg[r]["applies"] == se[r]["applies"]
+            assert sg[r]["inner_applies"] == se[r]["inner_applies"]
+            assert sg[r]["hist"] == se[r]["hist"]
+        xe2, _, _ = op.solve(bn, **kw)  # eager work between graph solves
+        assert torch.equal(xe2, xe)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_inner_gmres_near_exact_on_2x4(graph):
+    """On a 2^4 lattice (dimension 192) an inner GMRES(192) to 1e-5 is nearly
+    the exact inverse, so the outer FGMRES needs only a few FP64 applications
+    (the exact-preconditioner limit of Algorithm 2); this exercises the
+    device-side Givens rotations and triangular solve over long cycles."""
+    need_gpu()
+    dims = (2, 2, 2, 2)
+    m0, csw = -0.3, 1.0
+    U, b, op, bn = setup(dims, 11, m0, csw)
+    x, st, rc = op.solve(bn, restart=10, tol=1e-10, maxit=50, mode="mixed_f32", inner_restart=192, inner_tol=1e-5,
+                         inner_maxit=192, graph=graph)
+    assert rc == 0 and st[0]["converged"], st[0]
+    assert st[0]["applies"] <= 5, st[0]
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    assert true_relres(dims, U, m0, csw, xg, b) <= 1e-10 * 1.01
+
+
 def test_maxit_zero_rhs_and_warm_start():
     need_gpu()
     dims = (4, 4, 4, 4)
