@@ -141,9 +141,13 @@ int dirac_apply_adjoint(const dirac_op *op, void *out, const void *in, int nrhs,
 
 /*
  * Several independent batches of right-hand sides (possibly of different
- * sizes) through ONE persistent launch: out_b = D in_b (or D^H when
+ * sizes) through ONE launch over a work list of (site tile, register block of
+ * right-hand sides) items spanning all batches: out_b = D in_b (or D^H when
  * dagger != 0) for every batch.  Each link and clover entry is read once per
- * site tile and register block of right-hand sides.
+ * site tile and register block (tile orders 0-4), or once per site for all
+ * right-hand sides of the launch (order 5).  Work-groups are handed out by
+ * the hardware in item order, or, with the "persistent_blocks" knob set, a
+ * persistent grid of that many resident work-groups strides through the list.
  */
 typedef struct {
     void *out;       /* native, nrhs fields                                 */
@@ -160,10 +164,14 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * "order" (0 linear, 1 one contiguous 1/8 of the lattice per XCD, 2 every
  * XCD takes 1/8 of each T-slice and the slices are swept in order, 3 lanes
  * walk columns along T carrying the T neighbours in registers, 4 as 3 with
- * each work-group's columns forming a 16 (X) x 4 (Y) x block/64 (Z) patch),
+ * each work-group's columns forming a 16 (X) x 4 (Y) x block/64 (Z) patch,
+ * 5 link-stationary: FP32/FP16S with two-row links, each lane keeps its links
+ * and clover on chip for all right-hand sides of the launch, 128-lane
+ * work-groups; other precisions and link formats fall back to order 2),
  * "tchunk" (orders 3 and 4: sites per lane along T, >= 1),
- * "persistent_blocks" (cap on the work-groups of a dirac_apply_batched launch;
- * 0, the default, means all work-groups that fit on the device at once),
+ * "persistent_blocks" (0, the default: dirac_apply_batched launches one
+ * work-group per work item; > 0: a persistent grid of at most that many and
+ * at most the co-resident work-groups, each walking the item list),
  * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
  * or 4).  Setting any of these launch knobs makes them override autotuned
  * choices; "explicit" = 0 returns to the autotuned ones (1 forces the knobs).

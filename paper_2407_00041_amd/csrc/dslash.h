@@ -27,7 +27,17 @@ constexpr int kOrderXcdChunk = 1;  // each XCD gets a contiguous 1/8 of the latt
 constexpr int kOrderTSweep = 2;    // each XCD gets 1/8 of every T-slice; slices in order
 constexpr int kOrderColumn = 3;    // lanes walk columns along T (register-carried T neighbours)
 constexpr int kOrderPatch = 4;     // as kOrderColumn, a work-group's columns form a z-y-x patch
+constexpr int kOrderStationary = 5;  // FP32/FP16S, two-row links: each lane keeps its links (registers) and
+                                     // clover (LDS) for all right-hand sides of the launch; T-sweep tiles
 constexpr int kPatchX = 16, kPatchY = 4;  // patch extent in X and Y; Z extent = block / 64
+constexpr int kStationaryBlock = 128;     // work-group size of the link-stationary kernel (LDS budget)
+constexpr int kMaxStationaryRhs = 64;     // right-hand sides per link-stationary launch
+
+struct RhsTable {
+    const void *in[kMaxStationaryRhs];
+    void *out[kMaxStationaryRhs];
+    int n;
+};
 __host__ __device__ constexpr bool is_column_order(int order) { return order == kOrderColumn || order == kOrderPatch; }
 
 struct TileMap {

@@ -24,8 +24,9 @@
 // while the slice is still in the Infinity Cache, and the Z-neighbours
 // mostly come from the same XCD's L2.  The register blocks of one tile are
 // consecutive items on the same XCD, so their shared links and clover stay
-// in that XCD's L2.  With fewer work-groups than items the kernel is
-// persistent: each work-group strides through the item list.
+// in that XCD's L2 while it can hold them.  With fewer work-groups than
+// items (an optional persistent grid) each work-group strides through the
+// item list.
 #include "spinor_io.h"
 #include "dslash.h"
 
@@ -389,9 +390,19 @@ void dslash_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int apbc) {
 }
 
 // the column sweep carries psi(t+1) and the T half-spinors: fewer waves
+#ifndef WD_OCCC_F64_1
+#define WD_OCCC_F64_1 2
+#endif
+#ifndef WD_OCCC_F32_1
+#define WD_OCCC_F32_1 3
+#endif
+#ifndef WD_OCCC_F16_1
+#define WD_OCCC_F16_1 4
+#endif
 template <int P, int NR> constexpr int occupancy_col() {
-    return P == WDIRAC_F64 ? (NR == 1 ? 2 : 1) : P == WDIRAC_F32 ? (NR == 1 ? 3 : NR == 2 ? 2 : 1)
-                                                                 : (NR == 1 ? 4 : NR == 2 ? 2 : 1);
+    return P == WDIRAC_F64 ? (NR == 1 ? WD_OCCC_F64_1 : 1)
+                           : P == WDIRAC_F32 ? (NR == 1 ? WD_OCCC_F32_1 : NR == 2 ? 2 : 1)
+                                             : (NR == 1 ? WD_OCCC_F16_1 : NR == 2 ? 2 : 1);
 }
 
 template <int P, bool DAG, int NR>
@@ -421,6 +432,105 @@ void dslash_column_kernel(ChunkTable<NR> tab, OpData d, Geom g, TileMap m, int a
             if (cc < r1) col = cc;
         }
         if (col >= 0 && t0 < t1) column_sweep<P, DAG, NR>(tab.c[c], d, g, col, t0, t1, apbc != 0);
+    }
+}
+
+// Link-stationary multi-RHS stencil (FP32 compute, two-row links): a lane
+// loads the 8 links it needs (rows 0 and 1 of U_mu(x) and U_mu(x-mu), 96
+// registers) and stages its own clover blocks in LDS once, then walks every
+// right-hand side of the launch reading only spinors.  Links and clover
+// are thus read from memory once per launch instead of once per register
+// block, which a 4 MB L2 per XCD cannot provide when many right-hand sides
+// stream through.  The LDS slots are private to their lane (no barrier).
+// Per right-hand side the arithmetic is that of dslash_kernel (same order).
+template <int P, bool DAG>
+__global__ __launch_bounds__(kStationaryBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apbc) {
+    using T = typename Store<P>::T;
+    static_assert(P != WDIRAC_F64, "FP64 links do not fit in registers");
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    __shared__ float4 lds[18][kStationaryBlock];
+    int lo, hi;
+    tile_range(m, blockIdx.x, lo, hi);
+    const int s = lo + (int)threadIdx.x;
+    if (s >= hi) return;
+    const int V = g.V;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        T dd[6];
+        cx<T> uu[15];
+        Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+        lds[9 * b + 0][tid] = make_float4(dd[0], dd[1], dd[2], dd[3]);
+        lds[9 * b + 1][tid] = make_float4(dd[4], dd[5], uu[0].r, uu[0].i);
+#pragma unroll
+        for (int k = 0; k < 7; k++)
+            lds[9 * b + 2 + k][tid] = make_float4(uu[1 + 2 * k].r, uu[1 + 2 * k].i, uu[2 + 2 * k].r, uu[2 + 2 * k].i);
+    }
+    const Nbr nb = neighbours(g, s);
+    cx<T> Lf[4][6], Lb[4][6];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        cx<T> U[9];
+        Store<P>::load_link(d.links, V, mu, s, U, 2);
+#pragma unroll
+        for (int e = 0; e < 6; e++) Lf[mu][e] = U[e];
+        Store<P>::load_link(d.links, V, mu, nb.bwd[mu], U, 2);
+#pragma unroll
+        for (int e = 0; e < 6; e++) Lb[mu][e] = U[e];
+    }
+    const T ffT = (apbc && nb.fwd_wrapT) ? T(0.5) : T(-0.5);
+    const T fbT = (apbc && nb.bwd_wrapT) ? T(0.5) : T(-0.5);
+    for (int r = 0; r < tab.n; r++) {
+        const void *in = tab.in[r];
+        cx<T> acc[12];
+        {
+            cx<T> self[12];
+            Store<P>::load_spinor(in, V, s, self);
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                T dd[6];
+                cx<T> uu[15];
+                const float4 a0 = lds[9 * b][tid], a1 = lds[9 * b + 1][tid];
+                dd[0] = a0.x; dd[1] = a0.y; dd[2] = a0.z; dd[3] = a0.w; dd[4] = a1.x; dd[5] = a1.y;
+                uu[0] = {a1.z, a1.w};
+#pragma unroll
+                for (int k = 0; k < 7; k++) {
+                    const float4 q = lds[9 * b + 2 + k][tid];
+                    uu[1 + 2 * k] = {q.x, q.y};
+                    uu[2 + 2 * k] = {q.z, q.w};
+                }
+                clover_block(dd, uu, &self[6 * b], &acc[6 * b]);
+            }
+        }
+        hop_fence(1);
+#define WD_STAT_HOP(MU)                                                         \
+        {                                                                       \
+            cx<T> U[9], p[12], h[6], chi[6];                                    \
+            _Pragma("unroll") for (int e = 0; e < 6; e++) U[e] = Lf[MU][e];     \
+            third_row(U);                                                       \
+            Store<P>::load_spinor(in, V, nb.fwd[MU], p);                        \
+            project<MU, SF>(p, h, MU == 0 ? ffT : T(-0.5));                     \
+            su3_mul<false>(U, h, chi);                                          \
+            reconstruct<MU, SF>(acc, chi);                                      \
+        }                                                                       \
+        {                                                                       \
+            cx<T> U[9], p[12], h[6], chi[6];                                    \
+            _Pragma("unroll") for (int e = 0; e < 6; e++) U[e] = Lb[MU][e];     \
+            third_row(U);                                                       \
+            Store<P>::load_spinor(in, V, nb.bwd[MU], p);                        \
+            project<MU, SB>(p, h, MU == 0 ? fbT : T(-0.5));                     \
+            su3_mul<true>(U, h, chi);                                           \
+            reconstruct<MU, SB>(acc, chi);                                      \
+        }                                                                       \
+        hop_fence(1);
+        WD_STAT_HOP(0)
+        WD_STAT_HOP(1)
+        WD_STAT_HOP(2)
+        WD_STAT_HOP(3)
+#undef WD_STAT_HOP
+        Store<P>::store_spinor(tab.out[r], V, s, acc);
     }
 }
 
@@ -511,12 +621,13 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
         for (int i = 0; i < tab.nchunks; i++) tab.c[i] = chunks[c0 + i];
         const long long items = (long long)m.nslots * tab.nchunks;
         long long grid = items;
-        if (persistent) {
-            // every work-group must be resident, so that the work-groups of an
-            // XCD walk through its items together (in order)
+        if (persistent && tu.persistent_blocks > 0) {
+            // a persistent grid: at most the resident work-groups, each striding
+            // through the item list (by default the hardware dispatcher hands
+            // out one work-group per item in order, which measured faster)
             long long cap = is_column_order(m.order) ? resident_blocks_col<P, DAG, NR>(cfg.block)
                                                     : resident_blocks<P, DAG, NR>(cfg.block);
-            if (tu.persistent_blocks > 0 && tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
+            if (tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
             if (cap < 8) cap = 8;
             if (grid > cap) grid = cap;
         }
@@ -558,11 +669,45 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
     return launch_chunks<P, DAG, NR>(chunks, d, g, apbc, persistent, cfg, st);
 }
 
+// Link-stationary launch: all right-hand sides of all batches, in groups of
+// kMaxStationaryRhs, one work-group per T-sweep tile of kStationaryBlock sites.
+template <int P, bool DAG>
+static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g,
+                                    int apbc, hipStream_t st) {
+    const size_t rb = field_rhs_bytes(P, g.V);
+    std::vector<std::pair<const void *, void *>> rhs;
+    for (int b = 0; b < nbatch; b++)
+        for (int r = 0; r < batches[b].nrhs; r++)
+            rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
+                             static_cast<char *>(batches[b].out) + r * rb);
+    const TileMap m = make_tilemap(g, kOrderTSweep, kStationaryBlock, 1);
+    for (size_t r0 = 0; r0 < rhs.size(); r0 += kMaxStationaryRhs) {
+        RhsTable tab;
+        tab.n = (int)std::min<size_t>(kMaxStationaryRhs, rhs.size() - r0);
+        for (int i = 0; i < kMaxStationaryRhs; i++) {
+            const size_t k = r0 + std::min(i, tab.n - 1);
+            tab.in[i] = rhs[k].first;
+            tab.out[i] = rhs[k].second;
+        }
+        hipLaunchKernelGGL((dslash_stationary_kernel<P, DAG>), dim3((unsigned)m.nslots), dim3(kStationaryBlock), 0, st,
+                           tab, d, g, m, apbc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <int P, bool DAG>
 static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g, int apbc,
                            bool persistent, LaunchCfg cfg, hipStream_t st) {
     int total = 0;
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
+    if (cfg.order == kOrderStationary) {
+        if constexpr (P != WDIRAC_F64) {
+            if (d.rows == 2) return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, st);
+        }
+        cfg.order = kOrderTSweep;  // FP64 or full links: the register-blocked site kernel
+    }
     if (total == 1) cfg.nr = 1;
     if (is_column_order(cfg.order) && P == WDIRAC_F64 && cfg.nr > 2) cfg.nr = 2;  // register budget
     if (cfg.nr >= 4) return launch_nr<P, DAG, 4>(batches, nbatch, d, g, apbc, persistent, cfg, st);

@@ -51,7 +51,7 @@ void load_cache_locked() {
         double us;
         if (sscanf(line, "{\"key\": \"%255[^\"]\", \"order\": %d, \"block\": %d, \"tchunk\": %d, \"nr\": %d, \"us\": %lf",
                    key, &c.order, &c.block, &c.tchunk, &c.nr, &us) == 6) {
-            if (c.order >= 0 && c.order <= 4 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
+            if (c.order >= 0 && c.order <= 5 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
                 c.tchunk >= 1 && (c.nr == 1 || c.nr == 2 || c.nr == 4))
                 g_table[key] = c;
         }
@@ -93,6 +93,7 @@ extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_ou
     int rc = WDIRAC_OK;
     std::vector<LaunchCfg> cands;
     const int nrs[3] = {1, 2, 4};
+    if (prec != WDIRAC_F64 && op->link_rows == 2 && nrhs > 1) cands.push_back({kOrderStationary, kStationaryBlock, 1, 1});
     for (int order : {2, 3, 4})
         for (int block : {128, 256})
             for (int tchunk : {2, 4, 8}) {

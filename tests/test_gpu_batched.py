@@ -59,7 +59,7 @@ def test_persistent_batched_launch(prec, restore_tuning):
     op = DiracOp(dims, U, -0.35, 1.0)
     nat = op.pack(to_dev(psi), prec)
     rb = op.field_bytes(prec, 1)
-    for pb in (8, 64, 4096):
+    for pb in (0, 8, 64, 4096):
         tune_set("persistent_blocks", pb)
         outs, batches, r0 = [], [], 0
         for n in sizes:
@@ -151,6 +151,40 @@ def test_patch_order_equals_column_order(block, prec, restore_tuning):
     want = oracle.dirac_apply(dims, U, psi, -0.3, 1.0, antiperiodic_t=True, dagger=True)
     for r in range(3):
         assert rel_l2(got[r], want[r]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s", "f64"])
+@pytest.mark.parametrize("compress", [True, False])
+def test_stationary_order_equals_site_kernel(prec, compress, restore_tuning):
+    """Tile order 5 (links and clover kept on chip for every right-hand side
+    of the launch) runs the site kernel's arithmetic, so results agree bit for
+    bit; 70 right-hand sides in uneven batches need two launches, the lattice
+    leaves a ragged last tile.  FP64 and full links fall back to order 2."""
+    dims = (5, 3, 7, 4)
+    sizes = [1, 24, 45]
+    n = sum(sizes)
+    U, psi = fields(dims, 47, nrhs=n)
+    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_links=compress)
+    nat = op.pack(to_dev(psi), prec)
+    rb = op.field_bytes(prec, 1)
+    tune_set("nr_" + prec, 1)
+    tune_set("block", 128)
+    for dag in (False, True):
+        tune_set("order", 2)
+        ref = op.empty(prec, n).zero_()
+        op.apply_native(ref, nat, n, prec, dag)
+        tune_set("order", 5)
+        out = op.empty(prec, n).zero_()
+        batches, r0 = [], 0
+        for k in sizes:
+            batches.append((out[r0 * rb:(r0 + k) * rb], nat[r0 * rb:(r0 + k) * rb], k))
+            r0 += k
+        op.apply_batched(batches, prec, dagger=dag)
+        assert torch.equal(out, ref), dag
+    got = op.unpack(out, prec, n).cpu().numpy()
+    for r in (0, 1, 37, n - 1):
+        want = oracle.dirac_apply(dims, U, psi[r], -0.3, 1.0, antiperiodic_t=True, dagger=True)
+        assert rel_l2(got[r], want) < TOL[prec]
 
 
 def test_batched_argument_errors(restore_tuning):
