@@ -41,9 +41,12 @@ FLOP_HOP = 1320                # flop/site, hopping term (the paper's convention
 FLOP_FULL = 1872               # flop/site, with clover (504) and combine (48)
 # algorithmic bytes per site and right-hand side: in + out spinor + links + clover;
 # the links are stored as two rows (4 directions x 6 complex per site; the
-# third row is rebuilt in the kernel)
-BYTES_SITE = {"f64": 192 + 192 + 384 + 576, "f32": 96 + 96 + 192 + 288, "f16s": 52 + 52 + 96 + 144}
+# third row is rebuilt in the kernel) and each clover chirality block as its
+# spin-diagonal difference and off-diagonal 3x3 blocks (27 reals + 1 pad)
 LINK_BYTES = {"f64": 384, "f32": 192, "f16s": 96}
+CLOVER_BYTES = {"f64": 448, "f32": 224, "f16s": 112}
+SPINOR_BYTES = {"f64": 192, "f32": 96, "f16s": 52}
+BYTES_SITE = {p: 2 * SPINOR_BYTES[p] + LINK_BYTES[p] + CLOVER_BYTES[p] for p in LINK_BYTES}
 KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/csrc/dslash.h",
                   "paper_2407_00041_amd/csrc/tune.hip",
                   "paper_2407_00041_amd/csrc/spinor_io.h", "paper_2407_00041_amd/csrc/common.h"]
@@ -131,7 +134,8 @@ def batched_run(torch, op, dims, stream, steps):
     tuned = {"fixed": True} if TUNE_FIXED else op.autotune("f32", n)
     ms = time_launches(torch, lambda: op.apply_batched(batches, "f32", stream=stream), steps, 3, stream)
     res = {"batches": sizes, "prec": "f32", "ms_per_launch": ms, "rhs_applies_per_s": n * 1000.0 / ms,
-           "alg_GBps": (LINK_BYTES["f32"] + 288 + 192 * n) * op.V / (ms * 1e-3) / 1e9, "launch": tuned}
+           "alg_GBps": (LINK_BYTES["f32"] + CLOVER_BYTES["f32"] + 192 * n) * op.V / (ms * 1e-3) / 1e9,
+           "launch": tuned}
     del outs, batches, nat
     torch.cuda.empty_cache()
     return res
@@ -256,7 +260,8 @@ def main():
     U = Ud.cpu().numpy()
     del Ud
     log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
-    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"), compress_links=True)
+    op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"), compress_links=True,
+                    compress_clover=True)
     stream = torch.cuda.current_stream()
     inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
     out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}
@@ -323,7 +328,8 @@ def main():
         "config": {"workload": f"Wilson-clover D apply, {dims[1]}^3x{dims[0]} (T,Z,Y,X = {list(dims)}), "
                                f"FP64, 1 RHS, csw={a.csw}, m0={a.m0}, periodic",
                    "lattice": list(dims), "sites": V, "nrhs": 1, "parallelism": "single GPU",
-                   "link_storage": "two rows per SU(3) link (third rebuilt in the kernel)"},
+                   "link_storage": "two rows per SU(3) link (third rebuilt in the kernel)",
+                   "clover_storage": "per chirality block (A_00 - A_11)/2 and A_01 (27 of 36 reals)"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
                      "kernel": ("wd::dslash_column_kernel<0, false, 1>" if tuned["f64"]["order"] == 3

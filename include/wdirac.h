@@ -80,6 +80,9 @@ extern "C" {
 #define WDIRAC_WITH_F16 4u       /* also materialise FP16 links + clover    */
 #define WDIRAC_COMPRESS_LINKS 8u /* store two rows per link; the third is
                                     rebuilt as conj(row0 x row1) (SU(3) only) */
+#define WDIRAC_COMPRESS_CLOVER 16u /* store each chirality block of C as its
+                                    spin-diagonal difference and off-diagonal
+                                    3x3 blocks (27 of 36 reals) */
 
 typedef struct dirac_op dirac_op;
 
@@ -102,10 +105,20 @@ const char *dirac_version(void);
  *            WDIRAC_COMPRESS_LINKS keeps 2 of the 3 rows of every link (the
  *            third row of an SU(3) matrix is conj(row0 x row1)); it needs
  *            |U U^H - 1| and |det U - 1| <= 1e-12 for every link.
+ *            WDIRAC_COMPRESS_CLOVER uses that each 6x6 chirality block of
+ *            the clover term of Eq. (1.11) is sum_k sigma_k (x) G_k (Pauli
+ *            matrices in the block's two spins, since gamma_mu gamma_nu is
+ *            block diagonal with traceless 2x2 blocks for mu != nu): its two
+ *            spin-diagonal 3x3 blocks are opposite, so A's block is stored as
+ *            H = (A_00 - A_11)/2 (Hermitian, 9 reals) and A_01 (18 reals),
+ *            with A_00 = (4+m0) + H, A_11 = (4+m0) - H.  It needs
+ *            |C_00 + C_11| <= 1e-10 max(1, |C|) at every site (always true for
+ *            a clover built from the links).
  * Synchronous.  Copies everything into device memory owned by the handle;
  * the caller may free its arrays on return.  Errors: EINVAL (null pointer,
- * dims < 2, non-SU(3) links with WDIRAC_COMPRESS_LINKS), ENOMEM, EHIP,
- * EUNSUPPORTED (no HIP device).
+ * dims < 2, non-SU(3) links with WDIRAC_COMPRESS_LINKS, a clover without the
+ * structure above with WDIRAC_COMPRESS_CLOVER), ENOMEM, EHIP, EUNSUPPORTED
+ * (no HIP device).
  */
 int dirac_create(dirac_op **op, const int dims[4], const double *links, const double *clover,
                  double m0, double csw, unsigned flags);

@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ANTIPERIODIC_T, COMPRESS_LINKS, EUNSUPPORTED, F16S, F32, F64, FGMRES_F64,  # noqa: F401
+from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
+                   FGMRES_F64,
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
 PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
@@ -46,12 +47,14 @@ class DiracOp:
 
     dims = (nT, nZ, nY, nX); links canonical [V, 4, 3, 3] complex128 (host or
     device tensor / ndarray); clover None (build from links when csw != 0) or
-    the packed unit-c_sw term [V, 42].
+    the packed unit-c_sw term [V, 42].  compress_links: two stored rows per
+    SU(3) link; compress_clover: each clover chirality block stored as its
+    spin-diagonal difference and off-diagonal 3x3 blocks (27 of 36 reals).
     """
 
     def __init__(self, dims, links, m0: float, csw: float = 0.0, clover=None,
                  antiperiodic_t: bool = False, precisions=("f64", "f32", "f16s"),
-                 compress_links: bool = False):
+                 compress_links: bool = False, compress_clover: bool = False):
         self.lib = _lib.load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(np.prod(self.dims))
@@ -61,6 +64,9 @@ class DiracOp:
         if compress_links:
             flags |= COMPRESS_LINKS
         self.compress_links = bool(compress_links)
+        if compress_clover:
+            flags |= COMPRESS_CLOVER
+        self.compress_clover = bool(compress_clover)
         if "f32" in precisions:
             flags |= WITH_F32
         if "f16s" in precisions:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libwdirac.so")
 
 F64, F32, F16S = 0, 1, 2
-ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS = 1, 2, 4, 8
+ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER = 1, 2, 4, 8, 16
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV = 0, -1, -2, -3, -4, 1
 FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S = 0, 1, 2
 FGMRES_HIST_MAX = 4096

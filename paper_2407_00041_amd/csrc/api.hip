@@ -13,9 +13,11 @@ hipError_t clover_build_launch(double *out, const double *links, const Geom &g, 
 hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const double *clover_can_dev,
                               hipStream_t st);
 hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStream_t st);
+hipError_t clover_structure_deviation(const double *clover_can_dev, int V, double *out, hipStream_t st);
 
 static thread_local std::string g_err;
 constexpr double kSu3Tol = 1e-12;  // largest |U U^H - 1|, |det U - 1| accepted for two-row storage
+constexpr double kCloverTol = 1e-10;  // largest |C_00 + C_11| / max(1, |C|) accepted for compact clover storage
 
 void set_error(const std::string &msg) { g_err = msg; }
 
@@ -107,7 +109,9 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     op->flags = flags;
     (void)hipGetDevice(&op->device);
     op->link_rows = (flags & WDIRAC_COMPRESS_LINKS) ? 2 : 3;
+    op->clover_compact = (flags & WDIRAC_COMPRESS_CLOVER) != 0;
     const size_t lr = (size_t)op->link_rows * 3;  // stored complex entries per link
+    const size_t cr = op->clover_compact ? 56 : 72;  // stored reals per site of the clover
     const size_t nl = (size_t)V * 36 * 16, nc = (size_t)V * 42 * 16;
     double *lc = nullptr, *cc = nullptr;
     int rc = WDIRAC_OK;
@@ -121,13 +125,13 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     };
     hipStream_t st = nullptr;
     do {
-        if (!alloc((void **)&op->links64, (size_t)V * 4 * lr * 16) || !alloc((void **)&op->clover64, (size_t)V * 36 * 16))
+        if (!alloc((void **)&op->links64, (size_t)V * 4 * lr * 16) || !alloc((void **)&op->clover64, (size_t)V * cr * 8))
             break;
         if ((flags & WDIRAC_WITH_F32) && (!alloc((void **)&op->links32, (size_t)V * 4 * lr * 8) ||
-                                          !alloc((void **)&op->clover32, (size_t)V * 72 * 4)))
+                                          !alloc((void **)&op->clover32, (size_t)V * cr * 4)))
             break;
         if ((flags & WDIRAC_WITH_F16) && (!alloc((void **)&op->links16, (size_t)V * 4 * lr * 4) ||
-                                          !alloc((void **)&op->clover16, (size_t)V * 72 * 2)))
+                                          !alloc((void **)&op->clover16, (size_t)V * cr * 2)))
             break;
         if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
         lc = op->links_canon;
@@ -161,6 +165,18 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
         } else if (hipMemsetAsync(cc, 0, nc, st) != hipSuccess) {
             rc = fail(WDIRAC_EHIP, "memset failed");
             break;
+        }
+        if (op->clover_compact) {
+            double dev = 0;
+            if (clover_structure_deviation(cc, (int)V, &dev, st) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "clover structure check failed to run");
+                break;
+            }
+            if (!(dev <= kCloverTol)) {
+                rc = fail(WDIRAC_EINVAL, "compact clover storage needs C_00 + C_11 = 0 in each chirality block; "
+                                         "largest relative deviation " + std::to_string(dev) + " exceeds 1e-10");
+                break;
+            }
         }
         if (operator_to_native(op, lc, cc, st) != hipSuccess) {
             rc = fail(WDIRAC_EHIP, "layout conversion launch failed");

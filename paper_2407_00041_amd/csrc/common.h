@@ -87,8 +87,11 @@ inline size_t field_rhs_bytes(int prec, long long V) {
 struct OpData {
     const void *links = nullptr;   // rows = 3: F64 [4][9][V] double2, F32 float2, F16 half2;
                                    // rows = 2: F64 [4][6][V] double2, F32 [4][3][V] float4, F16 [4][3][V] 4 x half
-    const void *clover = nullptr;  // F64: [2][18][V] double2; F32: [2][9][V] float4; F16: [2][9][V] 4 x half
+    const void *clover = nullptr;  // packed: F64 [2][18][V] double2; F32 [2][9][V] float4; F16 [2][9][V] 4 x half
+                                   // compact: F64 [2][14][V] double2; F32 [2][7][V] float4; F16 [2][7][V] 4 x half
     int rows = 3;                  // link rows stored (2: the third is conj(row0 x row1))
+    int clover_compact = 0;        // 1: compact clover blocks (H, A_01) with the diagonal constant below
+    double diag = 0;               // 4 + m0 (compact clover only)
 };
 
 // wavefront-level constants
@@ -118,9 +121,12 @@ struct dirac_op {
     void *links16 = nullptr, *clover16 = nullptr;
     double *links_canon = nullptr;  // canonical FP64 links (force kernels)
     int link_rows = 3;
+    bool clover_compact = false;
     wd::OpData data(int prec) const {
         wd::OpData d;
         d.rows = link_rows;
+        d.clover_compact = clover_compact ? 1 : 0;
+        d.diag = 4.0 + m0;
         if (prec == WDIRAC_F64) { d.links = links64; d.clover = clover64; }
         if (prec == WDIRAC_F32) { d.links = links32; d.clover = clover32; }
         if (prec == WDIRAC_F16S) { d.links = links16; d.clover = clover16; }

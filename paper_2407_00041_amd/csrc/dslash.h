@@ -61,8 +61,9 @@ struct LaunchCfg {
 };
 
 // Autotuned configurations, keyed by lattice, precision, right-hand-side
-// bucket and link format (see tune.hip); returns false when none is stored.
-bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, LaunchCfg &out);
+// bucket, link format and clover format (see tune.hip); returns false when
+// none is stored.
+bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, int compact, LaunchCfg &out);
 
 // Process-wide launch parameters (set through dirac_tune_set).
 struct Tuning {

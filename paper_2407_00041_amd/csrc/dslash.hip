@@ -95,6 +95,43 @@ __device__ __forceinline__ void clover_block(const T d[6], const cx<T> u[15], co
         }
 }
 
+// y = A_blk x for a compact chirality block: A_00 = dg + H, A_11 = dg - H, A_01
+// (row-major), A_10 = A_01^H; r = (h00, h11, h22, h01, h02, h12 as re/im,
+// A_01 as re/im, pad)
+template <typename T>
+__device__ __forceinline__ void clover_block_compact(T dg, const T r[28], const cx<T> x[6], cx<T> y[6]) {
+    const cx<T> u01 = {r[3], r[4]}, u02 = {r[5], r[6]}, u12 = {r[7], r[8]};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        y[c] = (dg + r[c]) * x[c];
+        y[3 + c] = (dg - r[c]) * x[3 + c];
+    }
+    // off-diagonal entries of +H (spin 0) and -H (spin 1)
+    cx<T> t0 = cmul(u01, x[1]), t1 = cjmul(u01, x[0]), t2 = cjmul(u02, x[0]);
+    t0 = cfma(t0, u02, x[2]);
+    t1 = cfma(t1, u12, x[2]);
+    t2 = cjfma(t2, u12, x[1]);
+    y[0] = y[0] + t0;
+    y[1] = y[1] + t1;
+    y[2] = y[2] + t2;
+    cx<T> b0 = cmul(u01, x[4]), b1 = cjmul(u01, x[3]), b2 = cjmul(u02, x[3]);
+    b0 = cfma(b0, u02, x[5]);
+    b1 = cfma(b1, u12, x[5]);
+    b2 = cjfma(b2, u12, x[4]);
+    y[3] = y[3] - b0;
+    y[4] = y[4] - b1;
+    y[5] = y[5] - b2;
+    // spin-off-diagonal block A_01 and its adjoint
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const cx<T> m = {r[9 + 2 * (3 * i + j)], r[10 + 2 * (3 * i + j)]};
+            y[i] = cfma(y[i], m, x[3 + j]);
+            y[3 + j] = cjfma(y[3 + j], m, x[i]);
+        }
+}
+
 struct Nbr {
     int fwd[4], bwd[4];
     bool fwd_wrapT, bwd_wrapT;
@@ -175,15 +212,28 @@ __device__ __forceinline__ void site_apply(const Chunk<NR> &ch, const OpData &d,
     cx<T> acc[NR][12];
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-        T dd[6];
-        cx<T> uu[15];
-        Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+        if (d.clover_compact) {
+            T cr[28];
+            Store<P>::load_clover_compact(d.clover, V, b, s, cr);
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            if (r < ch.nr) {
-                cx<T> p[6];
-                Store<P>::load_half(ch.in[r], V, s, b, p);
-                clover_block(dd, uu, p, &acc[r][6 * b]);
+            for (int r = 0; r < NR; r++) {
+                if (r < ch.nr) {
+                    cx<T> p[6];
+                    Store<P>::load_half(ch.in[r], V, s, b, p);
+                    clover_block_compact((T)d.diag, cr, p, &acc[r][6 * b]);
+                }
+            }
+        } else {
+            T dd[6];
+            cx<T> uu[15];
+            Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r < ch.nr) {
+                    cx<T> p[6];
+                    Store<P>::load_half(ch.in[r], V, s, b, p);
+                    clover_block(dd, uu, p, &acc[r][6 * b]);
+                }
             }
         }
     }
@@ -251,12 +301,20 @@ __device__ __forceinline__ void column_sweep(const Chunk<NR> &ch, const OpData &
         // self coupling
 #pragma unroll
         for (int b = 0; b < 2; b++) {
-            T dd[6];
-            cx<T> uu[15];
-            Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+            if (d.clover_compact) {
+                T cr[28];
+                Store<P>::load_clover_compact(d.clover, V, b, s, cr);
 #pragma unroll
-            for (int r = 0; r < NR; r++)
-                if (r < ch.nr) clover_block(dd, uu, &self[r][6 * b], &acc[r][6 * b]);
+                for (int r = 0; r < NR; r++)
+                    if (r < ch.nr) clover_block_compact((T)d.diag, cr, &self[r][6 * b], &acc[r][6 * b]);
+            } else {
+                T dd[6];
+                cx<T> uu[15];
+                Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    if (r < ch.nr) clover_block(dd, uu, &self[r][6 * b], &acc[r][6 * b]);
+            }
         }
         // backward T hop (carried), then the one for site t+1
         const bool last = (t == nT - 1);
@@ -457,17 +515,26 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
     if (s >= hi) return;
     const int V = g.V;
     const int tid = threadIdx.x;
+    const bool compact = d.clover_compact != 0;
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-        T dd[6];
-        cx<T> uu[15];
-        Store<P>::load_clover(d.clover, V, b, s, dd, uu);
-        lds[9 * b + 0][tid] = make_float4(dd[0], dd[1], dd[2], dd[3]);
-        lds[9 * b + 1][tid] = make_float4(dd[4], dd[5], uu[0].r, uu[0].i);
+        if (compact) {
+            T cr[28];
+            Store<P>::load_clover_compact(d.clover, V, b, s, cr);
 #pragma unroll
-        for (int k = 0; k < 7; k++)
-            lds[9 * b + 2 + k][tid] = make_float4(uu[1 + 2 * k].r, uu[1 + 2 * k].i, uu[2 + 2 * k].r, uu[2 + 2 * k].i);
+            for (int k = 0; k < 7; k++) lds[7 * b + k][tid] = make_float4(cr[4 * k], cr[4 * k + 1], cr[4 * k + 2], cr[4 * k + 3]);
+        } else {
+            T dd[6];
+            cx<T> uu[15];
+            Store<P>::load_clover(d.clover, V, b, s, dd, uu);
+            lds[9 * b + 0][tid] = make_float4(dd[0], dd[1], dd[2], dd[3]);
+            lds[9 * b + 1][tid] = make_float4(dd[4], dd[5], uu[0].r, uu[0].i);
+#pragma unroll
+            for (int k = 0; k < 7; k++)
+                lds[9 * b + 2 + k][tid] = make_float4(uu[1 + 2 * k].r, uu[1 + 2 * k].i, uu[2 + 2 * k].r, uu[2 + 2 * k].i);
+        }
     }
+    const T dg = (T)d.diag;
     const Nbr nb = neighbours(g, s);
     cx<T> Lf[4][6], Lb[4][6];
 #pragma unroll
@@ -490,18 +557,28 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
             Store<P>::load_spinor(in, V, s, self);
 #pragma unroll
             for (int b = 0; b < 2; b++) {
-                T dd[6];
-                cx<T> uu[15];
-                const float4 a0 = lds[9 * b][tid], a1 = lds[9 * b + 1][tid];
-                dd[0] = a0.x; dd[1] = a0.y; dd[2] = a0.z; dd[3] = a0.w; dd[4] = a1.x; dd[5] = a1.y;
-                uu[0] = {a1.z, a1.w};
+                if (compact) {
+                    T cr[28];
 #pragma unroll
-                for (int k = 0; k < 7; k++) {
-                    const float4 q = lds[9 * b + 2 + k][tid];
-                    uu[1 + 2 * k] = {q.x, q.y};
-                    uu[2 + 2 * k] = {q.z, q.w};
+                    for (int k = 0; k < 7; k++) {
+                        const float4 q = lds[7 * b + k][tid];
+                        cr[4 * k] = q.x; cr[4 * k + 1] = q.y; cr[4 * k + 2] = q.z; cr[4 * k + 3] = q.w;
+                    }
+                    clover_block_compact(dg, cr, &self[6 * b], &acc[6 * b]);
+                } else {
+                    T dd[6];
+                    cx<T> uu[15];
+                    const float4 a0 = lds[9 * b][tid], a1 = lds[9 * b + 1][tid];
+                    dd[0] = a0.x; dd[1] = a0.y; dd[2] = a0.z; dd[3] = a0.w; dd[4] = a1.x; dd[5] = a1.y;
+                    uu[0] = {a1.z, a1.w};
+#pragma unroll
+                    for (int k = 0; k < 7; k++) {
+                        const float4 q = lds[9 * b + 2 + k][tid];
+                        uu[1 + 2 * k] = {q.x, q.y};
+                        uu[2 + 2 * k] = {q.z, q.w};
+                    }
+                    clover_block(dd, uu, &self[6 * b], &acc[6 * b]);
                 }
-                clover_block(dd, uu, &self[6 * b], &acc[6 * b]);
             }
         }
         hop_fence(1);
@@ -740,7 +817,7 @@ hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int pre
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
     const Tuning &tu = g_tuning;
     LaunchCfg cfg{tu.order, tu.block, tu.tchunk, (prec >= 0 && prec < 3) ? tu.nr[prec] : 1};
-    if (!tu.explicit_launch) tuned_cfg(g, prec, total, d.rows, cfg);
+    if (!tu.explicit_launch) tuned_cfg(g, prec, total, d.rows, d.clover_compact, cfg);
     return dslash_launch_cfg(batches, nbatch, prec, dagger, d, g, apbc, persistent, cfg, st);
 }
 

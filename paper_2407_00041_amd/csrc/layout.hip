@@ -201,6 +201,105 @@ __global__ __launch_bounds__(256) void clover_to_native(double2 *__restrict__ na
     }
 }
 
+// canonical unit clover [V][42] c128 -> compact native FP64 blocks of csw C(x):
+// [2 blocks][14][V] double2 holding 28 reals per block: H = csw (C_00 - C_11)/2
+// (h00, h11, h22, then h01, h02, h12 as re, im), A_01 = csw C_01 (9 complex,
+// row-major), one zero pad.  Block-local index 3 s + c (s = spin within the
+// block); the packed upper entries are in row-major pair order.
+__global__ __launch_bounds__(256) void clover_to_native_compact(double2 *__restrict__ nat,
+                                                                const double2 *__restrict__ can, int V, double csw) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *c = can + (size_t)42 * s;
+    // index of the packed strict-upper entry (i, j), i < j < 6
+    auto up = [](int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i - 1); };
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        const double2 *cb = c + 21 * b;
+        double r[28];
+        for (int k = 0; k < 3; k++) r[k] = 0.5 * csw * (cb[k].x - cb[3 + k].x);
+        const int hp[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int k = 0; k < 3; k++) {
+            const double2 a = cb[6 + up(hp[k][0], hp[k][1])], d = cb[6 + up(3 + hp[k][0], 3 + hp[k][1])];
+            r[3 + 2 * k] = 0.5 * csw * (a.x - d.x);
+            r[4 + 2 * k] = 0.5 * csw * (a.y - d.y);
+        }
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                const double2 m = cb[6 + up(i, 3 + j)];
+                r[9 + 2 * (3 * i + j)] = csw * m.x;
+                r[10 + 2 * (3 * i + j)] = csw * m.y;
+            }
+        r[27] = 0.0;
+        double2 *o = nat + (size_t)b * 14 * V;
+        for (int q = 0; q < 14; q++) o[(size_t)q * V + s] = make_double2(r[2 * q], r[2 * q + 1]);
+    }
+}
+
+// largest |C_00 + C_11| / max(1, max|C|) over sites and blocks (the compact
+// clover's structure condition), folded into *worst like su3_check
+__global__ __launch_bounds__(256) void clover_structure_check(const double2 *__restrict__ can, int V,
+                                                              unsigned long long *__restrict__ worst) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *c = can + (size_t)42 * s;
+    auto up = [](int i, int j) { return i * 5 - i * (i - 1) / 2 + (j - i - 1); };
+    double dev = 0.0, big = 1.0;
+    for (int k = 0; k < 42; k++) big = fmax(big, fmax(fabs(c[k].x), fabs(c[k].y)));
+    for (int b = 0; b < 2; b++) {
+        const double2 *cb = c + 21 * b;
+        for (int k = 0; k < 3; k++) dev = fmax(dev, fabs(cb[k].x + cb[3 + k].x));
+        const int hp[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int k = 0; k < 3; k++) {
+            const double2 a = cb[6 + up(hp[k][0], hp[k][1])], d = cb[6 + up(3 + hp[k][0], 3 + hp[k][1])];
+            dev = fmax(dev, fmax(fabs(a.x + d.x), fabs(a.y + d.y)));
+        }
+    }
+    dev /= big;
+    if (!(dev == dev)) dev = 1e300;  // NaN
+    atomicMax(worst, (unsigned long long)__double_as_longlong(dev));
+}
+
+hipError_t clover_structure_deviation(const double *clover_can_dev, int V, double *out, hipStream_t st) {
+    unsigned long long *w = nullptr;
+    hipError_t e = hipMalloc(&w, sizeof(*w));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(w, 0, sizeof(*w), st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(clover_structure_check, dim3((V + 255) / 256), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(clover_can_dev), V, w);
+        e = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, w, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(w);
+    double d;
+    memcpy(&d, &h, sizeof(d));
+    *out = d;
+    return e;
+}
+
+// compact FP64 clover [2][14][V] double2 -> [2][7][V] float4 / 4 x half (same real order)
+__global__ __launch_bounds__(256) void clover_narrow_compact(float4 *__restrict__ o32, half4 *__restrict__ o16,
+                                                             const double2 *__restrict__ nat, int V) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            double2 a = nat[(size_t)(b * 14 + 2 * q) * V + s];
+            double2 c = nat[(size_t)(b * 14 + 2 * q + 1) * V + s];
+            if (o32) o32[(size_t)(b * 7 + q) * V + s] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+            if (o16) {
+                half4 h;
+                h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)c.x; h[3] = (_Float16)c.y;
+                o16[(size_t)(b * 7 + q) * V + s] = h;
+            }
+        }
+}
+
 // native FP64 links (two stored rows) -> FP32 [4][3][V] float4 / FP16 [4][3][V] 4 x half
 __global__ __launch_bounds__(256) void links_narrow2(float4 *__restrict__ o32, half4 *__restrict__ o16,
                                                      const double2 *__restrict__ nat, int V) {
@@ -259,8 +358,12 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
     dim3 grid((V + 255) / 256);
     hipLaunchKernelGGL(links_to_native, grid, dim3(256), 0, st, (double2 *)op->links64,
                        (const double2 *)links_can_dev, V, op->link_rows);
-    hipLaunchKernelGGL(clover_to_native, grid, dim3(256), 0, st, (double2 *)op->clover64,
-                       (const double2 *)clover_can_dev, V, 4.0 + op->m0, op->csw);
+    if (op->clover_compact)
+        hipLaunchKernelGGL(clover_to_native_compact, grid, dim3(256), 0, st, (double2 *)op->clover64,
+                           (const double2 *)clover_can_dev, V, op->csw);
+    else
+        hipLaunchKernelGGL(clover_to_native, grid, dim3(256), 0, st, (double2 *)op->clover64,
+                           (const double2 *)clover_can_dev, V, 4.0 + op->m0, op->csw);
     if (op->links32 || op->links16) {
         if (op->link_rows == 2) {
             hipLaunchKernelGGL(links_narrow2, grid, dim3(256), 0, st, (float4 *)op->links32, (half4 *)op->links16,
@@ -270,8 +373,12 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
             hipLaunchKernelGGL(links_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                                (float2 *)op->links32, (half2v *)op->links16, (const double2 *)op->links64, n);
         }
-        hipLaunchKernelGGL(clover_narrow, grid, dim3(256), 0, st, (float4 *)op->clover32, (half4 *)op->clover16,
-                           (const double2 *)op->clover64, V);
+        if (op->clover_compact)
+            hipLaunchKernelGGL(clover_narrow_compact, grid, dim3(256), 0, st, (float4 *)op->clover32,
+                               (half4 *)op->clover16, (const double2 *)op->clover64, V);
+        else
+            hipLaunchKernelGGL(clover_narrow, grid, dim3(256), 0, st, (float4 *)op->clover32, (half4 *)op->clover16,
+                               (const double2 *)op->clover64, V);
     }
     return hipGetLastError();
 }

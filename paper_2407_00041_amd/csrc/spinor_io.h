@@ -100,6 +100,16 @@ template <> struct Store<WDIRAC_F64> {
             u[e] = {a.x, a.y};
         }
     }
+    // compact block b: 28 reals (H diagonal, H upper re/im, A_01 re/im row-major, pad)
+    static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
+        const d2v *p = static_cast<const d2v *>(base) + (size_t)b * 14 * V;
+#pragma unroll
+        for (int q = 0; q < 14; q++) {
+            d2v a = ld_once(&p[(size_t)q * V + s]);
+            r[2 * q] = a.x;
+            r[2 * q + 1] = a.y;
+        }
+    }
 };
 
 // ---------------------------------------------------------------- FP32
@@ -164,6 +174,14 @@ template <> struct Store<WDIRAC_F32> {
         for (int k = 0; k < 6; k++) d[k] = r[k];
 #pragma unroll
         for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    }
+    static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
+        const f4v *p = static_cast<const f4v *>(base) + (size_t)b * 7 * V;
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            f4v a = ld_once(&p[(size_t)q * V + s]);
+            r[4 * q] = a.x; r[4 * q + 1] = a.y; r[4 * q + 2] = a.z; r[4 * q + 3] = a.w;
+        }
     }
 };
 
@@ -241,6 +259,14 @@ template <> struct Store<WDIRAC_F16S> {
         for (int k = 0; k < 6; k++) d[k] = r[k];
 #pragma unroll
         for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    }
+    static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
+        const half4 *p = static_cast<const half4 *>(base) + (size_t)b * 7 * V;
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            half4 a = ld_once(&p[(size_t)q * V + s]);
+            r[4 * q] = (float)a[0]; r[4 * q + 1] = (float)a[1]; r[4 * q + 2] = (float)a[2]; r[4 * q + 3] = (float)a[3];
+        }
     }
 };
 

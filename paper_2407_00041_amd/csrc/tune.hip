@@ -4,8 +4,8 @@
 // a small set of candidate configurations (tile order, work-group size,
 // T-chunk of the column sweep, register block) with HIP events on temporary
 // buffers and keeps the fastest.  Choices are stored per (lattice extents,
-// precision, right-hand-side bucket, link format) and used by every later
-// launch with that key; they can be appended to a JSON-lines cache file
+// precision, right-hand-side bucket, link format, clover format) and used by
+// every later launch with that key; they can be appended to a JSON-lines cache file
 // (environment variable WDIRAC_TUNE_CACHE) and are read back from it the first
 // time a key is looked up in a new process.
 #include <cstdio>
@@ -31,10 +31,10 @@ int bucket(int nrhs) {
     return b;  // 1 -> 0, 2 -> 1, 3..4 -> 2, 5..8 -> 3, ..., > 32 -> 6
 }
 
-std::string key_of(const Geom &g, int prec, int nrhs, int rows) {
+std::string key_of(const Geom &g, int prec, int nrhs, int rows, int compact) {
     char buf[128];
-    snprintf(buf, sizeof(buf), "gfx950|%dx%dx%dx%d|p%d|b%d|r%d", g.n[0], g.n[1], g.n[2], g.n[3], prec, bucket(nrhs),
-             rows);
+    snprintf(buf, sizeof(buf), "gfx950|%dx%dx%dx%d|p%d|b%d|r%d|c%d", g.n[0], g.n[1], g.n[2], g.n[3], prec,
+             bucket(nrhs), rows, compact);
     return buf;
 }
 
@@ -61,10 +61,10 @@ void load_cache_locked() {
 
 }  // namespace
 
-bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, LaunchCfg &out) {
+bool tuned_cfg(const Geom &g, int prec, int nrhs, int rows, int compact, LaunchCfg &out) {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache_locked();
-    auto it = g_table.find(key_of(g, prec, nrhs, rows));
+    auto it = g_table.find(key_of(g, prec, nrhs, rows, compact));
     if (it == g_table.end()) return false;
     out = it->second;
     return true;
@@ -142,7 +142,7 @@ extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_ou
     (void)hipFree(in);
     (void)hipFree(out);
     if (rc) return rc;
-    const std::string key = key_of(op->g, prec, nrhs, op->link_rows);
+    const std::string key = key_of(op->g, prec, nrhs, op->link_rows, op->clover_compact ? 1 : 0);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         load_cache_locked();

@@ -172,3 +172,43 @@ def test_two_row_links_reject_non_su3():
         DiracOp(dims, U, -0.3, 1.0, compress_links=True)
     assert e.value.code == -1
     DiracOp(dims, U, -0.3, 1.0)            # full storage accepts any links
+
+
+@pytest.mark.parametrize("dims,kind,m0,csw,ap", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("links2", [False, True])
+def test_compact_clover_matches_oracle(dims, kind, m0, csw, ap, prec, dagger, links2):
+    """Clover blocks stored as H = (A_00 - A_11)/2 and A_01 (with and without
+    two-row links)."""
+    need_gpu()
+    U, psi = fields(dims, 19, kind, nrhs=2)
+    op = DiracOp(dims, U, m0, csw, antiperiodic_t=ap, compress_links=links2, compress_clover=True)
+    got = op.apply(to_dev(psi), prec, dagger=dagger).cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, m0, csw, antiperiodic_t=ap, dagger=dagger)
+    for r in range(2):
+        assert rel_l2(got[r], want[r]) < TOL[prec], (r, rel_l2(got[r], want[r]))
+
+
+def test_compact_clover_given_and_rejected():
+    """A clover passed in is accepted in compact storage when each chirality
+    block has C_00 + C_11 = 0 (a per-site rescaling keeps that), and rejected
+    with EINVAL otherwise; full storage accepts any Hermitian term."""
+    need_gpu()
+    dims = (4, 4, 6, 2)
+    U, psi = fields(dims, 3)
+    C = oracle.clover_term(dims, U)
+    rng = np.random.default_rng(5)
+    C2 = C * (1 + 0.1 * rng.standard_normal(C.shape[0]))[:, None]
+    op = DiracOp(dims, U, -0.2, 1.3, clover=C2, compress_clover=True)
+    got = op.apply(to_dev(psi), "f64").cpu().numpy()
+    want = oracle.dirac_apply(dims, U, psi, -0.2, 1.3, clover=C2)
+    assert rel_l2(got, want) < 1e-13
+    C3 = C2.copy()
+    C3[5, 0] += 0.01                      # block +, spin 0, colour 0 diagonal: C_00 + C_11 != 0
+    with pytest.raises(WdiracError) as e:
+        DiracOp(dims, U, -0.2, 1.3, clover=C3, compress_clover=True)
+    assert e.value.code == -1
+    op = DiracOp(dims, U, -0.2, 1.3, clover=C3)
+    got = op.apply(to_dev(psi), "f64").cpu().numpy()
+    assert rel_l2(got, oracle.dirac_apply(dims, U, psi, -0.2, 1.3, clover=C3)) < 1e-13

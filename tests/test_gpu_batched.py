@@ -111,12 +111,14 @@ def test_tile_orders_and_blocks(order, block, restore_tuning):
 @pytest.mark.parametrize("tchunk", [1, 3, 8])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("dagger", [False, True])
-def test_column_sweep_order(tchunk, prec, dagger, restore_tuning):
+@pytest.mark.parametrize("compact", [False, True])
+def test_column_sweep_order(tchunk, prec, dagger, compact, restore_tuning):
     """Tile order 3 (lanes walk columns along T with register-carried T
-    neighbours): ragged T-chunks, anti-periodic T, several right-hand sides."""
+    neighbours): ragged T-chunks, anti-periodic T, several right-hand sides,
+    packed and compact clover storage."""
     dims = (5, 3, 7, 4)
     U, psi = fields(dims, 31, nrhs=3)
-    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True)
+    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_clover=compact)
     tune_set("order", 3)
     tune_set("tchunk", tchunk)
     got = op.apply(to_dev(psi), prec, dagger=dagger).cpu().numpy()
@@ -155,7 +157,8 @@ def test_patch_order_equals_column_order(block, prec, restore_tuning):
 
 @pytest.mark.parametrize("prec", ["f32", "f16s", "f64"])
 @pytest.mark.parametrize("compress", [True, False])
-def test_stationary_order_equals_site_kernel(prec, compress, restore_tuning):
+@pytest.mark.parametrize("compact", [False, True])
+def test_stationary_order_equals_site_kernel(prec, compress, compact, restore_tuning):
     """Tile order 5 (links and clover kept on chip for every right-hand side
     of the launch) runs the site kernel's arithmetic, so results agree bit for
     bit; 70 right-hand sides in uneven batches need two launches, the lattice
@@ -164,7 +167,7 @@ def test_stationary_order_equals_site_kernel(prec, compress, restore_tuning):
     sizes = [1, 24, 45]
     n = sum(sizes)
     U, psi = fields(dims, 47, nrhs=n)
-    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_links=compress)
+    op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_links=compress, compress_clover=compact)
     nat = op.pack(to_dev(psi), prec)
     rb = op.field_bytes(prec, 1)
     tune_set("nr_" + prec, 1)

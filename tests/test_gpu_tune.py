@@ -46,8 +46,8 @@ def test_autotuned_launch_matches_oracle(prec, nrhs, clean_table, tmp_path, monk
 
 
 def test_full_size_bench_configuration(clean_table):
-    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links, autotuned FP64 and
-    FP32 launches (as bench.py times them): 1500 sampled sites vs the oracle."""
+    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links, compact clover, autotuned
+    FP64/FP32/FP16S launches (as bench.py times them): 1500 sampled sites vs the oracle."""
     dims = (96, 48, 48, 48)
     V = synth.volume(dims)
     m0, csw = -0.35, 1.0
@@ -56,7 +56,7 @@ def test_full_size_bench_configuration(clean_table):
     U = Ud.cpu().numpy()
     del Ud
     psi = psid.cpu().numpy()[0]
-    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32", "f16s"), compress_links=True)
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32", "f16s"), compress_links=True, compress_clover=True)
     sites = synth.random_sites(dims, 1500, 9)
     want = oracle.dirac_apply_sites(dims, U, psi, sites, m0, csw)
     st = torch.from_numpy(sites).cuda()
@@ -69,7 +69,7 @@ def test_full_size_bench_configuration(clean_table):
 
 
 def test_full_size_batched_launch(clean_table):
-    """48^3 x 96, FP32, two-row links, uneven batches {1, 4} in one launch, with
+    """48^3 x 96, FP32, two-row links, compact clover, uneven batches {1, 4} in one launch, with
     the autotuned configuration and with the link-stationary kernel (the one
     the benchmark's 41-RHS batch selects): 1000 sampled sites of every
     right-hand side vs the oracle."""
@@ -79,7 +79,7 @@ def test_full_size_batched_launch(clean_table):
     Ud = synth.smooth_links(dims, 1005, device="cuda")
     U = Ud.cpu().numpy()
     del Ud
-    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32"), compress_links=True)
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32"), compress_links=True, compress_clover=True)
     psid = synth.gaussian_spinor(dims, 2300, nrhs=5, device="cuda")
     nat = op.pack(psid, "f32")
     rb = op.field_bytes("f32", 1)
