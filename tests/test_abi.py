@@ -30,6 +30,23 @@ def test_header_declares_the_abi():
         assert n in names
 
 
+def test_header_constants_match_binding():
+    """Every status code, precision, flag and solver mode the header defines
+    has the same value in the Python binding; the solver parameter record has
+    the header's fields in order."""
+    text = open(os.path.join(ROOT, "include", "wdirac.h")).read()
+    defs = dict(re.findall(r"^#define (WDIRAC_\w+|FGMRES_\w+)\s+\(?(-?\d+)u?\)?", text, flags=re.M))
+    assert len(defs) >= 18
+    for name, value in defs.items():
+        attr = name[len("WDIRAC_"):] if name.startswith("WDIRAC_") else name
+        assert getattr(_lib, attr) == int(value), name
+    end = text.index("} fgmres_params;")
+    body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(\w+)\s*;", body)
+    assert fields == [f[0] for f in _lib.FgmresParams._fields_]
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for n in declared_functions():
