@@ -199,15 +199,19 @@ int dirac_tune_get(const char *key, int *value);
  * work-group size, T-chunk, register block) for this operator, precision and
  * nrhs right-hand sides in one launch, on temporary device buffers, and keep
  * the fastest for every later launch with the same lattice extents,
- * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...) and link format.
- * The choice is appended to the JSON-lines file named by the environment
- * variable WDIRAC_TUNE_CACHE when it is set; that file is read back the first
- * time a configuration is looked up.  Synchronous; allocates.
- *   cfg_out (optional): {order, block, tchunk, nr} chosen; us_out (optional):
- *   its time per launch in microseconds.
+ * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...), link format and
+ * clover format.  Candidates: tile orders 0, 2, 3, 4 (and 5 for FP32/FP16S
+ * with two-row links and several right-hand sides), work-groups of 128/256,
+ * T-chunks 2/4/8, register blocks 1/2/4 and, for several right-hand sides, a
+ * persistent grid.  The choice is appended to the JSON-lines file named by
+ * the environment variable WDIRAC_TUNE_CACHE when it is set; that file is
+ * read back the first time a configuration is looked up.  Synchronous;
+ * allocates.
+ *   cfg_out (optional): {order, block, tchunk, nr, persistent} chosen;
+ *   us_out (optional): its time per launch in microseconds.
  * Errors: EINVAL, EUNSUPPORTED (precision not materialised), ENOMEM, EHIP.
  */
-int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_out[4], double *us_out, void *stream);
+int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_out[5], double *us_out, void *stream);
 
 /* Forget every autotuned configuration of this process. */
 int dirac_tune_clear(void);

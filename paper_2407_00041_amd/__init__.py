@@ -195,11 +195,12 @@ class DiracOp:
 
     def autotune(self, prec="f64", nrhs: int = 1, stream=None) -> dict:
         """Time candidate launch configurations and keep the fastest (dirac_autotune)."""
-        cfg = (ctypes.c_int * 4)()
+        cfg = (ctypes.c_int * 5)()
         us = ctypes.c_double()
         check(self.lib.dirac_autotune(self.handle, _prec(prec), int(nrhs), cfg, ctypes.byref(us), _stream(stream)),
               "dirac_autotune")
-        return {"order": cfg[0], "block": cfg[1], "tchunk": cfg[2], "nr": cfg[3], "us": us.value}
+        return {"order": cfg[0], "block": cfg[1], "tchunk": cfg[2], "nr": cfg[3], "persistent": cfg[4],
+                "us": us.value}
 
     def force(self, eta: torch.Tensor, x: torch.Tensor, nrhs: int = 1, raw: bool = False,
               stream=None) -> torch.Tensor:

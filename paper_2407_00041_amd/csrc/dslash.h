@@ -58,6 +58,7 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk);
 // One launch configuration of the stencil.
 struct LaunchCfg {
     int order, block, tchunk, nr;
+    int persistent = 0;  // 1: a grid of the co-resident work-groups, each striding through the items
 };
 
 // Autotuned configurations, keyed by lattice, precision, right-hand-side

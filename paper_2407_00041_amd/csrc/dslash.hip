@@ -698,13 +698,13 @@ static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpDa
         for (int i = 0; i < tab.nchunks; i++) tab.c[i] = chunks[c0 + i];
         const long long items = (long long)m.nslots * tab.nchunks;
         long long grid = items;
-        if (persistent && tu.persistent_blocks > 0) {
+        if ((persistent && tu.persistent_blocks > 0) || cfg.persistent) {
             // a persistent grid: at most the resident work-groups, each striding
             // through the item list (by default the hardware dispatcher hands
             // out one work-group per item in order, which measured faster)
             long long cap = is_column_order(m.order) ? resident_blocks_col<P, DAG, NR>(cfg.block)
                                                     : resident_blocks<P, DAG, NR>(cfg.block);
-            if (tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
+            if (tu.persistent_blocks > 0 && tu.persistent_blocks < cap) cap = tu.persistent_blocks / 8 * 8;
             if (cap < 8) cap = 8;
             if (grid > cap) grid = cap;
         }

@@ -34,7 +34,8 @@ def test_autotuned_launch_matches_oracle(prec, nrhs, clean_table, tmp_path, monk
     U, psi = fields(dims, 12, nrhs=nrhs)
     op = DiracOp(dims, U, -0.3, 1.0, antiperiodic_t=True, compress_links=True)
     cfg = op.autotune(prec, nrhs)
-    assert cfg["order"] in (2, 3, 4, 5) and cfg["block"] in (128, 256) and cfg["nr"] in (1, 2, 4)
+    assert cfg["order"] in (0, 2, 3, 4, 5) and cfg["block"] in (128, 256) and cfg["nr"] in (1, 2, 4)
+    assert cfg["persistent"] in (0, 1) and (nrhs > 1 or cfg["persistent"] == 0)
     assert cfg["us"] > 0
     got = op.apply(to_dev(psi), prec).cpu().numpy()
     want = oracle.dirac_apply(dims, U, psi, -0.3, 1.0, antiperiodic_t=True)
@@ -42,6 +43,7 @@ def test_autotuned_launch_matches_oracle(prec, nrhs, clean_table, tmp_path, monk
         assert rel_l2(got[r], want[r]) < TOL[prec]
     lines = [json.loads(x) for x in cache.read_text().splitlines()]
     assert lines[-1]["order"] == cfg["order"] and lines[-1]["nr"] == cfg["nr"]
+    assert lines[-1]["persistent"] == cfg["persistent"]
     assert lines[-1]["key"].startswith("gfx950|6x4x6x4|")
 
 
