@@ -164,3 +164,27 @@ def test_full_size_fp64_fgmres_32():
     assert rc == 0 and st[0]["converged"]
     xg = op.unpack(x, "f64").cpu().numpy()[0]
     assert true_relres(dims, U, m0, csw, xg, bd.cpu().numpy()[0]) <= 1e-10 * 1.01
+
+
+def test_full_size_mixed_fgmres_bench_configuration():
+    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links and compact clover, the
+    benchmark's mixed solver (FP64 FGMRES(8), inner GMRES(10) on the FP16S
+    operator to 0.1) to 1e-10: the true residual of the GPU solution, computed
+    by the oracle operator over the whole lattice."""
+    need_gpu()
+    dims = (96, 48, 48, 48)
+    m0, csw = -0.35, 1.0
+    Ud = synth.smooth_links(dims, 1004, device="cuda")
+    bd = synth.gaussian_spinor(dims, 2400, nrhs=1, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f16s"), compress_links=True, compress_clover=True)
+    bn = op.pack(bd, "f64")
+    x, st, rc = op.solve(bn, restart=8, tol=1e-10, maxit=500, mode="mixed_f16s", inner_restart=10, inner_tol=0.1,
+                         inner_maxit=10)
+    assert rc == 0 and st[0]["converged"], st[0]
+    assert st[0]["true_residual"] < 1e-10
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    del op, x, bn
+    torch.cuda.empty_cache()
+    assert true_relres(dims, U, m0, csw, xg, bd.cpu().numpy()[0]) <= 1e-10 * 1.01
