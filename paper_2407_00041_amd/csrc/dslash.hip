@@ -47,6 +47,21 @@ __device__ __forceinline__ void project(const cx<T> p[12], cx<T> h[6], T f) {
     }
 }
 
+// h = u + S B_mu d (no factor)
+template <int MU, int S, typename T>
+__device__ __forceinline__ void project_unit(const cx<T> p[12], cx<T> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<T> d0 = p[6 + c], d1 = p[9 + c], b0, b1;
+        if (MU == 0) { b0 = d0; b1 = d1; }
+        else if (MU == 1) { b0 = times_mi(d0); b1 = times_i(d1); }
+        else if (MU == 2) { b0 = mk<T>(-d1.r, -d1.i); b1 = d0; }
+        else { b0 = times_mi(d1); b1 = times_mi(d0); }
+        if (S > 0) { h[c] = p[c] + b0; h[3 + c] = p[3 + c] + b1; }
+        else { h[c] = p[c] - b0; h[3 + c] = p[3 + c] - b1; }
+    }
+}
+
 // upper += chi; lower += S B_mu^H chi
 template <int MU, int S, typename T>
 __device__ __forceinline__ void reconstruct(cx<T> acc[12], const cx<T> chi[6]) {
@@ -522,19 +537,21 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
             T cr[28];
             Store<P>::load_clover_compact(d.clover, V, b, s, cr);
 #pragma unroll
-            for (int k = 0; k < 7; k++) lds[7 * b + k][tid] = make_float4(cr[4 * k], cr[4 * k + 1], cr[4 * k + 2], cr[4 * k + 3]);
+            for (int k = 0; k < 7; k++)
+                lds[7 * b + k][tid] = make_float4(-2 * cr[4 * k], -2 * cr[4 * k + 1], -2 * cr[4 * k + 2], -2 * cr[4 * k + 3]);
         } else {
             T dd[6];
             cx<T> uu[15];
             Store<P>::load_clover(d.clover, V, b, s, dd, uu);
-            lds[9 * b + 0][tid] = make_float4(dd[0], dd[1], dd[2], dd[3]);
-            lds[9 * b + 1][tid] = make_float4(dd[4], dd[5], uu[0].r, uu[0].i);
+            lds[9 * b + 0][tid] = make_float4(-2 * dd[0], -2 * dd[1], -2 * dd[2], -2 * dd[3]);
+            lds[9 * b + 1][tid] = make_float4(-2 * dd[4], -2 * dd[5], -2 * uu[0].r, -2 * uu[0].i);
 #pragma unroll
             for (int k = 0; k < 7; k++)
-                lds[9 * b + 2 + k][tid] = make_float4(uu[1 + 2 * k].r, uu[1 + 2 * k].i, uu[2 + 2 * k].r, uu[2 + 2 * k].i);
+                lds[9 * b + 2 + k][tid] = make_float4(-2 * uu[1 + 2 * k].r, -2 * uu[1 + 2 * k].i, -2 * uu[2 + 2 * k].r,
+                                                      -2 * uu[2 + 2 * k].i);
         }
     }
-    const T dg = (T)d.diag;
+    const T dg = T(-2) * (T)d.diag;
     const Nbr nb = neighbours(g, s);
     cx<T> Lf[4][6], Lb[4][6];
 #pragma unroll
@@ -547,8 +564,11 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
 #pragma unroll
         for (int e = 0; e < 6; e++) Lb[mu][e] = U[e];
     }
-    const T ffT = (apbc && nb.fwd_wrapT) ? T(0.5) : T(-0.5);
-    const T fbT = (apbc && nb.bwd_wrapT) ? T(0.5) : T(-0.5);
+    // everything up to the store is accumulated scaled by -2 (exact): the clover
+    // blocks were staged times -2, the hop projections drop their factor -1/2
+    // (an anti-periodic T wrap keeps a sign), and -1/2 is applied once at the end
+    const T ffT = (apbc && nb.fwd_wrapT) ? T(-1) : T(1);
+    const T fbT = (apbc && nb.bwd_wrapT) ? T(-1) : T(1);
     for (int r = 0; r < tab.n; r++) {
         const void *in = tab.in[r];
         cx<T> acc[12];
@@ -588,7 +608,7 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
             _Pragma("unroll") for (int e = 0; e < 6; e++) U[e] = Lf[MU][e];     \
             third_row(U);                                                       \
             Store<P>::load_spinor(in, V, nb.fwd[MU], p);                        \
-            project<MU, SF>(p, h, MU == 0 ? ffT : T(-0.5));                     \
+            if (MU == 0) project<MU, SF>(p, h, ffT); else project_unit<MU, SF>(p, h); \
             su3_mul<false>(U, h, chi);                                          \
             reconstruct<MU, SF>(acc, chi);                                      \
         }                                                                       \
@@ -597,7 +617,7 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
             _Pragma("unroll") for (int e = 0; e < 6; e++) U[e] = Lb[MU][e];     \
             third_row(U);                                                       \
             Store<P>::load_spinor(in, V, nb.bwd[MU], p);                        \
-            project<MU, SB>(p, h, MU == 0 ? fbT : T(-0.5));                     \
+            if (MU == 0) project<MU, SB>(p, h, fbT); else project_unit<MU, SB>(p, h); \
             su3_mul<true>(U, h, chi);                                           \
             reconstruct<MU, SB>(acc, chi);                                      \
         }                                                                       \
@@ -607,6 +627,8 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
         WD_STAT_HOP(2)
         WD_STAT_HOP(3)
 #undef WD_STAT_HOP
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = T(-0.5) * acc[k];
         Store<P>::store_spinor(tab.out[r], V, s, acc);
     }
 }

@@ -332,9 +332,12 @@ struct Ctx {
 
 // instantiated inner-cycle graphs of one solve, keyed by the right-hand sides they cover
 struct GraphCache {
-    hipStream_t cap = nullptr;  // private capture stream
+    hipStream_t cap = nullptr;     // private capture stream
+    hipStream_t launch = nullptr;  // stream the graphs are launched on
     std::map<std::vector<int>, hipGraphExec_t> exec;
     ~GraphCache() {
+        // an error return may leave launched graphs running: wait for them first
+        if (!exec.empty()) (void)hipStreamSynchronize(launch);
         for (auto &e : exec) (void)hipGraphExecDestroy(e.second);
         if (cap) (void)hipStreamDestroy(cap);
     }
@@ -502,12 +505,17 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     }
     struct PinnedGuard {
         double2 *p;
-        ~PinnedGuard() { (void)hipHostFree(p); }
-    } guard{pinned};
+        hipStream_t st;
+        ~PinnedGuard() {
+            (void)hipStreamSynchronize(st);  // no copy into the staging buffer may still be pending
+            (void)hipHostFree(p);
+        }
+    } guard{pinned, stream};
     Ctx c{op, p, stream, 12LL * op->g.V, op->g.V, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, pinned, pinned_n};
     const bool mixed = p->mode != FGMRES_F64;
     const int m = p->restart;
     GraphCache graphs;
+    graphs.launch = stream;
     // carve the workspace
     std::vector<Rhs> R(nrhs);
     char *wp = static_cast<char *>(work);
