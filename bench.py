@@ -286,6 +286,17 @@ def main():
                      "GFLOPs_1320": FLOP_HOP * V / (ms * 1e-3) / 1e9,
                      "GFLOPs_1872": FLOP_FULL * V / (ms * 1e-3) / 1e9}}
     if not a.no_extra:
+        # achievable streaming rate on this device: a plain 4 GiB device copy
+        n = 1 << 29
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        cms = time_launches(torch, lambda: dst.copy_(src), 10, 3, torch.cuda.current_stream())
+        copy_gbs = 2 * n * 8 / (cms * 1e-3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+        extra["f64"]["copy_GBps"] = copy_gbs
+        extra["f64"]["alg_frac_of_copy"] = gbs / copy_gbs
+        log(f"[bench] device copy {copy_gbs:.0f} GB/s; FP64 apply at {gbs / copy_gbs:.3f} of it")
         for p in ("f32", "f16s"):
             m = time_launches(torch, lambda: op.apply_native(out[p], inp[p], 1, p, stream=stream),
                               max(10, a.steps // 2), a.warmup, stream)
