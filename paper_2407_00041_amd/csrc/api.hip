@@ -125,13 +125,14 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     };
     hipStream_t st = nullptr;
     do {
-        if (!alloc((void **)&op->links64, (size_t)V * 4 * lr * 16) || !alloc((void **)&op->clover64, (size_t)V * cr * 8))
+        const size_t Vt = (size_t)op_sites(V);  // operator data are site-tiled (op_idx)
+        if (!alloc((void **)&op->links64, Vt * 4 * lr * 16) || !alloc((void **)&op->clover64, Vt * cr * 8))
             break;
-        if ((flags & WDIRAC_WITH_F32) && (!alloc((void **)&op->links32, (size_t)V * 4 * lr * 8) ||
-                                          !alloc((void **)&op->clover32, (size_t)V * cr * 4)))
+        if ((flags & WDIRAC_WITH_F32) && (!alloc((void **)&op->links32, Vt * 4 * lr * 8) ||
+                                          !alloc((void **)&op->clover32, Vt * cr * 4)))
             break;
-        if ((flags & WDIRAC_WITH_F16) && (!alloc((void **)&op->links16, (size_t)V * 4 * lr * 4) ||
-                                          !alloc((void **)&op->clover16, (size_t)V * cr * 2)))
+        if ((flags & WDIRAC_WITH_F16) && (!alloc((void **)&op->links16, Vt * 4 * lr * 4) ||
+                                          !alloc((void **)&op->clover16, Vt * cr * 2)))
             break;
         if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
         lc = op->links_canon;

@@ -83,12 +83,24 @@ inline size_t field_rhs_bytes(int prec, long long V) {
     }
 }
 
+// Operator data (links and clover, internal to the handle) are stored
+// site-tiled: entry e of site s at ((s / 64) * ne + e) * 64 + s % 64 with ne
+// entries per site, so one site tile's entries are contiguous and a
+// wavefront's loads of any entry hit one 64-site run; arrays are sized for V
+// rounded up to a multiple of 64.
+constexpr int kOpTile = 64;
+__host__ __device__ __forceinline__ size_t op_idx(int e, int ne, int s) {
+    return ((size_t)(s >> 6) * ne + e) * kOpTile + (s & (kOpTile - 1));
+}
+inline long long op_sites(long long V) { return (V + kOpTile - 1) / kOpTile * kOpTile; }
+
 // device-resident operator data at one precision
 struct OpData {
-    const void *links = nullptr;   // rows = 3: F64 [4][9][V] double2, F32 float2, F16 half2;
-                                   // rows = 2: F64 [4][6][V] double2, F32 [4][3][V] float4, F16 [4][3][V] 4 x half
-    const void *clover = nullptr;  // packed: F64 [2][18][V] double2; F32 [2][9][V] float4; F16 [2][9][V] 4 x half
-                                   // compact: F64 [2][14][V] double2; F32 [2][7][V] float4; F16 [2][7][V] 4 x half
+    // entries per site (site-tiled, op_idx):
+    const void *links = nullptr;   // rows = 3: 4 x 9 (F64 double2, F32 float2, F16 half2);
+                                   // rows = 2: F64 4 x 6 double2, F32 4 x 3 float4, F16 4 x 3 (4 x half)
+    const void *clover = nullptr;  // packed: F64 2 x 18 double2; F32 2 x 9 float4; F16 2 x 9 (4 x half)
+                                   // compact: F64 2 x 14 double2; F32 2 x 7 float4; F16 2 x 7 (4 x half)
     int rows = 3;                  // link rows stored (2: the third is conj(row0 x row1))
     int clover_compact = 0;        // 1: compact clover blocks (H, A_01) with the diagonal constant below
     double diag = 0;               // 4 + m0 (compact clover only)

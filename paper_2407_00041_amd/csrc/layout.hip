@@ -115,15 +115,15 @@ hipError_t unpack_launch(double *can, const void *nat, int nrhs, int prec, int V
 // ---------------------------------------------------------------------------
 // operator data
 
-// canonical links [V][4][3][3] c128 -> native FP64 [4][rows*3][V] double2
-// (rows = 2 keeps the first two rows of every link)
+// canonical links [V][4][3][3] c128 -> native FP64 site-tiled 4 x rows*3 double2
+// entries per site (rows = 2 keeps the first two rows of every link)
 __global__ __launch_bounds__(256) void links_to_native(double2 *__restrict__ nat, const double2 *__restrict__ can,
                                                        int V, int rows) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     const int ne = 3 * rows;
     for (int mu = 0; mu < 4; mu++)
-        for (int e = 0; e < ne; e++) nat[(size_t)(mu * ne + e) * V + s] = can[(size_t)36 * s + 9 * mu + e];
+        for (int e = 0; e < ne; e++) nat[op_idx(mu * ne + e, 4 * ne, s)] = can[(size_t)36 * s + 9 * mu + e];
 }
 
 // largest deviation of a link from SU(3): max |U U^H - 1| and |det U - 1|,
@@ -180,8 +180,8 @@ hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStr
 }
 
 // canonical unit clover [V][42] c128 -> native FP64 A(x) = (4+m0) I + csw C(x):
-// [2 blocks][18][V] double2, per block 3 vectors of diagonal reals then 15
-// strict-upper complex entries.
+// site-tiled 2 blocks x 18 double2 entries, per block 3 vectors of diagonal
+// reals then 15 strict-upper complex entries.
 __global__ __launch_bounds__(256) void clover_to_native(double2 *__restrict__ nat, const double2 *__restrict__ can,
                                                         int V, double diag, double csw) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -189,20 +189,20 @@ __global__ __launch_bounds__(256) void clover_to_native(double2 *__restrict__ na
     const double2 *c = can + (size_t)42 * s;
 #pragma unroll
     for (int b = 0; b < 2; b++) {
-        double2 *o = nat + (size_t)b * 18 * V;
 #pragma unroll
         for (int e = 0; e < 3; e++)
-            o[(size_t)e * V + s] = make_double2(diag + csw * c[21 * b + 2 * e].x, diag + csw * c[21 * b + 2 * e + 1].x);
+            nat[op_idx(b * 18 + e, 36, s)] =
+                make_double2(diag + csw * c[21 * b + 2 * e].x, diag + csw * c[21 * b + 2 * e + 1].x);
 #pragma unroll
         for (int e = 0; e < 15; e++) {
             double2 u = c[21 * b + 6 + e];
-            o[(size_t)(3 + e) * V + s] = make_double2(csw * u.x, csw * u.y);
+            nat[op_idx(b * 18 + 3 + e, 36, s)] = make_double2(csw * u.x, csw * u.y);
         }
     }
 }
 
 // canonical unit clover [V][42] c128 -> compact native FP64 blocks of csw C(x):
-// [2 blocks][14][V] double2 holding 28 reals per block: H = csw (C_00 - C_11)/2
+// site-tiled 2 blocks x 14 double2 entries holding 28 reals per block: H = csw (C_00 - C_11)/2
 // (h00, h11, h22, then h01, h02, h12 as re, im), A_01 = csw C_01 (9 complex,
 // row-major), one zero pad.  Block-local index 3 s + c (s = spin within the
 // block); the packed upper entries are in row-major pair order.
@@ -231,8 +231,7 @@ __global__ __launch_bounds__(256) void clover_to_native_compact(double2 *__restr
                 r[10 + 2 * (3 * i + j)] = csw * m.y;
             }
         r[27] = 0.0;
-        double2 *o = nat + (size_t)b * 14 * V;
-        for (int q = 0; q < 14; q++) o[(size_t)q * V + s] = make_double2(r[2 * q], r[2 * q + 1]);
+        for (int q = 0; q < 14; q++) nat[op_idx(b * 14 + q, 28, s)] = make_double2(r[2 * q], r[2 * q + 1]);
     }
 }
 
@@ -280,7 +279,7 @@ hipError_t clover_structure_deviation(const double *clover_can_dev, int V, doubl
     return e;
 }
 
-// compact FP64 clover [2][14][V] double2 -> [2][7][V] float4 / 4 x half (same real order)
+// compact FP64 clover (2 x 14 double2 entries) -> 2 x 7 float4 / 4 x half entries (same real order)
 __global__ __launch_bounds__(256) void clover_narrow_compact(float4 *__restrict__ o32, half4 *__restrict__ o16,
                                                              const double2 *__restrict__ nat, int V) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,34 +288,34 @@ __global__ __launch_bounds__(256) void clover_narrow_compact(float4 *__restrict_
     for (int b = 0; b < 2; b++)
 #pragma unroll
         for (int q = 0; q < 7; q++) {
-            double2 a = nat[(size_t)(b * 14 + 2 * q) * V + s];
-            double2 c = nat[(size_t)(b * 14 + 2 * q + 1) * V + s];
-            if (o32) o32[(size_t)(b * 7 + q) * V + s] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+            double2 a = nat[op_idx(b * 14 + 2 * q, 28, s)];
+            double2 c = nat[op_idx(b * 14 + 2 * q + 1, 28, s)];
+            if (o32) o32[op_idx(b * 7 + q, 14, s)] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
             if (o16) {
                 half4 h;
                 h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)c.x; h[3] = (_Float16)c.y;
-                o16[(size_t)(b * 7 + q) * V + s] = h;
+                o16[op_idx(b * 7 + q, 14, s)] = h;
             }
         }
 }
 
-// native FP64 links (two stored rows) -> FP32 [4][3][V] float4 / FP16 [4][3][V] 4 x half
+// native FP64 links (two stored rows, 24 entries) -> FP32 float4 / FP16 4 x half (12 entries)
 __global__ __launch_bounds__(256) void links_narrow2(float4 *__restrict__ o32, half4 *__restrict__ o16,
                                                      const double2 *__restrict__ nat, int V) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     for (int q = 0; q < 12; q++) {  // (mu, pair) pairs of the [4][6] entries
-        double2 a = nat[(size_t)(2 * q) * V + s], b = nat[(size_t)(2 * q + 1) * V + s];
-        if (o32) o32[(size_t)q * V + s] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        double2 a = nat[op_idx(2 * q, 24, s)], b = nat[op_idx(2 * q + 1, 24, s)];
+        if (o32) o32[op_idx(q, 12, s)] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
         if (o16) {
             half4 h;
             h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)b.x; h[3] = (_Float16)b.y;
-            o16[(size_t)q * V + s] = h;
+            o16[op_idx(q, 12, s)] = h;
         }
     }
 }
 
-// native FP64 links -> FP32 float2 / FP16 half2 (same [4][9][V] order)
+// native FP64 links -> FP32 float2 / FP16 half2 (same site-tiled entry order, flat)
 __global__ __launch_bounds__(256) void links_narrow(float2 *__restrict__ o32, half2v *__restrict__ o16,
                                                     const double2 *__restrict__ nat, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,7 +330,7 @@ __global__ __launch_bounds__(256) void links_narrow(float2 *__restrict__ o32, ha
     }
 }
 
-// native FP64 clover [2][18][V] double2 -> [2][9][V] float4 / 4 x half
+// native FP64 clover (2 x 18 double2 entries) -> 2 x 9 float4 / 4 x half entries
 // (the block's 36 reals in the same order, four per vector)
 __global__ __launch_bounds__(256) void clover_narrow(float4 *__restrict__ o32, half4 *__restrict__ o16,
                                                      const double2 *__restrict__ nat, int V) {
@@ -341,13 +340,13 @@ __global__ __launch_bounds__(256) void clover_narrow(float4 *__restrict__ o32, h
     for (int b = 0; b < 2; b++)
 #pragma unroll
         for (int q = 0; q < 9; q++) {
-            double2 a = nat[(size_t)(b * 18 + 2 * q) * V + s];
-            double2 c = nat[(size_t)(b * 18 + 2 * q + 1) * V + s];
-            if (o32) o32[(size_t)(b * 9 + q) * V + s] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
+            double2 a = nat[op_idx(b * 18 + 2 * q, 36, s)];
+            double2 c = nat[op_idx(b * 18 + 2 * q + 1, 36, s)];
+            if (o32) o32[op_idx(b * 9 + q, 18, s)] = make_float4((float)a.x, (float)a.y, (float)c.x, (float)c.y);
             if (o16) {
                 half4 h;
                 h[0] = (_Float16)a.x; h[1] = (_Float16)a.y; h[2] = (_Float16)c.x; h[3] = (_Float16)c.y;
-                o16[(size_t)(b * 9 + q) * V + s] = h;
+                o16[op_idx(b * 9 + q, 18, s)] = h;
             }
         }
 }
@@ -369,7 +368,7 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
             hipLaunchKernelGGL(links_narrow2, grid, dim3(256), 0, st, (float4 *)op->links32, (half4 *)op->links16,
                                (const double2 *)op->links64, V);
         } else {
-            size_t n = (size_t)36 * V;
+            size_t n = (size_t)36 * op_sites(V);
             hipLaunchKernelGGL(links_narrow, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                                (float2 *)op->links32, (half2v *)op->links16, (const double2 *)op->links64, n);
         }

@@ -72,7 +72,7 @@ template <> struct Store<WDIRAC_F64> {
         if (rows == 2) {
 #pragma unroll
             for (int e = 0; e < 6; e++) {
-                double2 a = p[(size_t)(mu * 6 + e) * V + s];
+                double2 a = p[op_idx(mu * 6 + e, 24, s)];
                 U[e] = {a.x, a.y};
             }
             third_row(U);
@@ -80,32 +80,32 @@ template <> struct Store<WDIRAC_F64> {
         }
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            double2 a = p[(size_t)(mu * 9 + e) * V + s];
+            double2 a = p[op_idx(mu * 9 + e, 36, s)];
             U[e] = {a.x, a.y};
         }
     }
     // block b of A(x): 6 real diagonal entries and 15 complex strict-upper entries
     static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
                                                        cx<T> u[15]) {
-        const d2v *p = static_cast<const d2v *>(base) + (size_t)b * 18 * V;
+        const d2v *p = static_cast<const d2v *>(base);
 #pragma unroll
         for (int e = 0; e < 3; e++) {
-            d2v a = ld_once(&p[(size_t)e * V + s]);
+            d2v a = ld_once(&p[op_idx(b * 18 + e, 36, s)]);
             d[2 * e] = a.x;
             d[2 * e + 1] = a.y;
         }
 #pragma unroll
         for (int e = 0; e < 15; e++) {
-            d2v a = ld_once(&p[(size_t)(3 + e) * V + s]);
+            d2v a = ld_once(&p[op_idx(b * 18 + 3 + e, 36, s)]);
             u[e] = {a.x, a.y};
         }
     }
     // compact block b: 28 reals (H diagonal, H upper re/im, A_01 re/im row-major, pad)
     static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
-        const d2v *p = static_cast<const d2v *>(base) + (size_t)b * 14 * V;
+        const d2v *p = static_cast<const d2v *>(base);
 #pragma unroll
         for (int q = 0; q < 14; q++) {
-            d2v a = ld_once(&p[(size_t)q * V + s]);
+            d2v a = ld_once(&p[op_idx(b * 14 + q, 28, s)]);
             r[2 * q] = a.x;
             r[2 * q + 1] = a.y;
         }
@@ -147,7 +147,7 @@ template <> struct Store<WDIRAC_F32> {
             const float4 *q = static_cast<const float4 *>(base);
 #pragma unroll
             for (int e = 0; e < 3; e++) {
-                float4 a = q[(size_t)(mu * 3 + e) * V + s];
+                float4 a = q[op_idx(mu * 3 + e, 12, s)];
                 U[2 * e] = {a.x, a.y};
                 U[2 * e + 1] = {a.z, a.w};
             }
@@ -157,17 +157,17 @@ template <> struct Store<WDIRAC_F32> {
         const float2 *p = static_cast<const float2 *>(base);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            float2 a = p[(size_t)(mu * 9 + e) * V + s];
+            float2 a = p[op_idx(mu * 9 + e, 36, s)];
             U[e] = {a.x, a.y};
         }
     }
     static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
                                                        cx<T> u[15]) {
-        const f4v *p = static_cast<const f4v *>(base) + (size_t)b * 9 * V;
+        const f4v *p = static_cast<const f4v *>(base);
         float r[36];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            f4v a = ld_once(&p[(size_t)e * V + s]);
+            f4v a = ld_once(&p[op_idx(b * 9 + e, 18, s)]);
             r[4 * e] = a.x; r[4 * e + 1] = a.y; r[4 * e + 2] = a.z; r[4 * e + 3] = a.w;
         }
 #pragma unroll
@@ -176,10 +176,10 @@ template <> struct Store<WDIRAC_F32> {
         for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
     }
     static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
-        const f4v *p = static_cast<const f4v *>(base) + (size_t)b * 7 * V;
+        const f4v *p = static_cast<const f4v *>(base);
 #pragma unroll
         for (int q = 0; q < 7; q++) {
-            f4v a = ld_once(&p[(size_t)q * V + s]);
+            f4v a = ld_once(&p[op_idx(b * 7 + q, 14, s)]);
             r[4 * q] = a.x; r[4 * q + 1] = a.y; r[4 * q + 2] = a.z; r[4 * q + 3] = a.w;
         }
     }
@@ -231,7 +231,7 @@ template <> struct Store<WDIRAC_F16S> {
             const half4 *q = static_cast<const half4 *>(base);
 #pragma unroll
             for (int e = 0; e < 3; e++) {
-                half4 a = q[(size_t)(mu * 3 + e) * V + s];
+                half4 a = q[op_idx(mu * 3 + e, 12, s)];
                 U[2 * e] = {(float)a[0], (float)a[1]};
                 U[2 * e + 1] = {(float)a[2], (float)a[3]};
             }
@@ -241,17 +241,17 @@ template <> struct Store<WDIRAC_F16S> {
         const half2v *p = static_cast<const half2v *>(base);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            half2v a = p[(size_t)(mu * 9 + e) * V + s];
+            half2v a = p[op_idx(mu * 9 + e, 36, s)];
             U[e] = {(float)a[0], (float)a[1]};
         }
     }
     static __device__ __forceinline__ void load_clover(const void *base, int V, int b, int s, T d[6],
                                                        cx<T> u[15]) {
-        const half4 *p = static_cast<const half4 *>(base) + (size_t)b * 9 * V;
+        const half4 *p = static_cast<const half4 *>(base);
         float r[36];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            half4 a = ld_once(&p[(size_t)e * V + s]);
+            half4 a = ld_once(&p[op_idx(b * 9 + e, 18, s)]);
             r[4 * e] = (float)a[0]; r[4 * e + 1] = (float)a[1];
             r[4 * e + 2] = (float)a[2]; r[4 * e + 3] = (float)a[3];
         }
@@ -261,10 +261,10 @@ template <> struct Store<WDIRAC_F16S> {
         for (int k = 0; k < 15; k++) u[k] = {r[6 + 2 * k], r[7 + 2 * k]};
     }
     static __device__ __forceinline__ void load_clover_compact(const void *base, int V, int b, int s, T r[28]) {
-        const half4 *p = static_cast<const half4 *>(base) + (size_t)b * 7 * V;
+        const half4 *p = static_cast<const half4 *>(base);
 #pragma unroll
         for (int q = 0; q < 7; q++) {
-            half4 a = ld_once(&p[(size_t)q * V + s]);
+            half4 a = ld_once(&p[op_idx(b * 7 + q, 14, s)]);
             r[4 * q] = (float)a[0]; r[4 * q + 1] = (float)a[1]; r[4 * q + 2] = (float)a[2]; r[4 * q + 3] = (float)a[3];
         }
     }
