@@ -255,6 +255,9 @@ typedef struct {
                         /* graph, captured once per set of right-hand sides  */
                         /* and replayed (no host step per inner iteration);  */
                         /* 0 = issue it step by step                         */
+    int wave;           /* right-hand sides solved together (lockstep, one   */
+                        /* batched apply per step); nrhs is processed in     */
+                        /* consecutive waves of this size; 0 = all at once   */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096
@@ -271,7 +274,8 @@ typedef struct {
     double hist[FGMRES_HIST_MAX]; /* relative residual estimate per step    */
 } fgmres_stats;
 
-/* Workspace bytes fgmres_solve needs for `nrhs` right-hand sides. */
+/* Workspace bytes fgmres_solve needs for `nrhs` right-hand sides (for one
+ * wave of min(p->wave, nrhs) of them when p->wave > 0). */
 size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nrhs);
 
 /*
@@ -281,8 +285,10 @@ size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nr
  * together as one batched launch.
  *   x, b : device, native FP64, nrhs fields each.  x is the initial guess on
  *          entry (x0) and the solution on return.
- *   st   : host array of nrhs stats records (may be NULL).
- *   work : device workspace of at least fgmres_workspace_bytes(op, p, nrhs).
+ *   st   : host array of nrhs stats records (may be NULL); `seconds` is the
+ *          wall time of the wave that solved the right-hand side.
+ *   work : device workspace of at least fgmres_workspace_bytes(op, p, nrhs),
+ *          reused by every wave.
  * Blocks until done (one host synchronisation per outer Arnoldi step to read
  * the residual estimates, plus one per inner step unless p->graph is set).  Returns WDIRAC_ENOTCONV (> 0) when some right-hand
  * side reached maxit (x still holds its last iterate); errors: EINVAL,

@@ -675,6 +675,7 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     if (p->maxit < 1) return fail(WDIRAC_EINVAL, "maxit must be >= 1");
     if (p->mode != FGMRES_F64 && p->mode != FGMRES_MIXED_F32 && p->mode != FGMRES_MIXED_F16S)
         return fail(WDIRAC_EINVAL, "unknown solver mode");
+    if (p->wave < 0) return fail(WDIRAC_EINVAL, "wave must be >= 0");
     if (p->mode != FGMRES_F64) {
         if (p->inner_restart < 1 || p->inner_restart > 1000) return fail(WDIRAC_EINVAL, "inner_restart in [1, 1000]");
         if (p->inner_maxit < 1) return fail(WDIRAC_EINVAL, "inner_maxit must be >= 1");
@@ -685,9 +686,12 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     return WDIRAC_OK;
 }
 
+// right-hand sides per wave
+static int wave_of(const fgmres_params *p, int nrhs) { return (p->wave > 0 && p->wave < nrhs) ? p->wave : nrhs; }
+
 size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nrhs) {
     if (nrhs < 1 || check_params(op, p)) return 0;
-    return solver_workspace(op, p, nrhs);
+    return solver_workspace(op, p, wave_of(p, nrhs));
 }
 
 int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres_params *p,
@@ -698,9 +702,19 @@ int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs, const
     if (nrhs < 1) return fail(WDIRAC_EINVAL, "nrhs must be >= 1");
     rc = check_apply(op, x, b, nrhs, WDIRAC_F64);
     if (rc) return rc;
-    if (work_bytes < solver_workspace(op, p, nrhs)) return fail(WDIRAC_EINVAL, "workspace too small");
+    const int w = wave_of(p, nrhs);
+    if (work_bytes < solver_workspace(op, p, w)) return fail(WDIRAC_EINVAL, "workspace too small");
     if (reinterpret_cast<uintptr_t>(work) & 255) return fail(WDIRAC_EINVAL, "workspace must be 256-byte aligned");
-    return solve(op, x, b, nrhs, p, st, work, work_bytes, (hipStream_t)stream);
+    const size_t field = (size_t)24 * op->g.V;  // doubles per right-hand side
+    bool notconv = false;
+    for (int k0 = 0; k0 < nrhs; k0 += w) {
+        const int nw = nrhs - k0 < w ? nrhs - k0 : w;
+        rc = solve(op, x + k0 * field, b + k0 * field, nw, p, st ? st + k0 : nullptr, work, work_bytes,
+                   (hipStream_t)stream);
+        if (rc < 0) return rc;
+        notconv = notconv || rc == WDIRAC_ENOTCONV;
+    }
+    return notconv ? WDIRAC_ENOTCONV : WDIRAC_OK;
 }
 
 }  // extern "C"

@@ -118,6 +118,25 @@ def test_inner_gmres_near_exact_on_2x4(graph):
     assert true_relres(dims, U, m0, csw, xg, b) <= 1e-10 * 1.01
 
 
+@pytest.mark.parametrize("mode", ["f64", "mixed_f16s"])
+def test_waves_equal_one_lockstep_solve(mode):
+    """Five right-hand sides in waves of 2 (one workspace sized for a wave) give
+    the same solutions, bit for bit, as all five in one lockstep solve."""
+    need_gpu()
+    dims = (4, 4, 6, 4)
+    U, b, op, bn = setup(dims, 9, -0.3, 1.0, nrhs=5)
+    kw = dict(nrhs=5, restart=8, tol=1e-10, maxit=2000, mode=mode, inner_restart=10, inner_tol=0.1, inner_maxit=10)
+    x_all, s_all, rc = op.solve(bn, **kw)
+    assert rc == 0
+    wb = op.workspace_bytes(5, 8, mode, 10, wave=2)
+    assert wb < op.workspace_bytes(5, 8, mode, 10)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    x_w, s_w, rc = op.solve(bn, wave=2, work=work, **kw)
+    assert rc == 0
+    assert torch.equal(x_w, x_all)
+    assert [s["applies"] for s in s_w] == [s["applies"] for s in s_all]
+
+
 def test_maxit_zero_rhs_and_warm_start():
     need_gpu()
     dims = (4, 4, 4, 4)
