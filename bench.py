@@ -165,6 +165,8 @@ def fgmres_run(torch, op, dims, nrhs_total):
             op.autotune("f64", n)
             op.autotune(inner, n)
     t64 = tmx = 0.0
+    ph64 = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
+    phmx = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
     a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
     for w0 in range(0, nrhs_total, wave):
         nw = min(wave, nrhs_total - w0)
@@ -178,6 +180,9 @@ def fgmres_run(torch, op, dims, nrhs_total):
         xmx, stmx, _ = op.solve(b, nrhs=nw, work=work, **pmx)
         torch.cuda.synchronize()
         tmx += time.perf_counter() - t
+        for k in ph64:  # GPU time per phase of this wave (shared by its right-hand sides)
+            ph64[k] += st64[0]["seconds_" + k]
+            phmx[k] += stmx[0]["seconds_" + k]
         for r in range(nw):
             u = x64[r * fb:(r + 1) * fb].view(torch.float64)
             v = xmx[r * fb:(r + 1) * fb].view(torch.float64)
@@ -191,11 +196,11 @@ def fgmres_run(torch, op, dims, nrhs_total):
         del b, x64, xmx
         torch.cuda.empty_cache()
     return {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
-            "fp64": {"solver": "FGMRES(30), FP64", "seconds": t64, "applies": a64,
+            "fp64": {"solver": "FGMRES(30), FP64", "seconds": t64, "phase_seconds": ph64, "applies": a64,
                      "true_residual_max": max(res64), "converged": all(r < 1e-10 for r in res64)},
             "mixed": {"solver": f"FP64 FGMRES({pmx['restart']}), preconditioner inner GMRES({pmx['inner_restart']}) "
                                 f"on the {pmx['mode'][6:].upper()} operator (relative tol {pmx['inner_tol']})",
-                      "seconds": tmx, "fp64_applies": amx, "fp16s_applies": ainner,
+                      "seconds": tmx, "phase_seconds": phmx, "fp64_applies": amx, "fp16s_applies": ainner,
                       "true_residual_max": max(resmx), "converged": all(r < 1e-10 for r in resmx)},
             "speedup_mixed_vs_fp64": t64 / tmx if tmx > 0 else None,
             "error_vs_fp64_max": max(errs)}

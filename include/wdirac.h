@@ -269,7 +269,11 @@ typedef struct {
     int converged;              /* 1 if the tolerance was met                */
     int breakdown;              /* 1 if |h_{j+1,j}| < tol/10 ended a cycle   */
     double true_residual;       /* final ||b - D x|| / ||b - D x0||, FP64    */
-    double seconds;             /* wall time of the solve                    */
+    double seconds;             /* wall time of the solve (of its wave)      */
+    double seconds_apply;       /* of which FP64 operator applications,      */
+    double seconds_precond;     /* inner (low-precision) solves, and          */
+    double seconds_ortho;       /* outer Gram-Schmidt and residuals (GPU     */
+                                /* time of the wave, from HIP events)         */
     int nhist;                  /* entries in hist[]                         */
     double hist[FGMRES_HIST_MAX]; /* relative residual estimate per step    */
 } fgmres_stats;

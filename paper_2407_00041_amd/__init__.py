@@ -193,6 +193,8 @@ class DiracOp:
             out.append({"applies": s.applies, "inner_applies": s.inner_applies, "restarts": s.restarts,
                         "converged": bool(s.converged), "breakdown": bool(s.breakdown),
                         "true_residual": s.true_residual, "seconds": s.seconds,
+                        "seconds_apply": s.seconds_apply, "seconds_precond": s.seconds_precond,
+                        "seconds_ortho": s.seconds_ortho,
                         "hist": [s.hist[i] for i in range(s.nhist)]})
         return x, out, rc
 

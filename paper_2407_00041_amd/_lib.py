@@ -35,6 +35,8 @@ class FgmresStats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_longlong), ("inner_applies", ctypes.c_longlong),
                 ("restarts", ctypes.c_longlong), ("converged", _I), ("breakdown", _I),
                 ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("seconds_apply", ctypes.c_double), ("seconds_precond", ctypes.c_double),
+                ("seconds_ortho", ctypes.c_double),
                 ("nhist", _I), ("hist", ctypes.c_double * FGMRES_HIST_MAX)]
 
 

@@ -553,6 +553,17 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     }
     if ((size_t)(wp - static_cast<char *>(work)) > work_bytes) return fail(WDIRAC_EINVAL, "workspace too small");
 
+    // phase timing: events around the preconditioner, the FP64 apply and the
+    // orthogonalisation of every step (read after the step's synchronisation)
+    struct Events {
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t &x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    for (hipEvent_t &x : ev.e) WD_TRY(hipEventCreate(&x));
+    double t_apply = 0, t_precond = 0, t_ortho = 0;
     bool any = true;
     while (any) {
         // preconditioning of the right-hand sides inside a cycle
@@ -561,15 +572,18 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             if (r.phase == Phase::Arnoldi) arn.push_back(&r);
             if (r.phase == Phase::Residual) res.push_back(&r);
         }
+        WD_TRY(hipEventRecord(ev.e[0], c.st));
         if (mixed && !arn.empty()) {
             int rc = inner_solve(c, arn, p->graph ? &graphs : nullptr, R);
             if (rc) return rc;
         }
+        WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (lines 4 and 9)
         std::vector<dirac_batch> bat;
         for (Rhs *r : res) bat.push_back({r->w, r->x, 1});
         for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], 1});
         WD_TRY(apply_many(c, WDIRAC_F64, bat, c.st));
+        WD_TRY(hipEventRecord(ev.e[2], c.st));
         for (Rhs *r : res) {
             r->applies++;
             WD_TRY(residual(r->b, r->w, static_cast<double2 *>(r->V[0]), c.N, r->partial, r->nrm, c.st));
@@ -580,6 +594,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             WD_TRY(mdot<double2>(r->V.data(), j + 1, r->w, c.N, r->partial, r->hcol, c.st));
             WD_TRY(axpy_multi<double2>(r->V.data(), j + 1, r->hcol, r->w, c.N, r->partial, r->hcol + j + 1, c.st));
         }
+        WD_TRY(hipEventRecord(ev.e[3], c.st));
         std::vector<std::pair<const double2 *, int>> src;
         for (Rhs *r : res) src.emplace_back(r->nrm, 1);
         for (Rhs *r : arn) src.emplace_back(r->hcol, r->outer.j + 2);
@@ -589,6 +604,15 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         if (!src.empty()) {
             int rc = fetch(c, src, got);
             if (rc) return rc;
+        } else {
+            WD_TRY(hipStreamSynchronize(c.st));
+        }
+        {
+            float ms[3] = {0, 0, 0};
+            for (int k = 0; k < 3; k++) WD_TRY(hipEventElapsedTime(&ms[k], ev.e[k], ev.e[k + 1]));
+            t_precond += ms[0] * 1e-3;
+            t_apply += ms[1] * 1e-3;
+            t_ortho += ms[2] * 1e-3;
         }
         // restarts: convergence test on the true residual
         for (size_t k = 0; k < res.size(); k++) {
@@ -656,6 +680,9 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         s.breakdown = r.breakdown ? 1 : 0;
         s.true_residual = r.relres;
         s.seconds = secs;
+        s.seconds_apply = t_apply;
+        s.seconds_precond = t_precond;
+        s.seconds_ortho = t_ortho;
         s.nhist = (int)std::min<size_t>(r.hist.size(), FGMRES_HIST_MAX);
         for (int i = 0; i < s.nhist; i++) s.hist[i] = r.hist[i];
     }

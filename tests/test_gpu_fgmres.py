@@ -55,6 +55,9 @@ def test_mixed_precision_reaches_fp64_tolerance(mode):
                          inner_maxit=30)
     assert rc == 0 and st[0]["converged"], st[0]
     assert st[0]["inner_applies"] > 0
+    phases = st[0]["seconds_apply"] + st[0]["seconds_precond"] + st[0]["seconds_ortho"]
+    assert st[0]["seconds_apply"] > 0 and st[0]["seconds_precond"] > 0 and st[0]["seconds_ortho"] > 0
+    assert phases <= st[0]["seconds"] * 1.05
     xg = op.unpack(x, "f64").cpu().numpy()[0]
     assert true_relres(dims, U, m0, csw, xg, b) <= 1e-10 * 1.01
     x64, st64, _ = op.solve(bn, restart=20, tol=1e-10, maxit=3000)
