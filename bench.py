@@ -291,12 +291,13 @@ def main():
                      "GFLOPs_1320": FLOP_HOP * V / (ms * 1e-3) / 1e9,
                      "GFLOPs_1872": FLOP_FULL * V / (ms * 1e-3) / 1e9}}
     if not a.no_extra:
-        # achievable streaming rate on this device: a plain 4 GiB device copy
-        n = 1 << 29
-        src = torch.ones(n, dtype=torch.float64, device=dev)
+        # achievable streaming rate on this device: an elementwise kernel reading
+        # 4 GiB and writing 4 GiB (a same-dtype copy_ would take the slower blit path)
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        cms = time_launches(torch, lambda: dst.copy_(src), 10, 3, torch.cuda.current_stream())
-        copy_gbs = 2 * n * 8 / (cms * 1e-3) / 1e9
+        cms = time_launches(torch, lambda: torch.mul(src, 2.0, out=dst), 10, 3, torch.cuda.current_stream())
+        copy_gbs = 2 * n * 4 / (cms * 1e-3) / 1e9
         del src, dst
         torch.cuda.empty_cache()
         extra["f64"]["copy_GBps"] = copy_gbs
