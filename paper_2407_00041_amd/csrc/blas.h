@@ -5,7 +5,9 @@
 
 namespace wd {
 
-constexpr int kGS = 8;            // basis vectors per orthogonalisation pass
+constexpr int kGS = 32;           // basis vectors per FP64 update pass (a restart-30 step in one pass)
+constexpr int kMdot = 8;          // basis vectors per FP64 inner-product pass (8 accumulators keep occupancy)
+constexpr int kGSSite = 8;        // basis vectors per pass of the per-site (low-precision) kernels
 constexpr int kRedThreads = 256;  // threads per reduction work-group
 constexpr int kRedBlocks = 1024;  // reduction work-groups (fixed: deterministic sums)
 
@@ -23,8 +25,8 @@ struct CoefList {
 __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
                                                         double2 *__restrict__ out);
 
-// out[i] = <v_i, w> = v_i^H w for i < nv, out[nv].x = |w|^2; partial needs
-// kRedBlocks * (kGS + 1) entries.  S = double2 (FP64 storage).
+// out[i] = <v_i, w> = v_i^H w for i < nv (passes of kMdot vectors),
+// out[nv].x = |w|^2; partial needs kRedBlocks * (kMdot + 1) entries.  S = double2 (FP64 storage).
 template <typename S>
 hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
                 hipStream_t st);
@@ -46,7 +48,8 @@ hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x,
 
 // Per-site operations on native fields of precision prec (WDIRAC_F64, _F32 or
 // _F16S), nrhs = 1, FP64 accumulation; results re-encoded in the field's
-// precision.  partial needs kRedBlocks * (kGS + 1) entries.  hdr (nullable) is
+// precision, in passes of kGSSite vectors.  partial needs kRedBlocks * (kGSSite + 1)
+// entries.  hdr (nullable) is
 // the device header of an inner cycle: hdr[0] = (completed steps, active
 // flag), hdr[1].x = normalisation factor; with hdr[0].y == 0 the kernels of
 // mdot and axpy do nothing.

@@ -49,20 +49,20 @@ __device__ __forceinline__ void block_reduce(double2 (&v)[NV], double2 *lds) {
 }
 
 // partial[blk][i] = sum conj(v_i) w over the group's elements (i < nv),
-// partial[blk][kGS] = sum |w|^2 (real part)
+// partial[blk][kMdot] = sum |w|^2 (real part)
 template <typename S>
 __global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__restrict__ w,
                                                        double2 *__restrict__ partial, long long N) {
-    __shared__ double2 lds[(kGS + 1) * kRedThreads];
-    double2 acc[kGS + 1];
+    __shared__ double2 lds[(kMdot + 1) * kRedThreads];
+    double2 acc[kMdot + 1];
 #pragma unroll
-    for (int i = 0; i <= kGS; i++) acc[i] = make_double2(0, 0);
+    for (int i = 0; i <= kMdot; i++) acc[i] = make_double2(0, 0);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
         const double2 we = Elem<S>::ld(w, e);
-        acc[kGS].x += we.x * we.x + we.y * we.y;
+        acc[kMdot].x += we.x * we.x + we.y * we.y;
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
+        for (int i = 0; i < kMdot; i++) {
             if (i < vl.n) {
                 const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
                 const double2 p = cj_mul(vi, we);
@@ -71,10 +71,10 @@ __global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__res
             }
         }
     }
-    block_reduce<kGS + 1>(acc, lds);
+    block_reduce<kMdot + 1>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i <= kGS; i++) partial[(size_t)blockIdx.x * (kGS + 1) + i] = acc[i];
+        for (int i = 0; i <= kMdot; i++) partial[(size_t)blockIdx.x * (kMdot + 1) + i] = acc[i];
     }
 }
 
@@ -184,18 +184,18 @@ static int red_grid(long long N) {
 template <typename S>
 hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
                 hipStream_t st) {
-    // out[0..nv) = <v_i, w>, out[nv] = |w|^2 (real part), in passes of kGS vectors
+    // out[0..nv) = <v_i, w>, out[nv] = |w|^2 (real part), in passes of kMdot vectors
     const int G = red_grid(N);
-    for (int i0 = 0; i0 < nv || i0 == 0; i0 += kGS) {
+    for (int i0 = 0; i0 < nv || i0 == 0; i0 += kMdot) {
         VecList vl;
-        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
+        vl.n = nv - i0 < kMdot ? nv - i0 : kMdot;
         if (vl.n < 0) vl.n = 0;
         for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
         hipLaunchKernelGGL(k_mdot<S>, dim3(G), dim3(kRedThreads), 0, st, vl, static_cast<const S *>(w), partial, N);
         if (vl.n > 0)
-            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kGS + 1, out + i0);
-        if (i0 + kGS >= nv) {
-            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kGS, G, kGS + 1, out + nv);
+            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kMdot + 1, out + i0);
+        if (i0 + kMdot >= nv) {
+            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kMdot, G, kMdot + 1, out + nv);
             break;
         }
     }

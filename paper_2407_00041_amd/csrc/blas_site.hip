@@ -62,22 +62,22 @@ __device__ __forceinline__ void reduce_block(double2 (&v)[NV], double2 *lds) {
 
 }  // namespace
 
-// partial[blk][i] = sum over the group's sites of v_i^H w (i < n), [kGS] = |w|^2
+// partial[blk][i] = sum over the group's sites of v_i^H w (i < n), [kGSSite] = |w|^2
 template <int P>
 __global__ __launch_bounds__(kRedThreads) void k_site_mdot(VecList vl, const void *__restrict__ w,
                                                             double2 *__restrict__ partial, const double2 *hdr, int V) {
     if (hdr && hdr[0].y == 0.0) return;
-    __shared__ double2 lds[(kGS + 1) * kRedThreads];
-    double2 acc[kGS + 1];
+    __shared__ double2 lds[(kGSSite + 1) * kRedThreads];
+    double2 acc[kGSSite + 1];
 #pragma unroll
-    for (int i = 0; i <= kGS; i++) acc[i] = make_double2(0, 0);
+    for (int i = 0; i <= kGSSite; i++) acc[i] = make_double2(0, 0);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < V; s += gridDim.x * blockDim.x) {
         double2 wv[12];
         SiteIO<P>::load(w, V, s, wv);
 #pragma unroll
-        for (int k = 0; k < 12; k++) acc[kGS].x += wv[k].x * wv[k].x + wv[k].y * wv[k].y;
+        for (int k = 0; k < 12; k++) acc[kGSSite].x += wv[k].x * wv[k].x + wv[k].y * wv[k].y;
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
+        for (int i = 0; i < kGSSite; i++) {
             if (i < vl.n) {
                 double2 vv[12];
                 SiteIO<P>::load(vl.v[i], V, s, vv);
@@ -89,10 +89,10 @@ __global__ __launch_bounds__(kRedThreads) void k_site_mdot(VecList vl, const voi
             }
         }
     }
-    reduce_block<kGS + 1>(acc, lds);
+    reduce_block<kGSSite + 1>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i <= kGS; i++) partial[(size_t)blockIdx.x * (kGS + 1) + i] = acc[i];
+        for (int i = 0; i <= kGSSite; i++) partial[(size_t)blockIdx.x * (kGSSite + 1) + i] = acc[i];
     }
 }
 
@@ -107,14 +107,14 @@ __global__ __launch_bounds__(kRedThreads) void k_site_axpy(VecList vl, const dou
     __shared__ double2 lds[kRedThreads];
     const double f = (hdr && apply_f) ? hdr[1].x : 1.0;
     double2 nrm[1] = {make_double2(0, 0)};
-    double2 c[kGS];
+    double2 c[kGSSite];
 #pragma unroll
-    for (int i = 0; i < kGS; i++) c[i] = i < vl.n ? coef[i] : make_double2(0, 0);
+    for (int i = 0; i < kGSSite; i++) c[i] = i < vl.n ? coef[i] : make_double2(0, 0);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < V; s += gridDim.x * blockDim.x) {
         double2 wv[12];
         SiteIO<P>::load(w, V, s, wv);
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
+        for (int i = 0; i < kGSSite; i++) {
             if (i < vl.n) {
                 double2 vv[12];
                 SiteIO<P>::load(vl.v[i], V, s, vv);
@@ -151,17 +151,17 @@ __global__ __launch_bounds__(kRedThreads) void k_site_scale(const void *__restri
 }
 
 // x (native FP64) = keep * x + sum_{i < n} coef[i] z_i, z_i of precision P,
-// n = min(kGS, count - i0) with count = hdr[0].x (device coefficients)
+// n = min(kGSSite, count - i0) with count = hdr[0].x (device coefficients)
 template <int P>
 __global__ __launch_bounds__(kRedThreads) void k_site_combine(VecList vl, const double2 *__restrict__ coef,
                                                                const double2 *hdr, int i0, double2 *__restrict__ x,
                                                                int V) {
     const int count = (int)hdr[0].x;
-    const int n = count - i0 < kGS ? count - i0 : kGS;
+    const int n = count - i0 < kGSSite ? count - i0 : kGSSite;
     if (i0 > 0 && n <= 0) return;
-    double2 c[kGS];
+    double2 c[kGSSite];
 #pragma unroll
-    for (int i = 0; i < kGS; i++) c[i] = i < n ? coef[i] : make_double2(0, 0);
+    for (int i = 0; i < kGSSite; i++) c[i] = i < n ? coef[i] : make_double2(0, 0);
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < V; s += gridDim.x * blockDim.x) {
         double2 xv[12];
         if (i0 > 0) {
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kRedThreads) void k_site_combine(VecList vl, const 
             for (int k = 0; k < 12; k++) xv[k] = make_double2(0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
+        for (int i = 0; i < kGSSite; i++) {
             if (i < n) {
                 double2 zv[12];
                 SiteIO<P>::load(vl.v[i], V, s, zv);
@@ -197,16 +197,16 @@ template <int P>
 static hipError_t site_mdot_p(const void *const *v, int nv, const void *w, int V, double2 *partial, double2 *out,
                               const double2 *hdr, hipStream_t st) {
     const int G = site_grid(V);
-    for (int i0 = 0;; i0 += kGS) {
+    for (int i0 = 0;; i0 += kGSSite) {
         VecList vl;
-        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
+        vl.n = nv - i0 < kGSSite ? nv - i0 : kGSSite;
         if (vl.n < 0) vl.n = 0;
-        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        for (int i = 0; i < kGSSite; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
         hipLaunchKernelGGL(k_site_mdot<P>, dim3(G), dim3(kRedThreads), 0, st, vl, w, partial, hdr, V);
         if (vl.n > 0)
-            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kGS + 1, out + i0);
-        if (i0 + kGS >= nv) {
-            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kGS, G, kGS + 1, out + nv);
+            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kGSSite + 1, out + i0);
+        if (i0 + kGSSite >= nv) {
+            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kGSSite, G, kGSSite + 1, out + nv);
             break;
         }
     }
@@ -217,11 +217,11 @@ template <int P>
 static hipError_t site_axpy_p(const void *const *v, int nv, const double2 *coef, void *w, int V, double2 *partial,
                               double2 *norm_out, const double2 *hdr, hipStream_t st) {
     const int G = site_grid(V);
-    for (int i0 = 0; i0 < nv; i0 += kGS) {
+    for (int i0 = 0; i0 < nv; i0 += kGSSite) {
         VecList vl;
-        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
-        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
-        const bool last = i0 + kGS >= nv;
+        vl.n = nv - i0 < kGSSite ? nv - i0 : kGSSite;
+        for (int i = 0; i < kGSSite; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        const bool last = i0 + kGSSite >= nv;
         hipLaunchKernelGGL(k_site_axpy<P>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, w,
                            (last && norm_out) ? partial : (double2 *)nullptr, hdr, last ? 1 : 0, V);
         if (last && norm_out)
@@ -233,14 +233,14 @@ static hipError_t site_axpy_p(const void *const *v, int nv, const double2 *coef,
 template <int P>
 static hipError_t site_combine_p(const void *const *z, int nmax, const double2 *coef, const double2 *hdr, double2 *x,
                                  int V, hipStream_t st) {
-    for (int i0 = 0;; i0 += kGS) {
+    for (int i0 = 0;; i0 += kGSSite) {
         VecList vl;
-        vl.n = nmax - i0 < kGS ? nmax - i0 : kGS;
+        vl.n = nmax - i0 < kGSSite ? nmax - i0 : kGSSite;
         if (vl.n < 0) vl.n = 0;
-        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
+        for (int i = 0; i < kGSSite; i++) vl.v[i] = i < vl.n ? z[i0 + i] : nullptr;
         hipLaunchKernelGGL(k_site_combine<P>, dim3(site_grid(V)), dim3(kRedThreads), 0, st, vl, coef + i0, hdr, i0,
                            x, V);
-        if (i0 + kGS >= nmax) break;
+        if (i0 + kGSSite >= nmax) break;
     }
     return hipGetLastError();
 }

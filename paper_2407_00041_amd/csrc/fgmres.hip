@@ -57,6 +57,8 @@ namespace {
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
+static_assert(kGSSite <= kMdot, "partial sums of a pass are laid out kMdot + 1 wide");
+
 // Device-side state of one right-hand side's inner GMRES cycle (carved from
 // its scalar block).
 struct InnerDev {
@@ -232,7 +234,7 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     L.f16 = align256(field_rhs_bytes(WDIRAC_F16S, V));
     const int m = p->restart, mi = p->mode == FGMRES_F64 ? 0 : p->inner_restart;
     const int kmax = kmax_of(p);
-    L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kGS + 1) + 3 * (size_t)kmax + 8));
+    L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kMdot + 1) + 3 * (size_t)kmax + 8));
     if (p->mode != FGMRES_F64) L.scal += align256(inner_state_bytes(mi));
     L.per_rhs = (size_t)(m + 2) * L.f64 + L.scal;  // V[0..m], w
     if (p->mode != FGMRES_F64) {
@@ -539,13 +541,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
         char *s = take(L.scal);
         r.partial = reinterpret_cast<double2 *>(s);
-        r.hcol = r.partial + (size_t)kRedBlocks * (kGS + 1);
+        r.hcol = r.partial + (size_t)kRedBlocks * (kMdot + 1);
         r.coef = r.hcol + kmax;
         r.hcol2 = r.coef + kmax;
         r.nrm = r.hcol2 + kmax;
         char *end = reinterpret_cast<char *>(r.nrm + 1);
         if (mixed) {
-            char *ib = s + align256(sizeof(double2) * ((size_t)kRedBlocks * (kGS + 1) + 3 * (size_t)kmax + 8));
+            char *ib = s + align256(sizeof(double2) * ((size_t)kRedBlocks * (kMdot + 1) + 3 * (size_t)kmax + 8));
             r.in = carve_inner(ib, p->inner_restart, r.hcol);
             end = ib + inner_state_bytes(p->inner_restart);
         }
