@@ -51,7 +51,9 @@ def test_oracle_reproduces_fgmres_fixture():
     x, info = oracle.fgmres(lambda v: oracle.dirac_apply(dims, U, v, g["m0"], g["csw"]), b, m=g["restart"],
                             tol=g["tol"], maxit=500, history=hist)
     assert info["applies"] == g["applies"]
-    assert np.allclose(hist, g["hist"], rtol=1e-10, atol=0)
+    # the residual estimates come from LAPACK least squares, whose rounding
+    # differs between CPUs: relative 1e-8, absolute 1e-13 (of ||r0|| = 1)
+    assert np.allclose(hist, g["hist"], rtol=1e-8, atol=1e-13)
 
 
 @pytest.mark.gpu
