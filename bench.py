@@ -19,7 +19,10 @@ timed steps (reported under "extra"):
     mixed solver (FP64 outer FGMRES(8) whose preconditioner is an inner
     GMRES(10) on the FP16S operator, relative tolerance 0.1), in memory-sized
     waves: wall time, applications and the difference between the two
-    solutions.
+    solutions;
+  * 32^4: FP64 apply rate and plain FP64 FGMRES(20) to 1e-10;
+  * 24^3 x 48: forward + backward through the autograd Function and the force
+    kernel alone.
 The CPU oracle's apply is timed on a bounded slab of sites ("cpu_baseline").
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -206,6 +209,66 @@ def fgmres_run(torch, op, dims, nrhs_total):
             "error_vs_fp64_max": max(errs)}
 
 
+def config32_run(torch, stream):
+    """32^4, c_sw = 1, m0 = -0.3, one right-hand side: the FP64 apply rate and
+    plain FP64 FGMRES(20) to 1e-10 (the 32^4 solver workload)."""
+    import paper_2407_00041_amd as wd
+    from paper_2407_00041_amd import synth
+    dims = (32, 32, 32, 32)
+    V = 32 ** 4
+    U = synth.smooth_links(dims, 1002, device="cuda").cpu().numpy()
+    op = wd.DiracOp(dims, U, -0.3, 1.0, precisions=("f64",), compress_links=True, compress_clover=True)
+    tuned = {"fixed": True} if TUNE_FIXED else op.autotune("f64", 1)
+    x = op.pack(synth.gaussian_spinor(dims, 2000, nrhs=1, device="cuda"), "f64")
+    y = op.empty("f64", 1)
+    ms = time_launches(torch, lambda: op.apply_native(y, x, 1, "f64", stream=stream), 100, 10, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st, rc = op.solve(x, restart=20, tol=1e-10, maxit=3000)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    res = {"dims": list(dims), "apply_ms": ms, "apps_per_s": 1000.0 / ms,
+           "alg_GBps": BYTES_SITE["f64"] * V / (ms * 1e-3) / 1e9, "launch": tuned,
+           "fgmres20_fp64": {"seconds": ts, "applies": st[0]["applies"], "true_residual": st[0]["true_residual"],
+                             "converged": st[0]["converged"], "phase_seconds": {
+                                 k: st[0]["seconds_" + k] for k in ("apply", "precond", "ortho")}}}
+    del op, x, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def differentiation_run(torch):
+    """24^3 x 48, c_sw = 1, FP64: L = Re<eta, D(U) x>; forward plus backward
+    through the autograd Function (dL/dx by the adjoint apply, dL/dU by the
+    force kernel), and the force kernel alone."""
+    import paper_2407_00041_amd as wd
+    from paper_2407_00041_amd import synth
+    from paper_2407_00041_amd.autograd import dirac_apply
+    dims = (48, 24, 24, 24)
+    m0, csw = -0.3, 1.0
+    Ut = synth.smooth_links(dims, 1005, device="cuda")
+    op = wd.DiracOp(dims, Ut.cpu().numpy(), m0, csw, precisions=("f64",))
+    x = synth.gaussian_spinor(dims, 3001, nrhs=1, device="cuda").requires_grad_(True)
+    eta = synth.gaussian_spinor(dims, 3002, nrhs=1, device="cuda")
+    links = Ut.clone().requires_grad_(True)
+
+    def step():
+        y = dirac_apply(x, links, dims, op=op, m0=m0, csw=csw)
+        loss = (eta.conj() * y).sum().real
+        return torch.autograd.grad(loss, (x, links))
+
+    cur = torch.cuda.current_stream()
+    ms_fb = time_launches(torch, step, 10, 2, cur)
+    en = op.pack(eta.detach(), "f64")
+    xn = op.pack(x.detach(), "f64")
+    ms_force = time_launches(torch, lambda: op.force(en, xn, 1), 20, 3, cur)
+    res = {"dims": list(dims), "forward_backward_ms": ms_fb, "force_kernel_ms": ms_force,
+           "note": "forward + backward include the canonical <-> native conversions of the autograd binding"}
+    del op, x, eta, links, en, xn
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline_run(dims, U, psi, m0, csw, target_s=3.0):
     """Oracle apply on a contiguous slab of T-slices (clover rows built first,
     outside the timed call); the slab is sized from a one-slice calibration so
@@ -328,6 +391,14 @@ def main():
         log(f"[bench] batched: {extra['batched']['rhs_applies_per_s']:.0f} RHS-applies/s")
     if not a.no_extra and not a.no_fgmres and a.fgmres_rhs > 0:
         extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs)
+    if not a.no_extra:
+        log("[bench] 32^4: FP64 apply and FGMRES(20)")
+        extra["config_32"] = config32_run(torch, stream)
+        log(f"[bench] 32^4: {extra['config_32']['apply_ms']:.4f} ms/apply, FGMRES(20) "
+            f"{extra['config_32']['fgmres20_fp64']['seconds']:.2f} s")
+        log("[bench] 24^3x48: differentiation")
+        extra["differentiation"] = differentiation_run(torch)
+        log(f"[bench] 24^3x48: forward+backward {extra['differentiation']['forward_backward_ms']:.2f} ms")
 
     res = {
         "metric": "Dirac apps/s & HBM GB/s; mixed vs FP64 FGMRES time to 1e-10 at 48^3x96",
