@@ -304,17 +304,25 @@ int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs,
 
 /* ------------------------------------------------------------------------ */
 /*
- * Link derivative ("force") of L = Re sum_r <eta_r, D(U) x_r> (FP64).
+ * Link derivative ("force") of L = Re sum_r <eta_r, D(U) x_r> (FP64):
+ * the hopping term of Eq. (1.13) and the clover leaves of Eqs. (1.11)-(1.12)
+ * differentiated with respect to each link.
  *   dU  : device [V][4][3][3] complex128 (canonical link layout), written:
  *         F_mu(x) = P_TA(G_mu(x) U_mu(x)^H), P_TA(M) = (M - M^H)/2 -
  *         tr(M - M^H)/6, with G = dL/dRe U + i dL/dIm U, summed over the
  *         nrhs pairs; with raw != 0, G itself is written instead.
  *   eta, x : device native FP64, nrhs fields each.
+ *   work : device workspace of at least dirac_force_workspace_bytes(op)
+ *          bytes (may be NULL when that is 0); it holds the clover
+ *          insertion matrices between the kernel's two passes, so calls that
+ *          overlap must not share it.
  * Includes the clover contribution when csw != 0 and the clover term was
- * built from the links.  Asynchronous.  Errors: EINVAL, EHIP.
+ * built from the links.  Asynchronous.  Errors: EINVAL (null pointer,
+ * nrhs < 1, workspace too small), EHIP.
  */
+size_t dirac_force_workspace_bytes(const dirac_op *op);
 int dirac_force(const dirac_op *op, double *dU, const double *eta, const double *x, int nrhs,
-                int raw, void *stream);
+                int raw, void *work, size_t work_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -211,8 +211,10 @@ class DiracOp:
               stream=None) -> torch.Tensor:
         """dL/dU for L = Re sum <eta, D x>; eta, x native FP64.  [V, 4, 3, 3] c128."""
         out = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=x.device)
+        nb = int(self.lib.dirac_force_workspace_bytes(self.handle))
+        work = torch.empty(max(nb, 1), dtype=torch.uint8, device=x.device)
         check(self.lib.dirac_force(self.handle, _ptr(out), _ptr(eta), _ptr(x), int(nrhs), int(bool(raw)),
-                                   _stream(stream)), "dirac_force")
+                                   _ptr(work), nb, _stream(stream)), "dirac_force")
         return out
 
 

@@ -62,7 +62,8 @@ SIGNATURES = {
     "fgmres_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(FgmresParams), _I]),
     "fgmres_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(FgmresParams),
                           ctypes.POINTER(FgmresStats), _P, ctypes.c_size_t, _P]),
-    "dirac_force": (_I, [_P, _P, _P, _P, _I, _I, _P]),
+    "dirac_force_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "dirac_force": (_I, [_P, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

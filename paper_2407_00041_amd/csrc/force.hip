@@ -6,26 +6,36 @@
 // site y and its adjoint multiplies x(y) in the backward hop of site y+rho:
 //   G += -1/2 sum_s eta(y)_s q_s^H,   q = (I - gamma_rho) x(y+rho)
 //   G += -1/2 sum_s p_s eta(y+rho)_s^H, p = (I + gamma_rho) x(y)
-// (times -1 for a link crossing the anti-periodic T boundary).
+// (times -1 for a link crossing the anti-periodic T boundary).  With
+// gamma = [[0, B], [B^H, 0]], q = (h, -B^H h) for h = u - B d, and
+// p = (k, B^H k) for k = u + B d, so both sums reduce to half-spinor outer
+// products:  sum_s eta_s q_s^H = sum_j (eta_u - B eta_d)_j h_j^H and
+// sum_s p_s eta'_s^H = sum_j k_j (eta'_u + B eta'_d)_j^H.
 //
 // Clover (Eqs. (1.11)-(1.12)): with Q_nu,mu = Q_mu,nu^H the clover part of L
 // is sum_x sum_{mu<nu} (-c_sw/16) Re tr(Q_mu,nu(x) M_mu,nu(x)) with
 // M = K - K^H, K_{ba}(x) = sum_{al,be} (gamma_mu gamma_nu)_{al,be} x_{be b}
-// conj(eta_{al a}); Re tr(Q_nu,mu M_nu,mu) = Re tr(Q_mu,nu M_mu,nu), so every
-// plane nu != rho can be taken in the orientation (rho, nu).  Each leaf of
-// Eq. (1.12) is the counter-clockwise plaquette loop starting at its base
-// corner, and U_rho(y) lies on two plaquettes of each plane: the one above
-// (corners y, y+rho, y+rho+nu, y+nu; the link un-daggered) and the one below
-// (corners y-nu, y-nu+rho, y+rho, y; the link daggered).  Cutting each of the
-// four corner loops open at the link gives, with kappa = -c_sw/16,
+// conj(eta_{al a}) summed over right-hand sides; M_nu,mu = -M_mu,nu since
+// distinct gammas anticommute.  U_rho(y) lies on two plaquettes of each plane
+// (rho, nu): the one above (corners y, y+rho, y+rho+nu, y+nu; the link
+// un-daggered) and the one below (corners y-nu, y-nu+rho, y+rho, y; the link
+// daggered).  Cutting each of the four corner loops of Eq. (1.12) open at the
+// link gives, with kappa = -c_sw/16,
 //   above: G += kappa [S M(y) + M(y+rho) S + U_nu(y+rho) M(y+rho+nu) W
 //                     + U_nu(y+rho) U_rho(y+nu)^H M(y+nu) U_nu(y)^H]^H,
-//          S = U_nu(y+rho) U_rho(y+nu)^H U_nu(y)^H, W = U_rho(y+nu)^H U_nu(y)^H
+//          S = U_nu(y+rho) W, W = U_rho(y+nu)^H U_nu(y)^H
 //   below: G += kappa [U_nu(a)^H M(a) U_rho(a) U_nu(b) + U_nu(a)^H U_rho(a)
 //                     M(b) U_nu(b) + R M(y+rho) + M(y) R],
 //          a = y-nu, b = y-nu+rho, R = U_nu(a)^H U_rho(a) U_nu(b)
 // (for P = A U B the derivative of Re tr(P M) is (B M A)^H, for
 // P = A U^H B it is B M A).
+//
+// Two passes: force_insert_kernel forms M_mu,nu(x) for the six planes once
+// per site (anti-Hermitian, 9 reals each), force_link_kernel then gathers
+// them with the links around each plaquette.  One work-group covers 64 sites;
+// its wave w computes the links of direction w, so every branch on the
+// direction is wave-uniform, and the work-group's 64 x 4 link matrices are
+// written out through LDS in contiguous order.
 //
 // Output: P_TA(G U^H) = (M - M^H)/2 - tr(M - M^H)/6 (the su(3) projection),
 // or G itself (raw), canonical [V][4][3][3] complex128.
@@ -37,15 +47,26 @@ namespace {
 
 using C = cx<double>;
 
+constexpr int kPlanes = 6;        // (T,Z) (T,Y) (T,X) (Z,Y) (Z,X) (Y,X)
+constexpr int kInsertVec = 5;     // double2 per plane and site
+constexpr int kLinkSites = 64;    // sites per work-group of force_link_kernel
+constexpr int kLdsPitch = 37;     // double2 per site in the LDS staging (36 + 1)
+
 struct M3 {
     C a[9];
 };
 
-__device__ __forceinline__ M3 mzero() {
-    M3 m;
-#pragma unroll
-    for (int e = 0; e < 9; e++) m.a[e] = mk<double>(0, 0);
-    return m;
+__device__ __forceinline__ C cz() { return mk<double>(0, 0); }
+__device__ __forceinline__ C neg(C v) { return {-v.r, -v.i}; }
+__device__ __forceinline__ C mul_i(C v) { return {-v.i, v.r}; }
+__device__ __forceinline__ C mul_mi(C v) { return {v.i, -v.r}; }
+// acc + conj(a) * b
+__device__ __forceinline__ C cjfma(C acc, C a, C b) {
+    acc.r = fma(a.r, b.r, acc.r);
+    acc.r = fma(a.i, b.i, acc.r);
+    acc.i = fma(a.r, b.i, acc.i);
+    acc.i = fma(-a.i, b.r, acc.i);
+    return acc;
 }
 
 __device__ __forceinline__ M3 mmul(const M3 &x, const M3 &y) {
@@ -54,236 +75,353 @@ __device__ __forceinline__ M3 mmul(const M3 &x, const M3 &y) {
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            C s = mk<double>(0, 0);
-#pragma unroll
-            for (int k = 0; k < 3; k++) s = cfma(s, x.a[3 * i + k], y.a[3 * k + j]);
-            m.a[3 * i + j] = s;
+            C s = cmul(x.a[3 * i], y.a[j]);
+            s = cfma(s, x.a[3 * i + 1], y.a[3 + j]);
+            m.a[3 * i + j] = cfma(s, x.a[3 * i + 2], y.a[6 + j]);
         }
     return m;
 }
 
-__device__ __forceinline__ M3 mdag(const M3 &x) {
-    M3 m;
+// acc += x * y
+__device__ __forceinline__ void mmul_acc(M3 &acc, const M3 &x, const M3 &y) {
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++) m.a[3 * i + j] = {x.a[3 * j + i].r, -x.a[3 * j + i].i};
-    return m;
-}
-
-__device__ __forceinline__ void madd(M3 &acc, const M3 &x, double s) {
+        for (int j = 0; j < 3; j++)
 #pragma unroll
-    for (int e = 0; e < 9; e++) acc.a[e] = acc.a[e] + s * x.a[e];
+            for (int k = 0; k < 3; k++) acc.a[3 * i + j] = cfma(acc.a[3 * i + j], x.a[3 * i + k], y.a[3 * k + j]);
 }
 
 __device__ __forceinline__ M3 link(const double2 *U, int site, int mu) {
     M3 m;
-    const double2 *p = U + (size_t)(4 * site + mu) * 9;
+    const double2 *p = U + ((size_t)4 * site + mu) * 9;
 #pragma unroll
     for (int e = 0; e < 9; e++) m.a[e] = {p[e].x, p[e].y};
     return m;
 }
 
-__device__ __forceinline__ int step(const Geom &g, int site, int mu, int d) {
-    int c[4];
-    int r = site;
-    c[3] = r % g.n[3]; r /= g.n[3];
-    c[2] = r % g.n[2]; r /= g.n[2];
-    c[1] = r % g.n[1];
-    c[0] = r / g.n[1];
-    c[mu] = (c[mu] + d + g.n[mu]) % g.n[mu];
-    return ((c[0] * g.n[1] + c[1]) * g.n[2] + c[2]) * g.n[3] + c[3];
-}
-
-// B_mu of gamma_mu = [[0, B], [B^H, 0]] (row-major 2x2)
-__device__ __forceinline__ void bspin(int mu, C B[4]) {
-    for (int k = 0; k < 4; k++) B[k] = mk<double>(0, 0);
-    if (mu == 0) { B[0] = mk<double>(1, 0); B[3] = mk<double>(1, 0); }
-    else if (mu == 1) { B[0] = mk<double>(0, -1); B[3] = mk<double>(0, 1); }
-    else if (mu == 2) { B[1] = mk<double>(-1, 0); B[2] = mk<double>(1, 0); }
-    else { B[1] = mk<double>(0, -1); B[2] = mk<double>(0, -1); }
-}
-
-__device__ __forceinline__ void load12(const double2 *f, int V, int s, C v[12]) {
-#pragma unroll
-    for (int k = 0; k < 12; k++) {
-        double2 a = f[(size_t)k * V + s];
-        v[k] = {a.x, a.y};
-    }
-}
-
-// M(x) = K - K^H for the plane (rho, nu), summed over right-hand sides
-__device__ M3 mcorner(const double2 *eta, const double2 *x, size_t rhs_stride, int nrhs, int V, int s,
-                      const C P[2][4]) {
-    M3 K = mzero();
-    for (int r = 0; r < nrhs; r++) {
-        C e[12], p[12];
-        load12(eta + r * rhs_stride, V, s, e);
-        load12(x + r * rhs_stride, V, s, p);
-        for (int blk = 0; blk < 2; blk++)
-            for (int al = 0; al < 2; al++)
-                for (int be = 0; be < 2; be++) {
-                    const C g = P[blk][2 * al + be];
-                    if (g.r == 0.0 && g.i == 0.0) continue;
-                    for (int b = 0; b < 3; b++)
-                        for (int a = 0; a < 3; a++) {
-                            // K_{ba} += g x_{be b} conj(eta_{al a})
-                            C t = cjmul(e[6 * blk + 3 * al + a], p[6 * blk + 3 * be + b]);
-                            K.a[3 * b + a] = cfma(K.a[3 * b + a], g, t);
-                        }
-                }
-    }
-    M3 M;
+__device__ __forceinline__ M3 link_dag(const double2 *U, int site, int mu) {
+    M3 m;
+    const double2 *p = U + ((size_t)4 * site + mu) * 9;
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++)
-            M.a[3 * i + j] = {K.a[3 * i + j].r - K.a[3 * j + i].r, K.a[3 * i + j].i + K.a[3 * j + i].i};
-    return M;
+        for (int j = 0; j < 3; j++) m.a[3 * j + i] = {p[3 * i + j].x, -p[3 * i + j].y};
+    return m;
+}
+
+// Half-spinor products with the 2x2 blocks of gamma_mu = [[0, B], [B^H, 0]]:
+// B_T = 1, B_Z = diag(-i, i), B_Y = [[0, -1], [1, 0]], B_X = [[0, -i], [-i, 0]].
+template <int MU> __device__ __forceinline__ void bmul(C v0, C v1, C &w0, C &w1) {
+    if constexpr (MU == 0) { w0 = v0; w1 = v1; }
+    else if constexpr (MU == 1) { w0 = mul_mi(v0); w1 = mul_i(v1); }
+    else if constexpr (MU == 2) { w0 = neg(v1); w1 = v0; }
+    else { w0 = mul_mi(v1); w1 = mul_mi(v0); }
+}
+template <int MU> __device__ __forceinline__ void bhmul(C v0, C v1, C &w0, C &w1) {
+    if constexpr (MU == 0) { w0 = v0; w1 = v1; }
+    else if constexpr (MU == 1) { w0 = mul_i(v0); w1 = mul_mi(v1); }
+    else if constexpr (MU == 2) { w0 = v1; w1 = neg(v0); }
+    else { w0 = mul_i(v1); w1 = mul_i(v0); }
+}
+
+__device__ __forceinline__ C ld(const double2 *f, int V, int k, int s) {
+    const double2 a = f[(size_t)k * V + s];
+    return {a.x, a.y};
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: M_mu,nu(s) for one plane, summed over right-hand sides
+template <int MU, int NU>
+__device__ __forceinline__ void insert_plane(double2 *__restrict__ out, const double2 *__restrict__ eta,
+                                             const double2 *__restrict__ x, int nrhs, int V, int s, int plane) {
+    // K = sum_blk sum_be x_{blk,be} (x) conj(zeta_{blk,be}) with zeta = P_blk^H eta_blk for the chiral blocks
+    // P_0 = B_mu B_nu^H and P_1 = B_mu^H B_nu of gamma_mu gamma_nu, i.e. zeta_0 = B_nu (B_mu^H eta_0) and
+    // zeta_1 = B_nu^H (B_mu eta_1).
+    M3 K;
+#pragma unroll
+    for (int e = 0; e < 9; e++) K.a[e] = cz();
+    const size_t rs = (size_t)12 * V;
+    for (int r = 0; r < nrhs; r++) {
+        const double2 *er = eta + r * rs, *xr = x + r * rs;
+#pragma unroll
+        for (int blk = 0; blk < 2; blk++) {
+            C z[2][3], xv[2][3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const C e0 = ld(er, V, 6 * blk + a, s), e1 = ld(er, V, 6 * blk + 3 + a, s);
+                C t0, t1;
+                if (blk == 0) {
+                    bhmul<MU>(e0, e1, t0, t1);
+                    bmul<NU>(t0, t1, z[0][a], z[1][a]);
+                } else {
+                    bmul<MU>(e0, e1, t0, t1);
+                    bhmul<NU>(t0, t1, z[0][a], z[1][a]);
+                }
+                xv[0][a] = ld(xr, V, 6 * blk + a, s);
+                xv[1][a] = ld(xr, V, 6 * blk + 3 + a, s);
+            }
+#pragma unroll
+            for (int be = 0; be < 2; be++)
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+#pragma unroll
+                    for (int a = 0; a < 3; a++) K.a[3 * b + a] = cjfma(K.a[3 * b + a], z[be][a], xv[be][b]);
+        }
+    }
+    // M = K - K^H: imaginary diagonal and upper triangle
+    double2 *o = out + (size_t)plane * kInsertVec * V + s;
+    const double m00 = 2.0 * K.a[0].i, m11 = 2.0 * K.a[4].i, m22 = 2.0 * K.a[8].i;
+    const C m01 = {K.a[1].r - K.a[3].r, K.a[1].i + K.a[3].i};
+    const C m02 = {K.a[2].r - K.a[6].r, K.a[2].i + K.a[6].i};
+    const C m12 = {K.a[5].r - K.a[7].r, K.a[5].i + K.a[7].i};
+    o[0] = make_double2(m00, m11);
+    o[(size_t)V] = make_double2(m22, m01.r);
+    o[(size_t)2 * V] = make_double2(m01.i, m02.r);
+    o[(size_t)3 * V] = make_double2(m02.i, m12.r);
+    o[(size_t)4 * V] = make_double2(m12.i, 0.0);
+}
+
+__device__ __forceinline__ M3 load_insert(const double2 *__restrict__ M, int V, int plane, int s) {
+    const double2 *p = M + (size_t)plane * kInsertVec * V + s;
+    const double2 a = p[0], b = p[(size_t)V], c = p[(size_t)2 * V], d = p[(size_t)3 * V], e = p[(size_t)4 * V];
+    M3 m;
+    m.a[0] = {0.0, a.x};
+    m.a[4] = {0.0, a.y};
+    m.a[8] = {0.0, b.x};
+    m.a[1] = {b.y, c.x};
+    m.a[2] = {c.y, d.x};
+    m.a[5] = {d.y, e.x};
+    m.a[3] = {-b.y, c.x};
+    m.a[6] = {-c.y, d.x};
+    m.a[7] = {-d.y, e.x};
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// pass 2 helpers
+struct Site {
+    int c[4];
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ int index_of(const Geom &g, const Site &p, int mu1, int d1, int mu2, int d2) {
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        int v = p.c[k];
+        if (k == mu1) v = wrap(v + d1, g.n[k]);
+        if (k == mu2) v = wrap(v + d2, g.n[k]);
+        s += v * g.stride[k];
+    }
+    return s;
+}
+
+__device__ __forceinline__ int plane_of(int mu, int nu) {
+    // mu < nu
+    return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
+}
+
+template <int RHO>
+__device__ M3 link_force(const double2 *__restrict__ U, const double2 *__restrict__ Mins,
+                         const double2 *__restrict__ eta, const double2 *__restrict__ x, int nrhs, const Geom &g,
+                         int apbc, int with_clover, double csw, int y, const Site &p) {
+    const int V = g.V;
+    M3 G;
+#pragma unroll
+    for (int e = 0; e < 9; e++) G.a[e] = cz();
+
+    // hopping
+    {
+        const int yp = index_of(g, p, RHO, 1, -1, 0);
+        const size_t rs = (size_t)12 * V;
+        for (int r = 0; r < nrhs; r++) {
+            const double2 *er = eta + r * rs, *xr = x + r * rs;
+            // sum_j (eta_u - B eta_d)(y)_j h_j^H,  h = x_u - B x_d at y + rho
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                C A[2][3], H[2][3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    C b0, b1;
+                    if (t == 0) {
+                        bmul<RHO>(ld(er, V, 6 + a, y), ld(er, V, 9 + a, y), b0, b1);
+                        A[0][a] = ld(er, V, a, y) - b0;
+                        A[1][a] = ld(er, V, 3 + a, y) - b1;
+                        bmul<RHO>(ld(xr, V, 6 + a, yp), ld(xr, V, 9 + a, yp), b0, b1);
+                        H[0][a] = ld(xr, V, a, yp) - b0;
+                        H[1][a] = ld(xr, V, 3 + a, yp) - b1;
+                    } else {
+                        // sum_j k_j (eta'_u + B eta'_d)_j^H, k = x_u + B x_d at y, eta' = eta(y + rho)
+                        bmul<RHO>(ld(xr, V, 6 + a, y), ld(xr, V, 9 + a, y), b0, b1);
+                        A[0][a] = ld(xr, V, a, y) + b0;
+                        A[1][a] = ld(xr, V, 3 + a, y) + b1;
+                        bmul<RHO>(ld(er, V, 6 + a, yp), ld(er, V, 9 + a, yp), b0, b1);
+                        H[0][a] = ld(er, V, a, yp) + b0;
+                        H[1][a] = ld(er, V, 3 + a, yp) + b1;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+#pragma unroll
+                    for (int a = 0; a < 3; a++)
+#pragma unroll
+                        for (int b = 0; b < 3; b++) G.a[3 * a + b] = cjfma(G.a[3 * a + b], H[j][b], A[j][a]);
+            }
+        }
+        const double sgn = (apbc && RHO == 0 && p.c[0] == g.n[0] - 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int e = 0; e < 9; e++) G.a[e] = (-0.5 * sgn) * G.a[e];
+    }
+
+    if (!with_clover) return G;
+    const double kappa = -csw / 16.0;
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == RHO) continue;
+        const int plane = RHO < nu ? plane_of(RHO, nu) : plane_of(nu, RHO);
+        const double kap = RHO < nu ? kappa : -kappa;
+        const int yr = index_of(g, p, RHO, 1, -1, 0);
+        const int yn = index_of(g, p, nu, 1, -1, 0);
+        const int yrn = index_of(g, p, RHO, 1, nu, 1);
+        const int ya = index_of(g, p, nu, -1, -1, 0);
+        const int yb = index_of(g, p, nu, -1, RHO, 1);
+        // plaquette above: T = M(y+rho) S + U_nu(y+rho) X, S = U_nu(y+rho) W,
+        // X = U_rho(y+nu)^H M(y+nu) U_nu(y)^H + W M(y) + M(y+rho+nu) W
+        {
+            const M3 W = mmul(link_dag(U, yn, RHO), link_dag(U, y, nu));
+            M3 X = mmul(link_dag(U, yn, RHO), mmul(load_insert(Mins, V, plane, yn), link_dag(U, y, nu)));
+            mmul_acc(X, W, load_insert(Mins, V, plane, y));
+            mmul_acc(X, load_insert(Mins, V, plane, yrn), W);
+            const M3 A = link(U, yr, nu);
+            const M3 S = mmul(A, W);
+            M3 T = mmul(A, X);
+            mmul_acc(T, load_insert(Mins, V, plane, yr), S);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    const C t = T.a[3 * j + i];
+                    G.a[3 * i + j].r = fma(kap, t.r, G.a[3 * i + j].r);
+                    G.a[3 * i + j].i = fma(-kap, t.i, G.a[3 * i + j].i);
+                }
+        }
+        // plaquette below: T = U_nu(a)^H Z + R M(y+rho) + M(y) R, R = U_nu(a)^H U_rho(a) U_nu(b),
+        // Z = (M(a) U_rho(a) + U_rho(a) M(b)) U_nu(b)
+        {
+            M3 Z = mmul(load_insert(Mins, V, plane, ya), link(U, ya, RHO));
+            mmul_acc(Z, link(U, ya, RHO), load_insert(Mins, V, plane, yb));
+            Z = mmul(Z, link(U, yb, nu));
+            const M3 E = mmul(link(U, ya, RHO), link(U, yb, nu));
+            const M3 a = link_dag(U, ya, nu);
+            M3 T = mmul(a, Z);
+            const M3 R = mmul(a, E);
+            mmul_acc(T, R, load_insert(Mins, V, plane, yr));
+            mmul_acc(T, load_insert(Mins, V, plane, y), R);
+#pragma unroll
+            for (int e = 0; e < 9; e++) {
+                G.a[e].r = fma(kap, T.a[e].r, G.a[e].r);
+                G.a[e].i = fma(kap, T.a[e].i, G.a[e].i);
+            }
+        }
+    }
+    return G;
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(128) void force_kernel(double2 *__restrict__ out, const double2 *__restrict__ U,
-                                                    const double2 *__restrict__ eta, const double2 *__restrict__ x,
-                                                    int nrhs, Geom g, int apbc, int with_clover, double csw, int raw) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= 4 * g.V) return;
-    const int y = tid >> 2, rho = tid & 3;
-    const int V = g.V;
-    const size_t rs = (size_t)12 * V;  // complex numbers per right-hand side
-    M3 G = mzero();
+__global__ __launch_bounds__(256) void force_insert_kernel(double2 *__restrict__ out, const double2 *__restrict__ eta,
+                                                           const double2 *__restrict__ x, int nrhs, int V) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    insert_plane<0, 1>(out, eta, x, nrhs, V, s, 0);
+    insert_plane<0, 2>(out, eta, x, nrhs, V, s, 1);
+    insert_plane<0, 3>(out, eta, x, nrhs, V, s, 2);
+    insert_plane<1, 2>(out, eta, x, nrhs, V, s, 3);
+    insert_plane<1, 3>(out, eta, x, nrhs, V, s, 4);
+    insert_plane<2, 3>(out, eta, x, nrhs, V, s, 5);
+}
 
-    // hopping
-    {
-        const int yp = step(g, y, rho, +1);
-        int c0 = y / g.stride[0];
-        const double sgn = (apbc && rho == 0 && c0 == g.n[0] - 1) ? -1.0 : 1.0;
-        C B[4];
-        bspin(rho, B);
-        for (int r = 0; r < nrhs; r++) {
-            C ey[12], eyp[12], xy[12], xyp[12];
-            load12(eta + r * rs, V, y, ey);
-            load12(eta + r * rs, V, yp, eyp);
-            load12(x + r * rs, V, y, xy);
-            load12(x + r * rs, V, yp, xyp);
-            // q = (I - gamma) x(y+rho) = (h, -B^H h), h = u - B d
-            // p = (I + gamma) x(y)     = (k,  B^H k), k = u + B d
-            C q[12], pp[12];
-            for (int c = 0; c < 3; c++) {
-                C d0 = xyp[6 + c], d1 = xyp[9 + c];
-                C bd0 = cmul(B[0], d0) + cmul(B[1], d1), bd1 = cmul(B[2], d0) + cmul(B[3], d1);
-                C h0 = xyp[c] - bd0, h1 = xyp[3 + c] - bd1;
-                q[c] = h0;
-                q[3 + c] = h1;
-                // B^H h: (B^H)_{ij} = conj(B_{ji})
-                q[6 + c] = -1.0 * (cjmul(B[0], h0) + cjmul(B[2], h1));
-                q[9 + c] = -1.0 * (cjmul(B[1], h0) + cjmul(B[3], h1));
-                C e0 = xy[6 + c], e1 = xy[9 + c];
-                C be0 = cmul(B[0], e0) + cmul(B[1], e1), be1 = cmul(B[2], e0) + cmul(B[3], e1);
-                C k0 = xy[c] + be0, k1 = xy[3 + c] + be1;
-                pp[c] = k0;
-                pp[3 + c] = k1;
-                pp[6 + c] = cjmul(B[0], k0) + cjmul(B[2], k1);
-                pp[9 + c] = cjmul(B[1], k0) + cjmul(B[3], k1);
-            }
-            for (int s = 0; s < 4; s++)
-                for (int a = 0; a < 3; a++)
-                    for (int b = 0; b < 3; b++) {
-                        // eta(y)_s q_s^H and p_s eta(y+rho)_s^H
-                        C t1 = cjmul(q[3 * s + b], ey[3 * s + a]);
-                        C t2 = cjmul(eyp[3 * s + b], pp[3 * s + a]);
-                        G.a[3 * a + b] = G.a[3 * a + b] + (-0.5 * sgn) * (t1 + t2);
-                    }
+__global__ __launch_bounds__(256, 2) void force_link_kernel(double2 *__restrict__ out, const double2 *__restrict__ U,
+                                                         const double2 *__restrict__ Mins,
+                                                         const double2 *__restrict__ eta,
+                                                         const double2 *__restrict__ x, int nrhs, Geom g, int apbc,
+                                                         int with_clover, double csw, int raw) {
+    __shared__ double2 stage[kLinkSites * kLdsPitch];
+    const int lane = threadIdx.x & 63, rho = threadIdx.x >> 6;
+    const int base = blockIdx.x * kLinkSites;
+    const int y = base + lane;
+    if (y < g.V) {
+        Site p;
+        int r = y;
+        p.c[3] = r % g.n[3]; r /= g.n[3];
+        p.c[2] = r % g.n[2]; r /= g.n[2];
+        p.c[1] = r % g.n[1];
+        p.c[0] = r / g.n[1];
+        M3 G;
+        switch (rho) {
+        case 0: G = link_force<0>(U, Mins, eta, x, nrhs, g, apbc, with_clover, csw, y, p); break;
+        case 1: G = link_force<1>(U, Mins, eta, x, nrhs, g, apbc, with_clover, csw, y, p); break;
+        case 2: G = link_force<2>(U, Mins, eta, x, nrhs, g, apbc, with_clover, csw, y, p); break;
+        default: G = link_force<3>(U, Mins, eta, x, nrhs, g, apbc, with_clover, csw, y, p); break;
         }
-    }
-
-    // clover leaves
-    if (with_clover) {
-        const double kappa = -csw / 16.0;
-        C Br[4];
-        bspin(rho, Br);
-        const M3 Ur = link(U, y, rho);
-        for (int nu = 0; nu < 4; nu++) {
-            if (nu == rho) continue;
-            // spin blocks of gamma_rho gamma_nu: upper B_rho B_nu^H, lower B_rho^H B_nu
-            C Bn[4], P[2][4];
-            bspin(nu, Bn);
-            for (int i = 0; i < 2; i++)
-                for (int j = 0; j < 2; j++) {
-                    C su = mk<double>(0, 0), sl = mk<double>(0, 0);
-                    for (int k = 0; k < 2; k++) {
-                        su = cfma(su, Br[2 * i + k], mk<double>(Bn[2 * j + k].r, -Bn[2 * j + k].i));
-                        sl = cfma(sl, mk<double>(Br[2 * k + i].r, -Br[2 * k + i].i), Bn[2 * k + j]);
-                    }
-                    P[0][2 * i + j] = su;
-                    P[1][2 * i + j] = sl;
-                }
-            const int yr = step(g, y, rho, +1);          // y + rho
-            const int yn = step(g, y, nu, +1);           // y + nu
-            const int yrn = step(g, yr, nu, +1);         // y + rho + nu
-            const int ya = step(g, y, nu, -1);           // y - nu
-            const int yb = step(g, ya, rho, +1);         // y - nu + rho
-            // plaquette above
-            {
-                const M3 Unb = link(U, yr, nu);                      // U_nu(y+rho)
-                const M3 Urd = mdag(link(U, yn, rho));               // U_rho(y+nu)^H
-                const M3 Una = mdag(link(U, y, nu));                 // U_nu(y)^H
-                const M3 Wd = mmul(Urd, Una);
-                const M3 S = mmul(Unb, Wd);
-                M3 T = mmul(S, mcorner(eta, x, rs, nrhs, V, y, P));
-                madd(T, mmul(mcorner(eta, x, rs, nrhs, V, yr, P), S), 1.0);
-                madd(T, mmul(mmul(Unb, mcorner(eta, x, rs, nrhs, V, yrn, P)), Wd), 1.0);
-                madd(T, mmul(mmul(mmul(Unb, Urd), mcorner(eta, x, rs, nrhs, V, yn, P)), Una), 1.0);
-                madd(G, mdag(T), kappa);
-            }
-            // plaquette below
-            {
-                const M3 Unad = mdag(link(U, ya, nu));               // U_nu(a)^H
-                const M3 Ura = link(U, ya, rho);                     // U_rho(a)
-                const M3 Unb = link(U, yb, nu);                      // U_nu(b)
-                const M3 R = mmul(mmul(Unad, Ura), Unb);
-                M3 T = mmul(mmul(Unad, mcorner(eta, x, rs, nrhs, V, ya, P)), mmul(Ura, Unb));
-                madd(T, mmul(mmul(mmul(Unad, Ura), mcorner(eta, x, rs, nrhs, V, yb, P)), Unb), 1.0);
-                madd(T, mmul(R, mcorner(eta, x, rs, nrhs, V, yr, P)), 1.0);
-                madd(T, mmul(mcorner(eta, x, rs, nrhs, V, y, P), R), 1.0);
-                madd(G, T, kappa);
-            }
-        }
-        (void)Ur;
-    }
-
-    double2 *o = out + (size_t)(4 * y + rho) * 9;
-    if (raw) {
+        double2 *o = stage + lane * kLdsPitch + rho * 9;
+        if (raw) {
 #pragma unroll
-        for (int e = 0; e < 9; e++) o[e] = make_double2(G.a[e].r, G.a[e].i);
-        return;
-    }
-    const M3 M = mmul(G, mdag(link(U, y, rho)));
-    C tr = mk<double>(0, 0);
-    for (int i = 0; i < 3; i++) tr = tr + mk<double>(0, 2.0 * M.a[4 * i].i);  // tr(M - M^H)
-    for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-            C f = 0.5 * (M.a[3 * i + j] - mk<double>(M.a[3 * j + i].r, -M.a[3 * j + i].i));
-            if (i == j) f = f - (1.0 / 6.0) * tr;
-            o[3 * i + j] = make_double2(f.r, f.i);
+            for (int e = 0; e < 9; e++) o[e] = make_double2(G.a[e].r, G.a[e].i);
+        } else {
+            const M3 F = mmul(G, link_dag(U, y, rho));
+            const double tr = (2.0 / 6.0) * (F.a[0].i + F.a[4].i + F.a[8].i);  // Im tr(M - M^H) / 6
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    double fr = 0.5 * (F.a[3 * i + j].r - F.a[3 * j + i].r);
+                    double fi = 0.5 * (F.a[3 * i + j].i + F.a[3 * j + i].i);
+                    if (i == j) fi -= tr;
+                    o[3 * i + j] = make_double2(fr, fi);
+                }
         }
+    }
+    __syncthreads();
+    const int nsite = min(kLinkSites, g.V - base);
+    double2 *dst = out + (size_t)base * 36;
+    for (int t = threadIdx.x; t < nsite * 36; t += blockDim.x) dst[t] = stage[(t / 36) * kLdsPitch + t % 36];
 }
 
 }  // namespace wd
 
 using namespace wd;
 
+static int force_has_clover(const dirac_op *op) { return (op->clover_from_links && op->csw != 0.0) ? 1 : 0; }
+
+extern "C" size_t dirac_force_workspace_bytes(const dirac_op *op) {
+    if (!op || !force_has_clover(op)) return 0;
+    return (size_t)kPlanes * kInsertVec * sizeof(double2) * op->g.V;
+}
+
 extern "C" int dirac_force(const dirac_op *op, double *dU, const double *eta, const double *x, int nrhs, int raw,
-                           void *stream) {
+                           void *work, size_t work_bytes, void *stream) {
     if (!op || !dU || !eta || !x) return fail(WDIRAC_EINVAL, "null argument");
     if (nrhs < 1) return fail(WDIRAC_EINVAL, "nrhs must be >= 1");
-    const int with_clover = (op->clover_from_links && op->csw != 0.0) ? 1 : 0;
-    const int n = 4 * op->g.V;
-    hipLaunchKernelGGL(force_kernel, dim3((n + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+    const int with_clover = force_has_clover(op);
+    const size_t need = dirac_force_workspace_bytes(op);
+    if (need && (!work || work_bytes < need))
+        return fail(WDIRAC_EINVAL, "force workspace smaller than dirac_force_workspace_bytes");
+    hipStream_t st = (hipStream_t)stream;
+    const int V = op->g.V;
+    const auto *e2 = reinterpret_cast<const double2 *>(eta);
+    const auto *x2 = reinterpret_cast<const double2 *>(x);
+    auto *M = reinterpret_cast<double2 *>(work);
+    if (with_clover) {
+        hipLaunchKernelGGL(force_insert_kernel, dim3((V + 255) / 256), dim3(256), 0, st, M, e2, x2, nrhs, V);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("force insert launch: ") + hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(force_link_kernel, dim3((V + kLinkSites - 1) / kLinkSites), dim3(4 * kLinkSites), 0, st,
                        reinterpret_cast<double2 *>(dU), reinterpret_cast<const double2 *>(op->links_canon),
-                       reinterpret_cast<const double2 *>(eta), reinterpret_cast<const double2 *>(x), nrhs, op->g,
-                       (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, with_clover, op->csw, raw ? 1 : 0);
+                       (const double2 *)M, e2, x2, nrhs, op->g, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0,
+                       with_clover, op->csw, raw ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     return WDIRAC_OK;

@@ -26,7 +26,7 @@ def test_header_declares_the_abi():
     names = declared_functions()
     for n in ["dirac_create", "dirac_destroy", "dirac_apply", "dirac_apply_adjoint", "dirac_apply_batched",
               "dirac_pack", "dirac_unpack", "fgmres_solve", "fgmres_workspace_bytes", "dirac_force",
-              "dirac_clover_term", "dirac_last_error"]:
+              "dirac_force_workspace_bytes", "dirac_clover_term", "dirac_last_error"]:
         assert n in names
 
 

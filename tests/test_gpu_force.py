@@ -97,3 +97,33 @@ def test_gradcheck_x_and_links():
     xr = x.clone().requires_grad_(True)
     f = lambda xx, uu: dirac_apply(xx, uu, dims, op=None, m0=-0.2, csw=1.0, antiperiodic_t=True)
     assert torch.autograd.gradcheck(f, (xr, Ur), eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
+
+
+def test_force_workspace_size_and_rejection():
+    """The clover pass needs 6 planes x 80 B per site of workspace; without
+    clover none; a short workspace is rejected before any launch."""
+    need_gpu()
+    import ctypes
+    from paper_2407_00041_amd import _lib
+    dims = (2, 2, 4, 2)
+    V = synth.volume(dims)
+    U = synth.haar_links(dims, 21)
+    x = to_dev(synth.gaussian_spinor(dims, 22, nrhs=1))
+    op = DiracOp(dims, U, -0.3, 1.0, precisions=("f64",))
+    op0 = DiracOp(dims, U, -0.3, 0.0, precisions=("f64",))
+    assert op.lib.dirac_force_workspace_bytes(op.handle) == 6 * 80 * V
+    assert op0.lib.dirac_force_workspace_bytes(op0.handle) == 0
+    xn = op.pack(x, "f64")
+    out = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    work = torch.empty(6 * 80 * V - 16, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    rc = op.lib.dirac_force(op.handle, out.data_ptr(), xn.data_ptr(), xn.data_ptr(), 1, 0, work.data_ptr(),
+                            work.numel(), s)
+    assert rc == _lib.EINVAL
+    rc = op.lib.dirac_force(op.handle, out.data_ptr(), xn.data_ptr(), xn.data_ptr(), 1, 0, None, 0, s)
+    assert rc == _lib.EINVAL
+    G0 = op0.force(xn, xn, 1, raw=True)
+    rc = op0.lib.dirac_force(op0.handle, out.data_ptr(), xn.data_ptr(), xn.data_ptr(), 1, 1, None, 0, s)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(out, G0)
