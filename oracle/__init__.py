@@ -8,6 +8,8 @@ library (no code, header, table or helper), and this package never imports it.
   the clover term of Eqs. (1.11)-(1.12), its adjoint, and the exact link
   derivative of L = Re<eta, D(U) psi>.
 - ``fgmres.py`` (NumPy): Algorithm 2 (FGMRES) of Sec. 1.2.
+- ``evenodd.py`` (NumPy): the even-odd (red-black) reduction of D x = b to
+  the even sites (Schur complement, right-hand side, odd-site reconstruction).
 
 All arrays use the canonical host layouts documented in ``oracle.c``:
 spinors [..., V, 12] complex128, links [V, 4, 3, 3] complex128, packed clover
