@@ -51,6 +51,7 @@ CLOVER_BYTES = {"f64": 448, "f32": 224, "f16s": 112}
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16s": 52}
 BYTES_SITE = {p: 2 * SPINOR_BYTES[p] + LINK_BYTES[p] + CLOVER_BYTES[p] for p in LINK_BYTES}
 KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/csrc/dslash.h",
+                  "paper_2407_00041_amd/csrc/stencil.h",
                   "paper_2407_00041_amd/csrc/tune.hip",
                   "paper_2407_00041_amd/csrc/spinor_io.h", "paper_2407_00041_amd/csrc/common.h"]
 TRAFFIC_PROFILE = "profiles/dslash_f64_48x96_hbm_traffic.md"

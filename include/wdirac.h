@@ -83,6 +83,9 @@ extern "C" {
 #define WDIRAC_COMPRESS_CLOVER 16u /* store each chirality block of C as its
                                     spin-diagonal difference and off-diagonal
                                     3x3 blocks (27 of 36 reals) */
+#define WDIRAC_EVEN_ODD 32u      /* also store A(x)^{-1} for the even-odd
+                                    (red-black) reduced system; every extent
+                                    must be even */
 
 typedef struct dirac_op dirac_op;
 
@@ -114,10 +117,15 @@ const char *dirac_version(void);
  *            with A_00 = (4+m0) + H, A_11 = (4+m0) - H.  It needs
  *            |C_00 + C_11| <= 1e-10 max(1, |C|) at every site (always true for
  *            a clover built from the links).
+ *            WDIRAC_EVEN_ODD additionally stores the inverse of each 6x6
+ *            chirality block of A(x) (FP64 Gauss-Jordan with partial
+ *            pivoting, packed like the clover, at every materialised
+ *            precision) for the even-odd functions below.
  * Synchronous.  Copies everything into device memory owned by the handle;
  * the caller may free its arrays on return.  Errors: EINVAL (null pointer,
  * dims < 2, non-SU(3) links with WDIRAC_COMPRESS_LINKS, a clover without the
- * structure above with WDIRAC_COMPRESS_CLOVER), ENOMEM, EHIP, EUNSUPPORTED
+ * structure above with WDIRAC_COMPRESS_CLOVER, an odd extent or a (nearly)
+ * singular block of A with WDIRAC_EVEN_ODD), ENOMEM, EHIP, EUNSUPPORTED
  * (no HIP device).
  */
 int dirac_create(dirac_op **op, const int dims[4], const double *links, const double *clover,
@@ -301,6 +309,45 @@ size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nr
 int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs,
                  const fgmres_params *p, fgmres_stats *st, void *work, size_t work_bytes,
                  void *stream);
+
+/* ------------------------------------------------------------------------ */
+/*
+ * Even-odd (red-black) reduction.  With D = A + H (A(x) the site-local term,
+ * H the hopping sum of Eq. (1.13), which only couples sites of opposite
+ * parity (t + z + y + x) mod 2), eliminating the odd sites gives
+ *     S x_e = b_e - H_eo A_oo^{-1} b_o,   S = A_ee - H_eo A_oo^{-1} H_oe,
+ *     x_o   = A_oo^{-1} (b_o - H_oe x_e).
+ * A parity field holds the V/2 sites of one parity in lexicographic order
+ * (half-lattice index s >> 1 of full-lattice site s), in the native layout
+ * of its precision with V/2 in place of V (dirac_field_bytes of a lattice of
+ * V/2 sites; nrhs fields back to back).  All need an operator created with
+ * WDIRAC_EVEN_ODD and the precision materialised; all are asynchronous on
+ * `stream`.  Errors: EINVAL (null or misaligned pointer, overlapping buffers
+ * as stated, nrhs < 1, unknown precision), EUNSUPPORTED (no WDIRAC_EVEN_ODD
+ * or precision not materialised), EHIP.
+ */
+/* Bytes of nrhs parity fields at a precision (0 for a null operator). */
+size_t dirac_parity_field_bytes(const dirac_op *op, int prec, int nrhs);
+/* full field -> even and odd parity fields (no overlap among the three). */
+int dirac_parity_split(const dirac_op *op, void *even, void *odd, const void *full, int nrhs, int prec,
+                       void *stream);
+/* even and odd parity fields -> full field (full overlaps neither). */
+int dirac_parity_merge(const dirac_op *op, void *full, const void *even, const void *odd, int nrhs, int prec,
+                       void *stream);
+/* out = S in (dagger != 0: S^H in = A_ee in - (H^H)_eo A_oo^{-1} (H^H)_oe in);
+ * in, out even fields; tmp: nrhs odd fields of scratch (receives
+ * A_oo^{-1} H_oe in).  out, tmp and in must not overlap. */
+int dirac_apply_schur(const dirac_op *op, void *out, const void *in, void *tmp, int nrhs, int prec, int dagger,
+                      void *stream);
+/* bhat = b_even - H_eo A_oo^{-1} b_odd (the reduced right-hand side); tmp:
+ * nrhs odd fields receiving A_oo^{-1} b_odd (may be b_odd itself); bhat may
+ * be b_even itself and must not overlap tmp. */
+int dirac_schur_prepare(const dirac_op *op, void *bhat, const void *b_even, const void *b_odd, void *tmp, int nrhs,
+                        int prec, void *stream);
+/* x_odd = A_oo^{-1} (b_odd - H_oe x_even); x_odd may be b_odd itself and
+ * must not overlap x_even. */
+int dirac_schur_reconstruct(const dirac_op *op, void *x_odd, const void *x_even, const void *b_odd, int nrhs,
+                            int prec, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /*

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
+from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EVEN_ODD, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
                    FGMRES_F64,
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
@@ -49,12 +49,13 @@ class DiracOp:
     device tensor / ndarray); clover None (build from links when csw != 0) or
     the packed unit-c_sw term [V, 42].  compress_links: two stored rows per
     SU(3) link; compress_clover: each clover chirality block stored as its
-    spin-diagonal difference and off-diagonal 3x3 blocks (27 of 36 reals).
+    spin-diagonal difference and off-diagonal 3x3 blocks (27 of 36 reals);
+    even_odd: also store A(x)^{-1} for the even-odd reduced system.
     """
 
     def __init__(self, dims, links, m0: float, csw: float = 0.0, clover=None,
                  antiperiodic_t: bool = False, precisions=("f64", "f32", "f16s"),
-                 compress_links: bool = False, compress_clover: bool = False):
+                 compress_links: bool = False, compress_clover: bool = False, even_odd: bool = False):
         self.lib = _lib.load()
         self.dims = tuple(int(d) for d in dims)
         self.V = int(np.prod(self.dims))
@@ -67,6 +68,9 @@ class DiracOp:
         if compress_clover:
             flags |= COMPRESS_CLOVER
         self.compress_clover = bool(compress_clover)
+        if even_odd:
+            flags |= EVEN_ODD
+        self.even_odd = bool(even_odd)
         if "f32" in precisions:
             flags |= WITH_F32
         if "f16s" in precisions:
@@ -122,6 +126,46 @@ class DiracOp:
         check(self.lib.dirac_unpack(self.handle, _ptr(out), _ptr(native), nrhs, p, _stream(stream)),
               "dirac_unpack")
         return out
+
+    # ------------------------------------------------------------- even-odd
+    def parity_field_bytes(self, prec="f64", nrhs: int = 1) -> int:
+        return int(self.lib.dirac_parity_field_bytes(self.handle, _prec(prec), int(nrhs)))
+
+    def empty_parity(self, prec="f64", nrhs: int = 1, device="cuda") -> torch.Tensor:
+        """Native parity-field buffer (V/2 sites) of parity_field_bytes."""
+        return torch.empty(self.parity_field_bytes(prec, nrhs), dtype=torch.uint8, device=device)
+
+    def split(self, full: torch.Tensor, prec="f64", nrhs: int = 1, stream=None):
+        """Native full field -> (even, odd) native parity fields."""
+        e, o = self.empty_parity(prec, nrhs, full.device), self.empty_parity(prec, nrhs, full.device)
+        check(self.lib.dirac_parity_split(self.handle, _ptr(e), _ptr(o), _ptr(full), int(nrhs), _prec(prec),
+                                          _stream(stream)), "dirac_parity_split")
+        return e, o
+
+    def merge(self, even: torch.Tensor, odd: torch.Tensor, prec="f64", nrhs: int = 1, stream=None):
+        """(even, odd) native parity fields -> native full field."""
+        f = self.empty(prec, nrhs, even.device)
+        check(self.lib.dirac_parity_merge(self.handle, _ptr(f), _ptr(even), _ptr(odd), int(nrhs), _prec(prec),
+                                          _stream(stream)), "dirac_parity_merge")
+        return f
+
+    def apply_schur_native(self, out, inp, tmp, nrhs: int = 1, prec="f64", dagger: bool = False, stream=None):
+        """out = S inp (S^H with dagger), S = A_ee - H_eo A_oo^-1 H_oe; tmp: nrhs odd fields."""
+        check(self.lib.dirac_apply_schur(self.handle, _ptr(out), _ptr(inp), _ptr(tmp), int(nrhs), _prec(prec),
+                                         int(bool(dagger)), _stream(stream)), "dirac_apply_schur")
+        return out
+
+    def schur_prepare_native(self, bhat, b_even, b_odd, tmp, nrhs: int = 1, prec="f64", stream=None):
+        """bhat = b_e - H_eo A_oo^-1 b_o."""
+        check(self.lib.dirac_schur_prepare(self.handle, _ptr(bhat), _ptr(b_even), _ptr(b_odd), _ptr(tmp),
+                                           int(nrhs), _prec(prec), _stream(stream)), "dirac_schur_prepare")
+        return bhat
+
+    def schur_reconstruct_native(self, x_odd, x_even, b_odd, nrhs: int = 1, prec="f64", stream=None):
+        """x_o = A_oo^-1 (b_o - H_oe x_e)."""
+        check(self.lib.dirac_schur_reconstruct(self.handle, _ptr(x_odd), _ptr(x_even), _ptr(b_odd), int(nrhs),
+                                               _prec(prec), _stream(stream)), "dirac_schur_reconstruct")
+        return x_odd
 
     # ---------------------------------------------------------------- applies
     def apply_native(self, out: torch.Tensor, inp: torch.Tensor, nrhs: int = 1, prec="f64",

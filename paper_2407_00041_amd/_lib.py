@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libwdirac.so")
 
 F64, F32, F16S = 0, 1, 2
-ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER = 1, 2, 4, 8, 16
+ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER, EVEN_ODD = 1, 2, 4, 8, 16, 32
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV = 0, -1, -2, -3, -4, 1
 FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S = 0, 1, 2
 FGMRES_HIST_MAX = 4096
@@ -63,6 +63,12 @@ SIGNATURES = {
     "fgmres_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(FgmresParams),
                           ctypes.POINTER(FgmresStats), _P, ctypes.c_size_t, _P]),
     "dirac_force_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "dirac_parity_field_bytes": (ctypes.c_size_t, [_P, _I, _I]),
+    "dirac_parity_split": (_I, [_P, _P, _P, _P, _I, _I, _P]),
+    "dirac_parity_merge": (_I, [_P, _P, _P, _P, _I, _I, _P]),
+    "dirac_apply_schur": (_I, [_P, _P, _P, _P, _I, _I, _I, _P]),
+    "dirac_schur_prepare": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
+    "dirac_schur_reconstruct": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_force": (_I, [_P, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
 }
 

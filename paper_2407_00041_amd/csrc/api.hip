@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "dslash.h"
+#include "schur.h"
 
 namespace wd {
 
@@ -14,6 +15,7 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
                               hipStream_t st);
 hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStream_t st);
 hipError_t clover_structure_deviation(const double *clover_can_dev, int V, double *out, hipStream_t st);
+hipError_t clover_inverse_to_native(dirac_op *op, const double *inv_can_dev, hipStream_t st);
 
 static thread_local std::string g_err;
 constexpr double kSu3Tol = 1e-12;  // largest |U U^H - 1|, |det U - 1| accepted for two-row storage
@@ -81,7 +83,7 @@ size_t dirac_field_bytes(const dirac_op *op, int prec, int nrhs) {
 int dirac_destroy(dirac_op *op) {
     if (!op) return WDIRAC_OK;
     void *bufs[] = {op->links64, op->clover64, op->links32, op->clover32, op->links16, op->clover16,
-                    op->links_canon};
+                    op->links_canon, op->cinv64, op->cinv32, op->cinv16};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     delete op;
@@ -100,6 +102,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     }
     // native offsets are 32-bit: 36 link entries per site must stay addressable
     if (V * 36 >= (1LL << 31)) return fail(WDIRAC_EINVAL, "lattice too large (V*36 >= 2^31)");
+    if ((flags & WDIRAC_EVEN_ODD) && (dims[0] % 2 || dims[1] % 2 || dims[2] % 2 || dims[3] % 2))
+        return fail(WDIRAC_EINVAL, "WDIRAC_EVEN_ODD needs every lattice extent even");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(WDIRAC_EUNSUPPORTED, "no HIP device");
     dirac_op *op = new dirac_op();
@@ -113,7 +117,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     const size_t lr = (size_t)op->link_rows * 3;  // stored complex entries per link
     const size_t cr = op->clover_compact ? 56 : 72;  // stored reals per site of the clover
     const size_t nl = (size_t)V * 36 * 16, nc = (size_t)V * 42 * 16;
-    double *lc = nullptr, *cc = nullptr;
+    double *lc = nullptr, *cc = nullptr, *ic = nullptr;
+    int *bad = nullptr;
     int rc = WDIRAC_OK;
     auto alloc = [&](void **p, size_t n) -> bool {
         if (hipMalloc(p, n) != hipSuccess) {
@@ -134,6 +139,13 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
         if ((flags & WDIRAC_WITH_F16) && (!alloc((void **)&op->links16, Vt * 4 * lr * 4) ||
                                           !alloc((void **)&op->clover16, Vt * cr * 2)))
             break;
+        if (flags & WDIRAC_EVEN_ODD) {
+            if (!alloc((void **)&op->cinv64, Vt * 72 * 8) || !alloc((void **)&ic, nc) ||
+                !alloc((void **)&bad, sizeof(int)))
+                break;
+            if ((flags & WDIRAC_WITH_F32) && !alloc((void **)&op->cinv32, Vt * 72 * 4)) break;
+            if ((flags & WDIRAC_WITH_F16) && !alloc((void **)&op->cinv16, Vt * 72 * 2)) break;
+        }
         if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
         lc = op->links_canon;
         if (hipMemcpy(lc, links, nl, hipMemcpyHostToDevice) != hipSuccess) {
@@ -183,6 +195,21 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
             rc = fail(WDIRAC_EHIP, "layout conversion launch failed");
             break;
         }
+        if (flags & WDIRAC_EVEN_ODD) {
+            int found = 0;
+            if (hipMemsetAsync(bad, 0, sizeof(int), st) != hipSuccess ||
+                clover_invert_launch(reinterpret_cast<double2 *>(ic), reinterpret_cast<const double2 *>(cc), (int)V,
+                                     4.0 + m0, csw, bad, st) != hipSuccess ||
+                clover_inverse_to_native(op, ic, st) != hipSuccess ||
+                hipMemcpy(&found, bad, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "inverse of the site-local term failed to run");
+                break;
+            }
+            if (found) {
+                rc = fail(WDIRAC_EINVAL, "a chirality block of A(x) = (4 + m0) + csw C(x) is singular");
+                break;
+            }
+        }
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             rc = fail(WDIRAC_EHIP, std::string("operator setup failed: ") + hipGetErrorString(e));
@@ -190,6 +217,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
         }
     } while (false);
     if (cc) (void)hipFree(cc);
+    if (ic) (void)hipFree(ic);
+    if (bad) (void)hipFree(bad);
     if (rc != WDIRAC_OK) {
         dirac_destroy(op);
         return rc;

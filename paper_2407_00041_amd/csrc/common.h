@@ -132,6 +132,8 @@ struct dirac_op {
     void *links32 = nullptr, *clover32 = nullptr;
     void *links16 = nullptr, *clover16 = nullptr;
     double *links_canon = nullptr;  // canonical FP64 links (force kernels)
+    // inverse site-local term A(x)^{-1} (even-odd flag only): packed clover layout
+    void *cinv64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
     int link_rows = 3;
     bool clover_compact = false;
     wd::OpData data(int prec) const {
@@ -143,5 +145,8 @@ struct dirac_op {
         if (prec == WDIRAC_F32) { d.links = links32; d.clover = clover32; }
         if (prec == WDIRAC_F16S) { d.links = links16; d.clover = clover16; }
         return d;
+    }
+    const void *cinv(int prec) const {
+        return prec == WDIRAC_F64 ? cinv64 : prec == WDIRAC_F32 ? cinv32 : prec == WDIRAC_F16S ? cinv16 : nullptr;
     }
 };

@@ -382,4 +382,15 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
     return hipGetLastError();
 }
 
+hipError_t clover_inverse_to_native(dirac_op *op, const double *inv_can_dev, hipStream_t st) {
+    int V = op->g.V;
+    dim3 grid((V + 255) / 256);
+    hipLaunchKernelGGL(clover_to_native, grid, dim3(256), 0, st, (double2 *)op->cinv64, (const double2 *)inv_can_dev,
+                       V, 0.0, 1.0);
+    if (op->cinv32 || op->cinv16)
+        hipLaunchKernelGGL(clover_narrow, grid, dim3(256), 0, st, (float4 *)op->cinv32, (half4 *)op->cinv16,
+                           (const double2 *)op->cinv64, V);
+    return hipGetLastError();
+}
+
 }  // namespace wd

@@ -1,0 +1,457 @@
+// Even-odd (red-black) reduction of D x = b, one parity at a time.
+//
+// With D = A + H (A(x): the site-local term, mass plus the clover term of
+// Eqs. (1.11)-(1.12); H: the hopping sum of Eq. (1.13), which only couples
+// sites of opposite parity), eliminating the odd sites gives
+//   S x_e = b_e - H_eo A_oo^{-1} b_o,   S = A_ee - H_eo A_oo^{-1} H_oe,
+//   x_o   = A_oo^{-1} (b_o - H_oe x_e).
+// Red-black site colouring is among the splittings the paper's solver
+// library uses for its Schwarz smoothers (Sec. 1.3); here it halves the
+// Krylov vectors of FGMRES and improves the conditioning of the system.
+//
+// parity_kernel: one lane per site of the output parity.  It forms, in
+// registers, an optional self term (the input itself or A(x) times it), the
+// eight hops from the opposite-parity field (spin projection, SU(3) product,
+// reconstruction: the same device functions as the full-lattice stencil),
+// and optionally multiplies the sum by A(x)^{-1}, stored per site in the
+// packed clover layout.  Parity fields list one parity's sites in
+// lexicographic order, i.e. at half-lattice index s >> 1 (n_X even), so a
+// neighbour's index is its full-lattice index shifted right by one.
+#include "schur.h"
+#include "stencil.h"
+
+namespace wd {
+
+namespace {
+
+// full-lattice site (and coordinates) of half-lattice index i of parity p
+__device__ __forceinline__ int parity_site(const Geom &g, int i, int p, int c[4]) {
+    const int X2 = g.n[3] >> 1;
+    int r = i / X2;
+    const int xh = i - r * X2;
+    c[2] = r % g.n[2];
+    r /= g.n[2];
+    c[1] = r % g.n[1];
+    c[0] = r / g.n[1];
+    c[3] = 2 * xh + ((p + c[0] + c[1] + c[2]) & 1);
+    return ((c[0] * g.n[1] + c[1]) * g.n[2] + c[2]) * g.n[3] + c[3];
+}
+
+// Fence between hops.  The kernel is one basic block, so the compiler would
+// issue every hop's loads first and do all the arithmetic afterwards (all
+// eight hops in flight, far beyond the register file).  The empty asm takes
+// the accumulator as an in/out operand, so a hop's arithmetic must be done
+// before it, and clobbers memory, so the next hop's loads stay after it.
+template <typename T> __device__ __forceinline__ void hop_boundary(cx<T> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].r), "+v"(acc[k].i) : : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int P, int MU, bool DAG, int ROWS>
+__device__ __forceinline__ void parity_hops(const OpData &d, const Geom &g, const void *hop, int Vh, int s,
+                                            const int c[4], bool apbc, typename Store<P>::T fh,
+                                            cx<typename Store<P>::T> acc[12]) {
+    using T = typename Store<P>::T;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const int st = g.stride[MU], L = g.n[MU];
+    const int sf = (c[MU] == L - 1) ? s - (L - 1) * st : s + st;
+    const int sb = (c[MU] == 0) ? s + (L - 1) * st : s - st;
+    cx<T> U[9], p[12], h[6], chi[6];
+    {
+        const T f = (MU == 0 && apbc && c[0] == g.n[0] - 1) ? -fh : fh;
+        Store<P>::load_link(d.links, g.V, MU, s, U, ROWS);
+        Store<P>::load_spinor(hop, Vh, sf >> 1, p);
+        project<MU, SF>(p, h, f);
+        su3_mul<false>(U, h, chi);
+        reconstruct<MU, SF>(acc, chi);
+    }
+    hop_boundary(acc);
+    {
+        const T f = (MU == 0 && apbc && c[0] == 0) ? -fh : fh;
+        Store<P>::load_link(d.links, g.V, MU, sb, U, ROWS);
+        Store<P>::load_spinor(hop, Vh, sb >> 1, p);
+        project<MU, SB>(p, h, f);
+        su3_mul<true>(U, h, chi);
+        reconstruct<MU, SB>(acc, chi);
+    }
+    hop_boundary(acc);
+}
+
+// SELF: 0 none, 1 the input, 2 A(x) times the input.  HOP: add fh * 2 * H hop
+// (fh = -1/2 adds H, +1/2 subtracts it).  INV: multiply the sum by A(x)^{-1}.
+// ROWS: stored rows per link (a compile-time constant: a run-time choice
+// between the two link formats costs the FP64 kernels spills).
+template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS>
+__global__ __launch_bounds__(256) void parity_kernel(void *out, const void *self,
+                                                     const void *hop, OpData d,
+                                                     const void *cinv, Geom g, int parity, int apbc,
+                                                     typename Store<P>::T fh, size_t rhs_bytes) {
+    using T = typename Store<P>::T;
+    const int Vh = g.V >> 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Vh) return;
+    const size_t off = (size_t)blockIdx.y * rhs_bytes;
+    void *o = static_cast<char *>(out) + off;
+    int c[4];
+    const int s = parity_site(g, i, parity, c);
+    cx<T> acc[12];
+    if (SELF == 1) {
+        Store<P>::load_spinor(static_cast<const char *>(self) + off, Vh, i, acc);
+    } else if (SELF == 2) {
+        const void *in = static_cast<const char *>(self) + off;
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            cx<T> x[6];
+            Store<P>::load_half(in, Vh, i, b, x);
+            if (d.clover_compact) {
+                T cr[28];
+                Store<P>::load_clover_compact(d.clover, g.V, b, s, cr);
+                clover_block_compact((T)d.diag, cr, x, &acc[6 * b]);
+            } else {
+                T dd[6];
+                cx<T> uu[15];
+                Store<P>::load_clover(d.clover, g.V, b, s, dd, uu);
+                clover_block(dd, uu, x, &acc[6 * b]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+    }
+    if (HOP) {
+        const void *hp = static_cast<const char *>(hop) + off;
+        hop_boundary(acc);
+        parity_hops<P, 0, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 1, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 2, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 3, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
+    }
+    if (INV) {
+        cx<T> r[12];
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            T dd[6];
+            cx<T> uu[15];
+            Store<P>::load_clover(cinv, g.V, b, s, dd, uu);
+            clover_block(dd, uu, &acc[6 * b], &r[6 * b]);
+        }
+        Store<P>::store_spinor(o, Vh, i, r);
+    } else {
+        Store<P>::store_spinor(o, Vh, i, acc);
+    }
+}
+
+template <int P, bool DAG, int SELF, bool HOP, bool INV>
+hipError_t launch_mode(const dirac_op *op, int parity, void *out, const void *self, const void *hop, double fh,
+                       int nrhs, hipStream_t st) {
+    using T = typename Store<P>::T;
+    const int Vh = op->g.V >> 1;
+    const dim3 grid((Vh + 255) / 256, nrhs);
+    const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
+    if (op->link_rows == 2 || !HOP)
+        hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2>), grid, dim3(256), 0, st, out, self, hop,
+                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh));
+    else
+        hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 3>), grid, dim3(256), 0, st, out, self, hop,
+                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh));
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_p(int mode, bool dag, const dirac_op *op, int parity, void *out, const void *self, const void *hop,
+                    int nrhs, hipStream_t st) {
+    switch (mode) {
+    case kParHopInv:
+        return dag ? launch_mode<P, true, 0, true, true>(op, parity, out, self, hop, -0.5, nrhs, st)
+                   : launch_mode<P, false, 0, true, true>(op, parity, out, self, hop, -0.5, nrhs, st);
+    case kParCloverSub:
+        return dag ? launch_mode<P, true, 2, true, false>(op, parity, out, self, hop, 0.5, nrhs, st)
+                   : launch_mode<P, false, 2, true, false>(op, parity, out, self, hop, 0.5, nrhs, st);
+    case kParApply: return launch_mode<P, false, 2, true, false>(op, parity, out, self, hop, -0.5, nrhs, st);
+    case kParInvSelf: return launch_mode<P, false, 1, false, true>(op, parity, out, self, hop, 0.0, nrhs, st);
+    case kParSelfSub: return launch_mode<P, false, 1, true, false>(op, parity, out, self, hop, 0.5, nrhs, st);
+    case kParInvSelfSub: return launch_mode<P, false, 1, true, true>(op, parity, out, self, hop, 0.5, nrhs, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// full <-> parity fields: K 16-byte vectors per site (+ the FP16S scale)
+template <int K, bool SCALE, bool MERGE>
+__global__ __launch_bounds__(256) void parity_copy_kernel(char *__restrict__ full, char *__restrict__ even,
+                                                          char *__restrict__ odd, Geom g, size_t rb_full,
+                                                          size_t rb_half) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int V = g.V, Vh = V >> 1;
+    if (s >= V) return;
+    int r = s, c3 = r % g.n[3];
+    r /= g.n[3];
+    int c2 = r % g.n[2];
+    r /= g.n[2];
+    int c1 = r % g.n[1], c0 = r / g.n[1];
+    const int p = (c0 + c1 + c2 + c3) & 1;
+    char *h = (p ? odd : even) + (size_t)blockIdx.y * rb_half;
+    char *f = full + (size_t)blockIdx.y * rb_full;
+    uint4 *hv = reinterpret_cast<uint4 *>(h);
+    uint4 *fv = reinterpret_cast<uint4 *>(f);
+    const int j = s >> 1;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (MERGE) fv[(size_t)k * V + s] = hv[(size_t)k * Vh + j];
+        else hv[(size_t)k * Vh + j] = fv[(size_t)k * V + s];
+    }
+    if (SCALE) {
+        float *hs = reinterpret_cast<float *>(h + (size_t)48 * Vh);
+        float *fs = reinterpret_cast<float *>(f + (size_t)48 * V);
+        if (MERGE) fs[s] = hs[j];
+        else hs[j] = fs[s];
+    }
+}
+
+template <bool MERGE>
+hipError_t parity_copy(const dirac_op *op, int prec, void *full, void *even, void *odd, int nrhs, hipStream_t st) {
+    const int V = op->g.V;
+    const dim3 grid((V + 255) / 256, nrhs);
+    const size_t rf = field_rhs_bytes(prec, V), rh = field_rhs_bytes(prec, V >> 1);
+    char *f = static_cast<char *>(full), *e = static_cast<char *>(even), *o = static_cast<char *>(odd);
+    if (prec == WDIRAC_F64)
+        hipLaunchKernelGGL((parity_copy_kernel<12, false, MERGE>), grid, dim3(256), 0, st, f, e, o, op->g, rf, rh);
+    else if (prec == WDIRAC_F32)
+        hipLaunchKernelGGL((parity_copy_kernel<6, false, MERGE>), grid, dim3(256), 0, st, f, e, o, op->g, rf, rh);
+    else
+        hipLaunchKernelGGL((parity_copy_kernel<3, true, MERGE>), grid, dim3(256), 0, st, f, e, o, op->g, rf, rh);
+    return hipGetLastError();
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting of one 6x6 complex
+// block; returns false when a pivot is below tiny.
+__device__ bool invert6(cx<double> a[6][6], double tiny) {
+    int piv[6];
+    for (int k = 0; k < 6; k++) {
+        int p = k;
+        double best = a[k][k].r * a[k][k].r + a[k][k].i * a[k][k].i;
+        for (int i = k + 1; i < 6; i++) {
+            const double m = a[i][k].r * a[i][k].r + a[i][k].i * a[i][k].i;
+            if (m > best) {
+                best = m;
+                p = i;
+            }
+        }
+        if (!(sqrt(best) > tiny)) return false;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < 6; j++) {
+                const cx<double> t = a[k][j];
+                a[k][j] = a[p][j];
+                a[p][j] = t;
+            }
+        const cx<double> inv = {a[k][k].r / best, -a[k][k].i / best};
+        a[k][k] = mk<double>(1, 0);
+        for (int j = 0; j < 6; j++) a[k][j] = cmul(a[k][j], inv);
+        for (int i = 0; i < 6; i++) {
+            if (i == k) continue;
+            const cx<double> f = a[i][k];
+            a[i][k] = mk<double>(0, 0);
+            for (int j = 0; j < 6; j++) a[i][j] = a[i][j] - cmul(f, a[k][j]);
+        }
+    }
+    for (int k = 5; k >= 0; k--)
+        if (piv[k] != k)
+            for (int i = 0; i < 6; i++) {
+                const cx<double> t = a[i][k];
+                a[i][k] = a[i][piv[k]];
+                a[i][piv[k]] = t;
+            }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void clover_invert_kernel(double2 *__restrict__ inv, const double2 *__restrict__ can,
+                                                            int V, double diag, double csw, int *__restrict__ bad) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    for (int b = 0; b < 2; b++) {
+        const double2 *c = can + (size_t)42 * s + 21 * b;
+        cx<double> a[6][6];
+        double scale = 0;
+        for (int i = 0; i < 6; i++) a[i][i] = mk<double>(diag + csw * c[i].x, 0.0);
+        int k = 6;
+        for (int i = 0; i < 6; i++)
+            for (int j = i + 1; j < 6; j++, k++) {
+                a[i][j] = mk<double>(csw * c[k].x, csw * c[k].y);
+                a[j][i] = mk<double>(csw * c[k].x, -csw * c[k].y);
+            }
+        for (int i = 0; i < 6; i++)
+            for (int j = 0; j < 6; j++) scale = fmax(scale, fabs(a[i][j].r) + fabs(a[i][j].i));
+        if (!invert6(a, 1e-12 * scale)) {
+            *bad = 1;
+            for (int i = 0; i < 6; i++)
+                for (int j = 0; j < 6; j++) a[i][j] = mk<double>(0, 0);
+        }
+        double2 *o = inv + (size_t)42 * s + 21 * b;
+        for (int i = 0; i < 6; i++) o[i] = make_double2(a[i][i].r, 0.0);
+        k = 6;
+        for (int i = 0; i < 6; i++)
+            for (int j = i + 1; j < 6; j++, k++)  // Hermitian part of the computed inverse
+                o[k] = make_double2(0.5 * (a[i][j].r + a[j][i].r), 0.5 * (a[i][j].i - a[j][i].i));
+    }
+}
+
+}  // namespace
+
+hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int parity, void *out, const void *self,
+                         const void *hop, int nrhs, hipStream_t st) {
+    if (nrhs < 1) return hipSuccess;
+    switch (prec) {
+    case WDIRAC_F64: return launch_p<WDIRAC_F64>(mode, dag, op, parity, out, self, hop, nrhs, st);
+    case WDIRAC_F32: return launch_p<WDIRAC_F32>(mode, dag, op, parity, out, self, hop, nrhs, st);
+    case WDIRAC_F16S: return launch_p<WDIRAC_F16S>(mode, dag, op, parity, out, self, hop, nrhs, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t schur_apply(int prec, bool dag, const dirac_op *op, void *out, const void *in, void *tmp, int nrhs,
+                       hipStream_t st) {
+    hipError_t e = parity_launch(kParHopInv, prec, dag, op, 1, tmp, nullptr, in, nrhs, st);
+    if (e != hipSuccess) return e;
+    return parity_launch(kParCloverSub, prec, dag, op, 0, out, in, tmp, nrhs, st);
+}
+
+hipError_t parity_split_launch(const dirac_op *op, int prec, void *even, void *odd, const void *full, int nrhs,
+                               hipStream_t st) {
+    return parity_copy<false>(op, prec, const_cast<void *>(full), even, odd, nrhs, st);
+}
+
+hipError_t parity_merge_launch(const dirac_op *op, int prec, void *full, const void *even, const void *odd,
+                               int nrhs, hipStream_t st) {
+    return parity_copy<true>(op, prec, full, const_cast<void *>(even), const_cast<void *>(odd), nrhs, st);
+}
+
+hipError_t clover_invert_launch(double2 *inv_can, const double2 *can, int V, double diag, double csw, int *bad,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(clover_invert_kernel, dim3((V + 255) / 256), dim3(256), 0, st, inv_can, can, V, diag, csw,
+                       bad);
+    return hipGetLastError();
+}
+
+int check_apply(const dirac_op *op, const void *out, const void *in, int nrhs, int prec);
+
+}  // namespace wd
+
+using namespace wd;
+
+namespace {
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + nb && y < x + na;
+}
+
+bool misaligned(const void *p) { return reinterpret_cast<uintptr_t>(p) & 15; }
+
+// operator prepared for even-odd work at this precision
+int check_parity(const dirac_op *op, int prec, int nrhs) {
+    if (!op) return fail(WDIRAC_EINVAL, "null operator");
+    if (nrhs < 1) return fail(WDIRAC_EINVAL, "nrhs must be >= 1");
+    if (prec != WDIRAC_F64 && prec != WDIRAC_F32 && prec != WDIRAC_F16S)
+        return fail(WDIRAC_EINVAL, "unknown precision " + std::to_string(prec));
+    if (!(op->flags & WDIRAC_EVEN_ODD)) return fail(WDIRAC_EUNSUPPORTED, "operator created without WDIRAC_EVEN_ODD");
+    if (!op->data(prec).links || !op->cinv(prec))
+        return fail(WDIRAC_EUNSUPPORTED, "precision " + std::to_string(prec) + " not materialised at create");
+    return WDIRAC_OK;
+}
+
+// out (n bytes) must not overlap `hop`, and equals or is disjoint from `self`
+int check_out(const void *out, const void *self, const void *hop, size_t n) {
+    if (!out) return fail(WDIRAC_EINVAL, "null field pointer");
+    if (misaligned(out) || misaligned(self) || misaligned(hop))
+        return fail(WDIRAC_EINVAL, "field pointers must be 16-byte aligned");
+    if (hop && overlaps(out, n, hop, n)) return fail(WDIRAC_EINVAL, "output overlaps a field read at neighbours");
+    if (self && self != out && overlaps(out, n, self, n))
+        return fail(WDIRAC_EINVAL, "output partially overlaps the same-parity input");
+    return WDIRAC_OK;
+}
+
+int hip_result(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return WDIRAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dirac_parity_field_bytes(const dirac_op *op, int prec, int nrhs) {
+    if (!op || nrhs < 0) return 0;
+    return field_rhs_bytes(prec, op->g.V / 2) * (size_t)nrhs;
+}
+
+int dirac_parity_split(const dirac_op *op, void *even, void *odd, const void *full, int nrhs, int prec,
+                       void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!even || !odd || !full) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t nh = field_rhs_bytes(prec, op->g.V / 2) * nrhs, nf = field_rhs_bytes(prec, op->g.V) * nrhs;
+    if (misaligned(even) || misaligned(odd) || misaligned(full))
+        return fail(WDIRAC_EINVAL, "field pointers must be 16-byte aligned");
+    if (overlaps(even, nh, odd, nh) || overlaps(even, nh, full, nf) || overlaps(odd, nh, full, nf))
+        return fail(WDIRAC_EINVAL, "split buffers overlap");
+    return hip_result(parity_split_launch(op, prec, even, odd, full, nrhs, (hipStream_t)stream), "split launch");
+}
+
+int dirac_parity_merge(const dirac_op *op, void *full, const void *even, const void *odd, int nrhs, int prec,
+                       void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!even || !odd || !full) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t nh = field_rhs_bytes(prec, op->g.V / 2) * nrhs, nf = field_rhs_bytes(prec, op->g.V) * nrhs;
+    if (misaligned(even) || misaligned(odd) || misaligned(full))
+        return fail(WDIRAC_EINVAL, "field pointers must be 16-byte aligned");
+    if (overlaps(full, nf, even, nh) || overlaps(full, nf, odd, nh)) return fail(WDIRAC_EINVAL, "merge buffers overlap");
+    return hip_result(parity_merge_launch(op, prec, full, even, odd, nrhs, (hipStream_t)stream), "merge launch");
+}
+
+int dirac_apply_schur(const dirac_op *op, void *out, const void *in, void *tmp, int nrhs, int prec, int dagger,
+                      void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!in || !tmp) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t nh = field_rhs_bytes(prec, op->g.V / 2) * nrhs;
+    rc = check_out(out, nullptr, in, nh);
+    if (rc) return rc;
+    rc = check_out(tmp, nullptr, in, nh);
+    if (rc) return rc;
+    if (overlaps(out, nh, tmp, nh)) return fail(WDIRAC_EINVAL, "out overlaps tmp");
+    return hip_result(schur_apply(prec, dagger != 0, op, out, in, tmp, nrhs, (hipStream_t)stream), "schur launch");
+}
+
+int dirac_schur_prepare(const dirac_op *op, void *bhat, const void *b_even, const void *b_odd, void *tmp, int nrhs,
+                        int prec, void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!b_even || !b_odd || !tmp) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t nh = field_rhs_bytes(prec, op->g.V / 2) * nrhs;
+    rc = check_out(tmp, b_odd, nullptr, nh);
+    if (rc) return rc;
+    rc = check_out(bhat, b_even, tmp, nh);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = hip_result(parity_launch(kParInvSelf, prec, false, op, 1, tmp, b_odd, nullptr, nrhs, st), "prepare launch");
+    if (rc) return rc;
+    return hip_result(parity_launch(kParSelfSub, prec, false, op, 0, bhat, b_even, tmp, nrhs, st), "prepare launch");
+}
+
+int dirac_schur_reconstruct(const dirac_op *op, void *x_odd, const void *x_even, const void *b_odd, int nrhs,
+                            int prec, void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!x_even || !b_odd) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t nh = field_rhs_bytes(prec, op->g.V / 2) * nrhs;
+    rc = check_out(x_odd, b_odd, x_even, nh);
+    if (rc) return rc;
+    return hip_result(parity_launch(kParInvSelfSub, prec, false, op, 1, x_odd, b_odd, x_even, nrhs,
+                                    (hipStream_t)stream),
+                      "reconstruct launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+"""GPU parity of the even-odd (red-black) entry points through the C ABI
+against the oracle's reduction (oracle/evenodd.py): parity split and merge,
+the reduced operator S and its adjoint, the reduced right-hand side and the
+odd-site reconstruction, at every precision and storage format."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import evenodd
+from paper_2407_00041_amd import DiracOp, WdiracError, synth
+from paper_2407_00041_amd import _lib
+from util import TOL, fields, need_gpu, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# (dims, link kind, m0, csw, antiperiodic): extent 2 (x + mu = x - mu), a
+# ragged half-lattice (V/2 not a multiple of the 256-lane work-group),
+# non-cubic lattices, and plain Wilson
+CASES = [
+    ((2, 2, 2, 2), "haar", -0.4, 1.0, False),
+    ((4, 6, 2, 10), "smooth", -0.3, 1.0, True),
+    ((6, 4, 4, 8), "haar", 0.2, 1.7, False),
+    ((4, 4, 4, 4), "haar", -0.4, 0.0, True),
+]
+
+
+def dev_parity(op, canon_half, p, prec):
+    """Canonical parity field [nrhs, V/2, 12] (oracle order) -> native parity field."""
+    full = evenodd.merge(op.dims, canon_half, np.zeros_like(canon_half)) if p == 0 else \
+        evenodd.merge(op.dims, np.zeros_like(canon_half), canon_half)
+    nrhs = canon_half.shape[0]
+    e, o = op.split(op.pack(to_dev(full), prec), prec, nrhs)
+    return e if p == 0 else o
+
+
+def host_parity(op, nat, p, prec, nrhs):
+    """Native parity field -> canonical [nrhs, V/2, 12]."""
+    z = op.empty_parity(prec, nrhs)
+    z.zero_()
+    full = op.merge(nat, z, prec, nrhs) if p == 0 else op.merge(z, nat, prec, nrhs)
+    c = op.unpack(full, prec, nrhs).cpu().numpy()
+    return evenodd.split(op.dims, c)[p]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_split_merge_roundtrip_and_site_order(prec):
+    need_gpu()
+    dims = (4, 6, 2, 10)
+    U, psi = fields(dims, 3, nrhs=2)
+    op = DiracOp(dims, U, -0.3, 1.0, even_odd=True)
+    nat = op.pack(to_dev(psi), prec)
+    e, o = op.split(nat, prec, 2)
+    back = op.unpack(op.merge(e, o, prec, 2), prec, 2).cpu().numpy()
+    assert np.array_equal(back, op.unpack(nat, prec, 2).cpu().numpy())
+    # each parity field holds that parity's sites in lexicographic order
+    pe, po = evenodd.split(dims, op.unpack(nat, prec, 2).cpu().numpy())
+    assert np.array_equal(host_parity(op, e, 0, prec, 2), pe)
+    assert np.array_equal(host_parity(op, o, 1, prec, 2), po)
+
+
+@pytest.mark.parametrize("dims,kind,m0,csw,ap", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("compress", [False, True])
+def test_schur_apply_matches_oracle(dims, kind, m0, csw, ap, prec, dagger, compress):
+    need_gpu()
+    U, _ = fields(dims, 17, kind)
+    Vh = synth.volume(dims) // 2
+    rng = np.random.default_rng(4)
+    xe = rng.standard_normal((3, Vh, 12)) + 1j * rng.standard_normal((3, Vh, 12))
+    op = DiracOp(dims, U, m0, csw, antiperiodic_t=ap, even_odd=True, compress_links=compress,
+                 compress_clover=compress)
+    eo = evenodd.EvenOdd(dims, U, m0, csw, antiperiodic_t=ap)
+    inp = dev_parity(op, xe, 0, prec)
+    out, tmp = op.empty_parity(prec, 3), op.empty_parity(prec, 3)
+    op.apply_schur_native(out, inp, tmp, 3, prec, dagger)
+    got = host_parity(op, out, 0, prec, 3)
+    for r in range(3):
+        want = eo.schur(xe[r], dagger=dagger)
+        assert rel_l2(got[r], want) < TOL[prec], (r, rel_l2(got[r], want))
+
+
+@pytest.mark.parametrize("dims,kind,m0,csw,ap", CASES[:3])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_prepare_and_reconstruct_match_oracle(dims, kind, m0, csw, ap, prec):
+    need_gpu()
+    U, b = fields(dims, 23, kind, nrhs=2)
+    op = DiracOp(dims, U, m0, csw, antiperiodic_t=ap, even_odd=True)
+    eo = evenodd.EvenOdd(dims, U, m0, csw, antiperiodic_t=ap)
+    be, bo = op.split(op.pack(to_dev(b), prec), prec, 2)
+    cbe, cbo = evenodd.split(dims, b)
+    bhat, tmp = op.empty_parity(prec, 2), op.empty_parity(prec, 2)
+    op.schur_prepare_native(bhat, be, bo, tmp, 2, prec)
+    got = host_parity(op, bhat, 0, prec, 2)
+    rng = np.random.default_rng(9)
+    xe = rng.standard_normal(cbe.shape) + 1j * rng.standard_normal(cbe.shape)
+    xo = op.empty_parity(prec, 2)
+    op.schur_reconstruct_native(xo, dev_parity(op, xe, 0, prec), bo, 2, prec)
+    got_o = host_parity(op, xo, 1, prec, 2)
+    for r in range(2):
+        assert rel_l2(got[r], eo.prepare(cbe[r], cbo[r])) < TOL[prec]
+        assert rel_l2(got_o[r], eo.reconstruct(xe[r], cbo[r])) < TOL[prec]
+    # in place: bhat over b_even, x_odd over b_odd
+    op.schur_prepare_native(be, be, bo, tmp, 2, prec)
+    assert rel_l2(host_parity(op, be, 0, prec, 2), got) == 0.0
+
+
+def test_exact_solution_satisfies_reduced_system():
+    """x with D x = b (dense solve): S x_e equals the reduced right-hand side and
+    the reconstruction returns x_o, at 1e-12 through the GPU path."""
+    need_gpu()
+    dims = (2, 2, 4, 2)
+    U, b = fields(dims, 41, "haar")
+    m0, csw = -0.25, 1.2
+    V = synth.volume(dims)
+    n = 12 * V
+    D = oracle.dirac_apply(dims, U, np.eye(n, dtype=complex).reshape(n, V, 12), m0, csw).reshape(n, n).T
+    x = np.linalg.solve(D, b.reshape(-1)).reshape(1, V, 12)
+    op = DiracOp(dims, U, m0, csw, even_odd=True)
+    xe, xo = op.split(op.pack(to_dev(x), "f64"), "f64", 1)
+    be, bo = op.split(op.pack(to_dev(b), "f64"), "f64", 1)
+    lhs, tmp, rhs = op.empty_parity("f64"), op.empty_parity("f64"), op.empty_parity("f64")
+    op.apply_schur_native(lhs, xe, tmp, 1, "f64")
+    op.schur_prepare_native(rhs, be, bo, tmp, 1, "f64")
+    l, r = host_parity(op, lhs, 0, "f64", 1), host_parity(op, rhs, 0, "f64", 1)
+    assert rel_l2(l, r) < 1e-12
+    xo2 = op.empty_parity("f64")
+    op.schur_reconstruct_native(xo2, xe, bo, 1, "f64")
+    assert rel_l2(host_parity(op, xo2, 1, "f64", 1), evenodd.split(dims, x)[1]) < 1e-12
+
+
+def test_even_odd_errors():
+    need_gpu()
+    U, psi = fields((4, 4, 4, 4), 5)
+    with pytest.raises(WdiracError) as e:
+        DiracOp((4, 4, 3, 4), synth.haar_links((4, 4, 3, 4), 1), -0.3, 1.0, even_odd=True)
+    assert e.value.code == _lib.EINVAL
+    op = DiracOp((4, 4, 4, 4), U, -0.3, 1.0)
+    nat = op.pack(to_dev(psi), "f64")
+    half = torch.empty(op.field_bytes("f64") // 2, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    rc = op.lib.dirac_parity_split(op.handle, half.data_ptr(), half.data_ptr() + half.numel() // 2,
+                                   nat.data_ptr(), 1, 0, s)
+    assert rc == _lib.EUNSUPPORTED
+    op2 = DiracOp((4, 4, 4, 4), U, -0.3, 1.0, even_odd=True, precisions=("f64",))
+    e, o = op2.split(op2.pack(to_dev(psi), "f64"), "f64")
+    out = op2.empty_parity("f32")
+    assert op2.lib.dirac_apply_schur(op2.handle, out.data_ptr(), e.data_ptr(), o.data_ptr(), 1, 1, 0, s) == \
+        _lib.EUNSUPPORTED
+    # the output may not overlap the field read at neighbours
+    assert op2.lib.dirac_schur_reconstruct(op2.handle, e.data_ptr(), e.data_ptr(), o.data_ptr(), 1, 0, s) == \
+        _lib.EINVAL
