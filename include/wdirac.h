@@ -266,6 +266,10 @@ typedef struct {
     int wave;           /* right-hand sides solved together (lockstep, one   */
                         /* batched apply per step); nrhs is processed in     */
                         /* consecutive waves of this size; 0 = all at once   */
+    int schur;          /* 1 = solve the even-odd reduced system S x_e = bhat */
+                        /* (operator created with WDIRAC_EVEN_ODD) and       */
+                        /* reconstruct x_o; tol stays relative to the full   */
+                        /* |b - D x0|; applies count applications of S       */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096

@@ -194,15 +194,17 @@ class DiracOp:
         return self.unpack(b, prec, nrhs).reshape(shape)
 
     @staticmethod
-    def _params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph=False, wave=0):
+    def _params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph=False, wave=0,
+                schur=False):
         modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S}
         return _lib.FgmresParams(int(restart), float(tol), int(maxit),
                                  modes[mode] if isinstance(mode, str) else int(mode),
-                                 int(inner_restart), float(inner_tol), int(inner_maxit), int(bool(graph)), int(wave))
+                                 int(inner_restart), float(inner_tol), int(inner_maxit), int(bool(graph)), int(wave),
+                                 int(bool(schur)))
 
     def workspace_bytes(self, nrhs: int = 1, restart: int = 20, mode="f64", inner_restart: int = 30,
-                        wave: int = 0) -> int:
-        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave)
+                        wave: int = 0, schur: bool = False) -> int:
+        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave, schur=schur)
         n = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if n == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
@@ -211,14 +213,17 @@ class DiracOp:
     def solve(self, b: torch.Tensor, nrhs: int = 1, x0: torch.Tensor | None = None, restart: int = 20,
               tol: float = 1e-10, maxit: int = 10000, mode="f64", inner_restart: int = 30,
               inner_tol: float = 1e-2, inner_maxit: int = 30, work: torch.Tensor | None = None, stream=None,
-              graph: bool = False, wave: int = 0):
+              graph: bool = False, wave: int = 0, schur: bool = False):
         """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
         "mixed_f16s".  ``work`` may be a reusable device buffer of at least
         workspace_bytes(...) bytes.  ``graph``: run the inner cycles of the mixed
         modes as captured HIP graphs.  ``wave``: solve the right-hand sides in
         consecutive groups of this size (workspace for one group; 0 = all).
+        ``schur``: solve the even-odd reduced system (operator built with
+        even_odd=True) and reconstruct the odd sites; tol stays relative to the
+        full system's initial residual.
         Returns (x native FP64, per-RHS stats dicts, status)."""
-        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave)
+        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur)
         nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if nbytes == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")

@@ -28,7 +28,7 @@ class DiracBatch(ctypes.Structure):
 class FgmresParams(ctypes.Structure):
     _fields_ = [("restart", _I), ("tol", ctypes.c_double), ("maxit", ctypes.c_longlong),
                 ("mode", _I), ("inner_restart", _I), ("inner_tol", ctypes.c_double),
-                ("inner_maxit", _I), ("graph", _I), ("wave", _I)]
+                ("inner_maxit", _I), ("graph", _I), ("wave", _I), ("schur", _I)]
 
 
 class FgmresStats(ctypes.Structure):

@@ -46,6 +46,7 @@
 
 #include "blas.h"
 #include "dslash.h"
+#include "schur.h"
 
 namespace wd {
 
@@ -226,9 +227,12 @@ int kmax_of(const fgmres_params *p) {
     return (m > mi ? m : mi) + 2;
 }
 
+// sites of the solved system's vectors: V, or V/2 for the even-odd reduced system
+long long system_sites(const dirac_op *op, const fgmres_params *p) { return p->schur ? op->g.V / 2 : op->g.V; }
+
 Layout layout(const dirac_op *op, const fgmres_params *p) {
     Layout L;
-    const long long V = op->g.V;
+    const long long V = system_sites(op, p);
     L.f64 = align256(field_rhs_bytes(WDIRAC_F64, V));
     L.f32 = align256(field_rhs_bytes(WDIRAC_F32, V));
     L.f16 = align256(field_rhs_bytes(WDIRAC_F16S, V));
@@ -240,6 +244,10 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     if (p->mode != FGMRES_F64) {
         L.per_rhs += (size_t)m * L.f64;                                          // Z[0..m)
         L.per_rhs += (size_t)(mi + 1) * (p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16);  // inner W[0..mi]
+    }
+    if (p->schur) {
+        L.per_rhs += 3 * L.f64;  // x_e, reduced right-hand side, odd scratch of S
+        if (p->mode != FGMRES_F64) L.per_rhs += p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;  // inner odd scratch
     }
     return L;
 }
@@ -305,8 +313,12 @@ enum class Phase { Residual, Arnoldi, Done };
 
 struct Rhs {
     // device
-    double2 *x = nullptr;
+    double2 *x = nullptr;  // iterate of the solved system (the user's x, or x_e for the reduced system)
     const double2 *b = nullptr;
+    double2 *xu = nullptr;  // reduced system: the user's full x and b, the reduced right-hand side, and the
+    const double2 *bu = nullptr;  // odd-parity scratch of S at FP64 and at the inner precision
+    double2 *bh = nullptr;
+    void *t64 = nullptr, *ti = nullptr;
     std::vector<void *> V, Z;  // outer basis (F64), preconditioned vectors (F64)
     double2 *w = nullptr;
     std::vector<void *> Vi;    // inner basis, inner operator precision
@@ -325,9 +337,10 @@ struct Ctx {
     const dirac_op *op;
     const fgmres_params *p;
     hipStream_t st;
-    long long N;  // complex numbers per field
-    int V;
+    long long N;  // complex numbers per field of the solved system
+    int V;        // its sites (V/2 for the even-odd reduced system)
     int apbc;
+    bool schur;   // solve S x_e = bhat (even-odd reduction) instead of D x = b
     double2 *pinned;  // host staging for scalar reads (hipHostMalloc)
     size_t pinned_n;
 };
@@ -345,8 +358,25 @@ struct GraphCache {
     }
 };
 
-hipError_t apply_many(const Ctx &c, int prec, const std::vector<dirac_batch> &b, hipStream_t s) {
-    if (b.empty()) return hipSuccess;
+// operator applications of the solved system: one batched stencil launch for D, or two parity launches per
+// right-hand side for S (tmp: that right-hand side's odd scratch)
+struct ApplyItem {
+    void *out;
+    const void *in;
+    void *tmp;
+};
+
+hipError_t apply_many(const Ctx &c, int prec, const std::vector<ApplyItem> &items, hipStream_t s) {
+    if (items.empty()) return hipSuccess;
+    if (c.schur) {
+        for (const ApplyItem &it : items) {
+            hipError_t e = schur_apply(prec, false, c.op, it.out, it.in, it.tmp, 1, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    std::vector<dirac_batch> b;
+    for (const ApplyItem &it : items) b.push_back({it.out, it.in, 1});
     return dslash_launch_batches(b.data(), (int)b.size(), prec, false, c.op->data(prec), c.op->g, c.apbc, false, s);
 }
 
@@ -419,8 +449,8 @@ int issue_inner_body(const Ctx &c, const std::vector<Rhs *> &list, bool host_ste
     std::vector<Rhs *> act = list;
     for (int k = 0; k < maxit && !act.empty(); k++) {
         // W_{k+1} = D W_k, one batched launch for the right-hand sides still iterating
-        std::vector<dirac_batch> b;
-        for (Rhs *r : act) b.push_back({r->Vi[k + 1], r->Vi[k], 1});
+        std::vector<ApplyItem> b;
+        for (Rhs *r : act) b.push_back({r->Vi[k + 1], r->Vi[k], r->ti});
         WD_TRY(apply_many(c, prec, b, s));
         for (Rhs *r : act)
             WD_TRY(site_mdot(prec, r->Vi.data(), k + 1, r->Vi[k + 1], c.V, r->partial, r->hcol, r->in.hdr, s));
@@ -513,7 +543,9 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             (void)hipHostFree(p);
         }
     } guard{pinned, stream};
-    Ctx c{op, p, stream, 12LL * op->g.V, op->g.V, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, pinned, pinned_n};
+    const long long Vs = system_sites(op, p);
+    Ctx c{op, p, stream, 12LL * Vs, (int)Vs, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, p->schur != 0, pinned,
+          pinned_n};
     const bool mixed = p->mode != FGMRES_F64;
     const int m = p->restart;
     GraphCache graphs;
@@ -528,8 +560,17 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     };
     for (int k = 0; k < nrhs; k++) {
         Rhs &r = R[k];
-        r.x = reinterpret_cast<double2 *>(x) + (size_t)k * c.N;
-        r.b = reinterpret_cast<const double2 *>(b) + (size_t)k * c.N;
+        r.xu = reinterpret_cast<double2 *>(x) + (size_t)k * 12 * op->g.V;
+        r.bu = reinterpret_cast<const double2 *>(b) + (size_t)k * 12 * op->g.V;
+        r.x = r.xu;
+        r.b = r.bu;
+        if (c.schur) {
+            r.x = reinterpret_cast<double2 *>(take(L.f64));
+            r.bh = reinterpret_cast<double2 *>(take(L.f64));
+            r.b = r.bh;
+            r.t64 = take(L.f64);
+            if (mixed) r.ti = take(p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16);
+        }
         for (int i = 0; i <= m; i++) r.V.push_back(take(L.f64));
         r.w = reinterpret_cast<double2 *>(take(L.f64));
         if (mixed) {
@@ -565,6 +606,29 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
     } ev;
     for (hipEvent_t &x : ev.e) WD_TRY(hipEventCreate(&x));
+    if (c.schur) {
+        // |b - D x0| over both parities (the tolerance's reference, so that tol means the same as for D x = b),
+        // then the reduced right-hand side bhat = b_e - H_eo A_oo^{-1} b_o
+        std::vector<std::pair<const double2 *, int>> src;
+        for (Rhs &r : R) {
+            double2 *xo = static_cast<double2 *>(r.V[0]), *bo = static_cast<double2 *>(r.V[1]);
+            WD_TRY(parity_split_launch(op, WDIRAC_F64, r.x, xo, r.xu, 1, c.st));
+            WD_TRY(parity_split_launch(op, WDIRAC_F64, r.bh, bo, r.bu, 1, c.st));
+            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 0, r.w, r.x, xo, 1, c.st));
+            WD_TRY(residual(r.bh, r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.nrm, c.st));
+            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 1, r.w, xo, r.x, 1, c.st));
+            WD_TRY(residual(bo, r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.hcol2, c.st));
+            WD_TRY(parity_launch(kParInvSelf, WDIRAC_F64, false, op, 1, r.t64, bo, nullptr, 1, c.st));
+            WD_TRY(parity_launch(kParSelfSub, WDIRAC_F64, false, op, 0, r.bh, r.bh, r.t64, 1, c.st));
+            src.emplace_back(r.nrm, 1);
+            src.emplace_back(r.hcol2, 1);
+        }
+        std::vector<std::vector<zc>> got;
+        int rc = fetch(c, src, got);
+        if (rc) return rc;
+        for (size_t k = 0; k < R.size(); k++)
+            R[k].r0norm = std::sqrt(std::max(got[2 * k][0].real(), 0.0) + std::max(got[2 * k + 1][0].real(), 0.0));
+    }
     double t_apply = 0, t_precond = 0, t_ortho = 0;
     bool any = true;
     while (any) {
@@ -581,9 +645,9 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
         WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (lines 4 and 9)
-        std::vector<dirac_batch> bat;
-        for (Rhs *r : res) bat.push_back({r->w, r->x, 1});
-        for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], 1});
+        std::vector<ApplyItem> bat;
+        for (Rhs *r : res) bat.push_back({r->w, r->x, r->t64});
+        for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], r->t64});
         WD_TRY(apply_many(c, WDIRAC_F64, bat, c.st));
         WD_TRY(hipEventRecord(ev.e[2], c.st));
         for (Rhs *r : res) {
@@ -667,6 +731,31 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         for (Rhs &r : R)
             if (r.phase != Phase::Done) any = true;
     }
+    if (c.schur) {
+        // x_o = A_oo^{-1} (b_o - H_oe x_e), x = (x_e, x_o), and the true residual |b - D x| over both parities
+        std::vector<std::pair<const double2 *, int>> src;
+        for (Rhs &r : R) {
+            double2 *xo = static_cast<double2 *>(r.V[0]), *be = static_cast<double2 *>(r.V[1]);
+            double2 *bo = static_cast<double2 *>(r.t64);
+            WD_TRY(parity_split_launch(op, WDIRAC_F64, be, bo, r.bu, 1, c.st));
+            WD_TRY(parity_launch(kParInvSelfSub, WDIRAC_F64, false, op, 1, xo, bo, r.x, 1, c.st));
+            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 0, r.w, r.x, xo, 1, c.st));
+            WD_TRY(residual(be, r.w, r.bh, c.N, r.partial, r.nrm, c.st));
+            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 1, r.w, xo, r.x, 1, c.st));
+            WD_TRY(residual(bo, r.w, r.bh, c.N, r.partial, r.hcol2, c.st));
+            WD_TRY(parity_merge_launch(op, WDIRAC_F64, r.xu, r.x, xo, 1, c.st));
+            src.emplace_back(r.nrm, 1);
+            src.emplace_back(r.hcol2, 1);
+        }
+        std::vector<std::vector<zc>> got;
+        int rc = fetch(c, src, got);
+        if (rc) return rc;
+        for (size_t k = 0; k < R.size(); k++) {
+            const double rn =
+                std::sqrt(std::max(got[2 * k][0].real(), 0.0) + std::max(got[2 * k + 1][0].real(), 0.0));
+            R[k].relres = R[k].r0norm > 0 ? rn / R[k].r0norm : 0.0;
+        }
+    }
     WD_TRY(hipStreamSynchronize(stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool all = true;
@@ -705,6 +794,12 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     if (p->mode != FGMRES_F64 && p->mode != FGMRES_MIXED_F32 && p->mode != FGMRES_MIXED_F16S)
         return fail(WDIRAC_EINVAL, "unknown solver mode");
     if (p->wave < 0) return fail(WDIRAC_EINVAL, "wave must be >= 0");
+    if (p->schur != 0 && p->schur != 1) return fail(WDIRAC_EINVAL, "schur must be 0 or 1");
+    if (p->schur) {
+        if (!(op->flags & WDIRAC_EVEN_ODD)) return fail(WDIRAC_EUNSUPPORTED, "schur needs WDIRAC_EVEN_ODD at create");
+        if (p->mode != FGMRES_F64 && !op->cinv(inner_prec(p->mode)))
+            return fail(WDIRAC_EUNSUPPORTED, "inner precision not materialised at create");
+    }
     if (p->mode != FGMRES_F64) {
         if (p->inner_restart < 1 || p->inner_restart > 1000) return fail(WDIRAC_EINVAL, "inner_restart in [1, 1000]");
         if (p->inner_maxit < 1) return fail(WDIRAC_EINVAL, "inner_maxit must be >= 1");

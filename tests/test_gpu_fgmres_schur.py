@@ -1,0 +1,135 @@
+"""GPU FGMRES on the even-odd reduced system (fgmres_params.schur) through
+the C ABI: against the oracle FGMRES on the oracle's reduced system
+(operator-application count and residual history), the full system's true
+residual checked with the oracle operator, the mixed modes, graph replay,
+waves, warm starts and the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import evenodd
+from paper_2407_00041_amd import DiracOp, WdiracError, synth
+from util import need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(dims, seed, m0, csw=1.0, nrhs=1, precisions=("f64", "f32", "f16s")):
+    U = synth.smooth_links(dims, seed).numpy()
+    b = synth.gaussian_spinor(dims, seed + 1, nrhs=nrhs)
+    op = DiracOp(dims, U, m0, csw, precisions=precisions, even_odd=True)
+    bn = op.pack(to_dev(b), "f64")
+    return U, b, op, bn
+
+
+def true_relres(dims, U, m0, csw, x, b, x0=None):
+    r = b - oracle.dirac_apply(dims, U, x, m0, csw)
+    r0 = b if x0 is None else b - oracle.dirac_apply(dims, U, x0, m0, csw)
+    return np.linalg.norm(r) / np.linalg.norm(r0)
+
+
+@pytest.mark.parametrize("dims,m", [((4, 4, 4, 4), 20), ((8, 4, 6, 4), 10)])
+def test_reduced_fp64_matches_oracle(dims, m):
+    need_gpu()
+    m0, csw, tol = -0.3, 1.0, 1e-10
+    U, b, op, bn = setup(dims, 1000, m0, csw)
+    x, st, rc = op.solve(bn, restart=m, tol=tol, maxit=3000, schur=True)
+    assert rc == 0 and st[0]["converged"]
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    assert true_relres(dims, U, m0, csw, xg, b) <= tol * 1.05
+    assert st[0]["true_residual"] <= tol * 1.05
+    # the oracle FGMRES on the oracle's reduced system, with the same reference norm |b|
+    eo = evenodd.EvenOdd(dims, U, m0, csw)
+    be, bo = evenodd.split(dims, b)
+    bh = eo.prepare(be, bo)
+    scale = np.linalg.norm(bh) / np.linalg.norm(b)
+    hist = []
+    xe, info = oracle.fgmres(eo.schur, bh, m=m, tol=tol / scale, maxit=3000, history=hist)
+    assert abs(st[0]["applies"] - info["applies"]) <= 2, (st[0]["applies"], info["applies"])
+    k = 0
+    while k < min(len(hist), len(st[0]["hist"])) and hist[k] * scale > 1e-9:
+        assert abs(st[0]["hist"][k] - hist[k] * scale) <= 1e-8 * hist[k] * scale, (k, st[0]["hist"][k], hist[k])
+        k += 1
+    xo = evenodd.merge(dims, xe, eo.reconstruct(xe, bo))
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-8
+    # the reduced system needs fewer operator applications than D x = b
+    _, st_full, _ = op.solve(bn, restart=m, tol=tol, maxit=3000)
+    assert st[0]["applies"] < st_full[0]["applies"]
+
+
+@pytest.mark.parametrize("mode", ["mixed_f32", "mixed_f16s"])
+def test_reduced_mixed_reaches_fp64_tolerance(mode):
+    need_gpu()
+    dims = (8, 8, 8, 8)
+    m0, csw = -0.35, 1.0
+    U, b, op, bn = setup(dims, 3, m0, csw, nrhs=2)
+    x, st, rc = op.solve(bn, nrhs=2, restart=8, tol=1e-10, maxit=200, mode=mode, inner_restart=10,
+                         inner_tol=0.1, inner_maxit=10, schur=True)
+    assert rc == 0
+    xg = op.unpack(x, "f64", 2).cpu().numpy()
+    x64, _, _ = op.solve(bn, nrhs=2, restart=20, tol=1e-10, maxit=3000)
+    x64 = op.unpack(x64, "f64", 2).cpu().numpy()
+    for r in range(2):
+        assert st[r]["converged"] and st[r]["inner_applies"] > 0
+        assert true_relres(dims, U, m0, csw, xg[r], b[r]) <= 1e-10 * 1.05
+        assert abs(st[r]["true_residual"] - true_relres(dims, U, m0, csw, xg[r], b[r])) < 1e-12
+        assert np.linalg.norm(xg[r] - x64[r]) / np.linalg.norm(x64[r]) < 1e-8
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed_f16s"])
+def test_reduced_graph_and_waves_equal_lockstep(mode):
+    """Graph-replayed inner cycles and waves of 2 give bit-identical solutions
+    to one step-by-step lockstep solve of all right-hand sides."""
+    need_gpu()
+    dims = (4, 4, 6, 4)
+    U, b, op, bn = setup(dims, 9, -0.3, 1.0, nrhs=3)
+    kw = dict(nrhs=3, restart=8, tol=1e-10, maxit=2000, mode=mode, inner_restart=10, inner_tol=0.1, inner_maxit=10,
+              schur=True)
+    x_all, s_all, rc = op.solve(bn, **kw)
+    assert rc == 0
+    wb = op.workspace_bytes(3, 8, mode, 10, wave=2, schur=True)
+    assert wb < op.workspace_bytes(3, 8, mode, 10, wave=2)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    x_w, s_w, rc = op.solve(bn, wave=2, work=work, **kw)
+    assert rc == 0 and torch.equal(x_w, x_all)
+    assert [s["applies"] for s in s_w] == [s["applies"] for s in s_all]
+    if mode != "f64":
+        for rep in range(2):
+            x_g, s_g, rc = op.solve(bn, graph=True, **kw)
+            assert rc == 0 and torch.equal(x_g, x_all), rep
+            assert [s["hist"] for s in s_g] == [s["hist"] for s in s_all]
+
+
+def test_reduced_warm_start_maxit_and_zero_rhs():
+    need_gpu()
+    dims = (4, 4, 4, 4)
+    m0, csw = -0.3, 1.0
+    U, b, op, bn = setup(dims, 7, m0, csw)
+    x, st, rc = op.solve(bn, restart=5, tol=1e-12, maxit=7, schur=True)
+    assert rc == 1 and not st[0]["converged"] and st[0]["applies"] == 7
+    x0 = op.unpack(x, "f64").cpu().numpy()[0]
+    # the reported true residual is the full system's, relative to |b - D x0| (x0 = 0 here)
+    assert abs(st[0]["true_residual"] - true_relres(dims, U, m0, csw, x0, b)) < 1e-13
+    x2, st2, rc2 = op.solve(bn, x0=x, restart=20, tol=1e-10, maxit=3000, schur=True)
+    assert rc2 == 0 and st2[0]["converged"]
+    assert true_relres(dims, U, m0, csw, op.unpack(x2, "f64").cpu().numpy()[0], b, x0) <= 1e-10 * 1.05
+    z = torch.zeros_like(bn)
+    x3, st3, rc3 = op.solve(z, restart=5, tol=1e-10, maxit=50, schur=True)
+    assert rc3 == 0 and st3[0]["converged"] and not x3.any()
+
+
+def test_reduced_argument_errors():
+    need_gpu()
+    dims = (2, 2, 2, 4)
+    U = synth.smooth_links(dims, 1).numpy()
+    b = synth.gaussian_spinor(dims, 2)
+    op = DiracOp(dims, U, -0.3, 1.0)
+    bn = op.pack(to_dev(b), "f64")
+    with pytest.raises(WdiracError) as e:
+        op.solve(bn, schur=True)
+    assert e.value.code in (-1, -4) and "WDIRAC_EVEN_ODD" in str(e.value)
+    op2 = DiracOp(dims, U, -0.3, 1.0, precisions=("f64",), even_odd=True)
+    with pytest.raises(WdiracError) as e:
+        op2.solve(op2.pack(to_dev(b), "f64"), schur=True, mode="mixed_f16s")
+    assert e.value.code in (-1, -4) and "not materialised" in str(e.value)
