@@ -19,7 +19,9 @@ timed steps (reported under "extra"):
     mixed solver (FP64 outer FGMRES(8) whose preconditioner is an inner
     GMRES(10) on the FP16S operator, relative tolerance 0.1), in memory-sized
     waves: wall time, applications and the difference between the two
-    solutions;
+    solutions; then both again on the even-odd reduced system (half-lattice
+    vectors, odd sites reconstructed; the same tolerance relative to the full
+    system's |b|);
   * 32^4: FP64 apply rate and plain FP64 FGMRES(20) to 1e-10;
   * 24^3 x 48: forward + backward through the autograd Function and the force
     kernel alone.
@@ -147,7 +149,8 @@ def batched_run(torch, op, dims, stream, steps):
 
 def fgmres_run(torch, op, dims, nrhs_total):
     """Plain FP64 FGMRES(30) vs the mixed FP16S-preconditioned FGMRES on the
-    same right-hand sides, in waves sized to the free HBM."""
+    same right-hand sides, in waves sized to the free HBM, on D x = b and on
+    the even-odd reduced system."""
     from paper_2407_00041_amd import synth
     p64 = dict(restart=30, tol=1e-10, maxit=5000, mode="f64")
     pmx = dict(restart=MIXED["restart"], tol=1e-10, maxit=500, mode=MIXED["mode"],
@@ -155,7 +158,7 @@ def fgmres_run(torch, op, dims, nrhs_total):
     fb = op.field_bytes("f64", 1)
     free, _ = torch.cuda.mem_get_info()
     per = max(op.workspace_bytes(1, 30, "f64"),
-              op.workspace_bytes(1, pmx["restart"], pmx["mode"], pmx["inner_restart"])) + 3 * fb
+              op.workspace_bytes(1, pmx["restart"], pmx["mode"], pmx["inner_restart"])) + 5 * fb
     wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
     log(f"[bench] fgmres: {nrhs_total} RHS in waves of {wave} "
         f"(free {free / 2**30:.0f} GiB, {per / 2**30:.1f} GiB per RHS)")
@@ -168,10 +171,11 @@ def fgmres_run(torch, op, dims, nrhs_total):
         if not TUNE_FIXED:
             op.autotune("f64", n)
             op.autotune(inner, n)
-    t64 = tmx = 0.0
+    t64 = tmx = t64r = tmxr = 0.0
     ph64 = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
     phmx = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
     a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
+    a64r, amxr, ainr, errsr, res64r, resmxr = [], [], [], [], [], []
     for w0 in range(0, nrhs_total, wave):
         nw = min(wave, nrhs_total - w0)
         b = op.pack(synth.gaussian_spinor(dims, 3000 + w0, nrhs=nw, device="cuda"), "f64")
@@ -184,20 +188,38 @@ def fgmres_run(torch, op, dims, nrhs_total):
         xmx, stmx, _ = op.solve(b, nrhs=nw, work=work, **pmx)
         torch.cuda.synchronize()
         tmx += time.perf_counter() - t
+        xmx_keep = xmx
         for k in ph64:  # GPU time per phase of this wave (shared by its right-hand sides)
             ph64[k] += st64[0]["seconds_" + k]
             phmx[k] += stmx[0]["seconds_" + k]
+        del xmx
+        t = time.perf_counter()
+        x64r, st64r, _ = op.solve(b, nrhs=nw, work=work, schur=True, **p64)
+        torch.cuda.synchronize()
+        t64r += time.perf_counter() - t
+        t = time.perf_counter()
+        xmxr, stmxr, _ = op.solve(b, nrhs=nw, work=work, schur=True, **pmx)
+        torch.cuda.synchronize()
+        tmxr += time.perf_counter() - t
         for r in range(nw):
             u = x64[r * fb:(r + 1) * fb].view(torch.float64)
-            v = xmx[r * fb:(r + 1) * fb].view(torch.float64)
-            errs.append(float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(u)))
+            nu = torch.linalg.vector_norm(u)
+            for xs, e in ((xmx_keep, errs), (x64r, errsr), (xmxr, errsr)):
+                v = xs[r * fb:(r + 1) * fb].view(torch.float64)
+                e.append(float(torch.linalg.vector_norm(u - v) / nu))
             a64.append(st64[r]["applies"])
             amx.append(stmx[r]["applies"])
             ainner.append(stmx[r]["inner_applies"])
             res64.append(st64[r]["true_residual"])
             resmx.append(stmx[r]["true_residual"])
-        log(f"[bench] fgmres after RHS {w0 + nw}: fp64 {t64:.2f}s mixed {tmx:.2f}s")
-        del b, x64, xmx
+            a64r.append(st64r[r]["applies"])
+            amxr.append(stmxr[r]["applies"])
+            ainr.append(stmxr[r]["inner_applies"])
+            res64r.append(st64r[r]["true_residual"])
+            resmxr.append(stmxr[r]["true_residual"])
+        log(f"[bench] fgmres after RHS {w0 + nw}: fp64 {t64:.2f}s mixed {tmx:.2f}s; even-odd reduced: "
+            f"fp64 {t64r:.2f}s mixed {tmxr:.2f}s")
+        del b, x64, xmx_keep, x64r, xmxr
         torch.cuda.empty_cache()
     return {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
             "fp64": {"solver": "FGMRES(30), FP64", "seconds": t64, "phase_seconds": ph64, "applies": a64,
@@ -207,7 +229,19 @@ def fgmres_run(torch, op, dims, nrhs_total):
                       "seconds": tmx, "phase_seconds": phmx, "fp64_applies": amx, "fp16s_applies": ainner,
                       "true_residual_max": max(resmx), "converged": all(r < 1e-10 for r in resmx)},
             "speedup_mixed_vs_fp64": t64 / tmx if tmx > 0 else None,
-            "error_vs_fp64_max": max(errs)}
+            "error_vs_fp64_max": max(errs),
+            "even_odd": {
+                "fp64": {"solver": "FGMRES(30), FP64, on S = A_ee - H_eo A_oo^-1 H_oe", "seconds": t64r,
+                         "applies_of_S": a64r, "true_residual_max": max(res64r),
+                         "converged": all(r < 1e-10 for r in res64r)},
+                "mixed": {"solver": "the mixed solver above on S (FP16S S in the inner GMRES)", "seconds": tmxr,
+                          "fp64_applies_of_S": amxr, "fp16s_applies_of_S": ainr,
+                          "true_residual_max": max(resmxr), "converged": all(r < 1e-10 for r in resmxr)},
+                "speedup_mixed_vs_fp64": t64r / tmxr if tmxr > 0 else None,
+                "speedup_vs_full_system": {"fp64": t64 / t64r if t64r > 0 else None,
+                                           "mixed": tmx / tmxr if tmxr > 0 else None},
+                "speedup_mixed_even_odd_vs_plain_fp64": t64 / tmxr if tmxr > 0 else None,
+                "error_vs_plain_fp64_max": max(errsr)}}
 
 
 def config32_run(torch, stream):
@@ -330,7 +364,7 @@ def main():
     del Ud
     log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
     op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"), compress_links=True,
-                    compress_clover=True)
+                    compress_clover=True, even_odd=True)
     stream = torch.cuda.current_stream()
     inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
     out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}

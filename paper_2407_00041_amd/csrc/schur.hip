@@ -17,6 +17,12 @@
 // packed clover layout.  Parity fields list one parity's sites in
 // lexicographic order, i.e. at half-lattice index s >> 1 (n_X even), so a
 // neighbour's index is its full-lattice index shifted right by one.
+//
+// Work-groups are dealt like the full stencil's T-sweep: the eight XCDs
+// (work-groups go to them round-robin) each take 1/8 of every T-slice of the
+// half lattice and advance through the slices together, so T-neighbour
+// slices are still in the Infinity Cache and Z/Y neighbours mostly in the
+// same XCD's L2.
 #include "schur.h"
 #include "stencil.h"
 
@@ -42,7 +48,12 @@ __device__ __forceinline__ int parity_site(const Geom &g, int i, int p, int c[4]
 // eight hops in flight, far beyond the register file).  The empty asm takes
 // the accumulator as an in/out operand, so a hop's arithmetic must be done
 // before it, and clobbers memory, so the next hop's loads stay after it.
-template <typename T> __device__ __forceinline__ void hop_boundary(cx<T> acc[12]) {
+// WD_PARITY_FENCE = 1: a fence after every hop; 2: after each direction's pair of hops.
+#ifndef WD_PARITY_FENCE
+#define WD_PARITY_FENCE 1
+#endif
+template <typename T> __device__ __forceinline__ void hop_boundary(cx<T> acc[12], int level = 1) {
+    if (level < WD_PARITY_FENCE) return;
 #pragma unroll
     for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].r), "+v"(acc[k].i) : : "memory");
     __builtin_amdgcn_sched_barrier(0);
@@ -67,7 +78,7 @@ __device__ __forceinline__ void parity_hops(const OpData &d, const Geom &g, cons
         su3_mul<false>(U, h, chi);
         reconstruct<MU, SF>(acc, chi);
     }
-    hop_boundary(acc);
+    hop_boundary(acc, 1);
     {
         const T f = (MU == 0 && apbc && c[0] == 0) ? -fh : fh;
         Store<P>::load_link(d.links, g.V, MU, sb, U, ROWS);
@@ -76,7 +87,7 @@ __device__ __forceinline__ void parity_hops(const OpData &d, const Geom &g, cons
         su3_mul<true>(U, h, chi);
         reconstruct<MU, SB>(acc, chi);
     }
-    hop_boundary(acc);
+    hop_boundary(acc, 2);
 }
 
 // SELF: 0 none, 1 the input, 2 A(x) times the input.  HOP: add fh * 2 * H hop
@@ -87,11 +98,20 @@ template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS>
 __global__ __launch_bounds__(256) void parity_kernel(void *out, const void *self,
                                                      const void *hop, OpData d,
                                                      const void *cinv, Geom g, int parity, int apbc,
-                                                     typename Store<P>::T fh, size_t rhs_bytes) {
+                                                     typename Store<P>::T fh, size_t rhs_bytes, int tpr) {
     using T = typename Store<P>::T;
     const int Vh = g.V >> 1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Vh) return;
+    int i;
+    {
+        // block -> (XCD k, T-slice t, tile within the slice's k-th eighth)
+        const int hs = Vh / g.n[0];
+        const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+        const int t = j / tpr, tile = j - t * tpr;
+        const int r0 = t * hs + (int)(((long long)k * hs) >> 3);
+        const int r1 = t * hs + (int)(((long long)(k + 1) * hs) >> 3);
+        i = r0 + tile * (int)blockDim.x + (int)threadIdx.x;
+        if (i >= r1) return;
+    }
     const size_t off = (size_t)blockIdx.y * rhs_bytes;
     void *o = static_cast<char *>(out) + off;
     int c[4];
@@ -122,7 +142,7 @@ __global__ __launch_bounds__(256) void parity_kernel(void *out, const void *self
     }
     if (HOP) {
         const void *hp = static_cast<const char *>(hop) + off;
-        hop_boundary(acc);
+        hop_boundary(acc, 2);
         parity_hops<P, 0, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
         parity_hops<P, 1, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
         parity_hops<P, 2, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
@@ -148,14 +168,16 @@ hipError_t launch_mode(const dirac_op *op, int parity, void *out, const void *se
                        int nrhs, hipStream_t st) {
     using T = typename Store<P>::T;
     const int Vh = op->g.V >> 1;
-    const dim3 grid((Vh + 255) / 256, nrhs);
+    const int hs = Vh / op->g.n[0];                 // half-lattice sites per T-slice
+    const int tpr = ((hs + 7) / 8 + 255) / 256;     // 256-site tiles per eighth of a slice
+    const dim3 grid(op->g.n[0] * 8 * tpr, nrhs);
     const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
     if (op->link_rows == 2 || !HOP)
         hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2>), grid, dim3(256), 0, st, out, self, hop,
-                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh));
+                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh), tpr);
     else
         hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 3>), grid, dim3(256), 0, st, out, self, hop,
-                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh));
+                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh), tpr);
     return hipGetLastError();
 }
 
