@@ -358,8 +358,8 @@ struct GraphCache {
     }
 };
 
-// operator applications of the solved system: one batched stencil launch for D, or two parity launches per
-// right-hand side for S (tmp: that right-hand side's odd scratch)
+// operator applications of the solved system: one batched stencil launch for D, or two parity launches for S
+// over all listed right-hand sides (tmp: each one's odd scratch)
 struct ApplyItem {
     void *out;
     const void *in;
@@ -369,11 +369,9 @@ struct ApplyItem {
 hipError_t apply_many(const Ctx &c, int prec, const std::vector<ApplyItem> &items, hipStream_t s) {
     if (items.empty()) return hipSuccess;
     if (c.schur) {
-        for (const ApplyItem &it : items) {
-            hipError_t e = schur_apply(prec, false, c.op, it.out, it.in, it.tmp, 1, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        std::vector<SchurItem> list;
+        for (const ApplyItem &it : items) list.push_back({it.out, it.in, it.tmp});
+        return schur_apply_list(prec, false, c.op, list, s);
     }
     std::vector<dirac_batch> b;
     for (const ApplyItem &it : items) b.push_back({it.out, it.in, 1});

@@ -4,6 +4,8 @@
 // H the hopping sum, which couples only sites of opposite parity).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace wd {
@@ -24,13 +26,29 @@ enum ParityMode : int {
 
 // `self` may equal `out` (each site reads only its own entries before
 // writing them); `hop` must not overlap `out`.  dag selects H^H for
-// kParHopInv and kParCloverSub (the adjoint of S).
+// kParHopInv and kParCloverSub (the adjoint of S).  Fields of nrhs right-hand
+// sides back to back, or a list of separate ones; pairs of right-hand sides
+// share each lane's loads of the links and of A or A^{-1}.
+struct ParityItem {
+    void *out;
+    const void *self;
+    const void *hop;
+};
 hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int parity, void *out, const void *self,
                          const void *hop, int nrhs, hipStream_t st);
+hipError_t parity_launch_list(int mode, int prec, bool dag, const dirac_op *op, int parity,
+                              const std::vector<ParityItem> &items, hipStream_t st);
 
 // S x (or S^H x) for nrhs even fields: tmp (nrhs odd fields) receives A_oo^{-1} H_oe x.
 hipError_t schur_apply(int prec, bool dag, const dirac_op *op, void *out, const void *in, void *tmp, int nrhs,
                        hipStream_t st);
+struct SchurItem {
+    void *out;
+    const void *in;
+    void *tmp;
+};
+hipError_t schur_apply_list(int prec, bool dag, const dirac_op *op, const std::vector<SchurItem> &items,
+                            hipStream_t st);
 
 // full <-> (even, odd)
 hipError_t parity_split_launch(const dirac_op *op, int prec, void *even, void *odd, const void *full, int nrhs,

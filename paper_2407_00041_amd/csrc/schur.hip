@@ -23,6 +23,9 @@
 // half lattice and advance through the slices together, so T-neighbour
 // slices are still in the Infinity Cache and Z/Y neighbours mostly in the
 // same XCD's L2.
+#include <algorithm>
+#include <vector>
+
 #include "schur.h"
 #include "stencil.h"
 
@@ -46,59 +49,85 @@ __device__ __forceinline__ int parity_site(const Geom &g, int i, int p, int c[4]
 // Fence between hops.  The kernel is one basic block, so the compiler would
 // issue every hop's loads first and do all the arithmetic afterwards (all
 // eight hops in flight, far beyond the register file).  The empty asm takes
-// the accumulator as an in/out operand, so a hop's arithmetic must be done
+// the accumulators as in/out operands, so a hop's arithmetic must be done
 // before it, and clobbers memory, so the next hop's loads stay after it.
 // WD_PARITY_FENCE = 1: a fence after every hop; 2: after each direction's pair of hops.
 #ifndef WD_PARITY_FENCE
 #define WD_PARITY_FENCE 1
 #endif
-template <typename T> __device__ __forceinline__ void hop_boundary(cx<T> acc[12], int level = 1) {
+template <typename T, int NR>
+__device__ __forceinline__ void hop_boundary(cx<T> (&acc)[NR][12], int level = 1) {
     if (level < WD_PARITY_FENCE) return;
 #pragma unroll
-    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].r), "+v"(acc[k].i) : : "memory");
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[r][k].r), "+v"(acc[r][k].i) : : "memory");
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int P, int MU, bool DAG, int ROWS>
-__device__ __forceinline__ void parity_hops(const OpData &d, const Geom &g, const void *hop, int Vh, int s,
-                                            const int c[4], bool apbc, typename Store<P>::T fh,
-                                            cx<typename Store<P>::T> acc[12]) {
+// Right-hand sides of one launch: a work-group row (blockIdx.y) takes NR
+// consecutive entries, so each lane loads its links and A(x) or A(x)^{-1}
+// once for all of them.
+constexpr int kParMax = 16;
+constexpr int kParNr = 2;  // right-hand sides per lane
+struct ParityTable {
+    void *out[kParMax];
+    const void *self[kParMax];
+    const void *hop[kParMax];
+    int n;
+};
+
+template <int P, int MU, bool DAG, int ROWS, int NR>
+__device__ __forceinline__ void parity_hops(const OpData &d, const Geom &g, const ParityTable &tab, int r0, int nr,
+                                            int Vh, int s, const int c[4], bool apbc, typename Store<P>::T fh,
+                                            cx<typename Store<P>::T> (&acc)[NR][12]) {
     using T = typename Store<P>::T;
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     const int st = g.stride[MU], L = g.n[MU];
     const int sf = (c[MU] == L - 1) ? s - (L - 1) * st : s + st;
     const int sb = (c[MU] == 0) ? s + (L - 1) * st : s - st;
-    cx<T> U[9], p[12], h[6], chi[6];
+    cx<T> U[9];
     {
         const T f = (MU == 0 && apbc && c[0] == g.n[0] - 1) ? -fh : fh;
         Store<P>::load_link(d.links, g.V, MU, s, U, ROWS);
-        Store<P>::load_spinor(hop, Vh, sf >> 1, p);
-        project<MU, SF>(p, h, f);
-        su3_mul<false>(U, h, chi);
-        reconstruct<MU, SF>(acc, chi);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < nr) {
+                cx<T> p[12], h[6], chi[6];
+                Store<P>::load_spinor(tab.hop[r0 + r], Vh, sf >> 1, p);
+                project<MU, SF>(p, h, f);
+                su3_mul<false>(U, h, chi);
+                reconstruct<MU, SF>(acc[r], chi);
+            }
+        }
     }
-    hop_boundary(acc, 1);
+    hop_boundary<T, NR>(acc, 1);
     {
         const T f = (MU == 0 && apbc && c[0] == 0) ? -fh : fh;
         Store<P>::load_link(d.links, g.V, MU, sb, U, ROWS);
-        Store<P>::load_spinor(hop, Vh, sb >> 1, p);
-        project<MU, SB>(p, h, f);
-        su3_mul<true>(U, h, chi);
-        reconstruct<MU, SB>(acc, chi);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (r < nr) {
+                cx<T> p[12], h[6], chi[6];
+                Store<P>::load_spinor(tab.hop[r0 + r], Vh, sb >> 1, p);
+                project<MU, SB>(p, h, f);
+                su3_mul<true>(U, h, chi);
+                reconstruct<MU, SB>(acc[r], chi);
+            }
+        }
     }
-    hop_boundary(acc, 2);
+    hop_boundary<T, NR>(acc, 2);
 }
 
 // SELF: 0 none, 1 the input, 2 A(x) times the input.  HOP: add fh * 2 * H hop
 // (fh = -1/2 adds H, +1/2 subtracts it).  INV: multiply the sum by A(x)^{-1}.
 // ROWS: stored rows per link (a compile-time constant: a run-time choice
-// between the two link formats costs the FP64 kernels spills).
-template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS>
-__global__ __launch_bounds__(256) void parity_kernel(void *out, const void *self,
-                                                     const void *hop, OpData d,
-                                                     const void *cinv, Geom g, int parity, int apbc,
-                                                     typename Store<P>::T fh, size_t rhs_bytes, int tpr) {
+// between the two link formats costs the FP64 kernels spills).  NR: right-
+// hand sides per lane (register block).
+template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS, int NR>
+__global__ __launch_bounds__(256) void parity_kernel(ParityTable tab, OpData d, const void *cinv, Geom g, int parity,
+                                                     int apbc, typename Store<P>::T fh, int tpr) {
     using T = typename Store<P>::T;
     const int Vh = g.V >> 1;
     int i;
@@ -112,89 +141,123 @@ __global__ __launch_bounds__(256) void parity_kernel(void *out, const void *self
         i = r0 + tile * (int)blockDim.x + (int)threadIdx.x;
         if (i >= r1) return;
     }
-    const size_t off = (size_t)blockIdx.y * rhs_bytes;
-    void *o = static_cast<char *>(out) + off;
+    const int r0 = (int)blockIdx.y * NR;
+    const int nr = min(NR, tab.n - r0);
     int c[4];
     const int s = parity_site(g, i, parity, c);
-    cx<T> acc[12];
+    cx<T> acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[r][k] = mk<T>(0, 0);
     if (SELF == 1) {
-        Store<P>::load_spinor(static_cast<const char *>(self) + off, Vh, i, acc);
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            if (r < nr) Store<P>::load_spinor(tab.self[r0 + r], Vh, i, acc[r]);
     } else if (SELF == 2) {
-        const void *in = static_cast<const char *>(self) + off;
 #pragma unroll
         for (int b = 0; b < 2; b++) {
-            cx<T> x[6];
-            Store<P>::load_half(in, Vh, i, b, x);
             if (d.clover_compact) {
                 T cr[28];
                 Store<P>::load_clover_compact(d.clover, g.V, b, s, cr);
-                clover_block_compact((T)d.diag, cr, x, &acc[6 * b]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if (r < nr) {
+                        cx<T> x[6];
+                        Store<P>::load_half(tab.self[r0 + r], Vh, i, b, x);
+                        clover_block_compact((T)d.diag, cr, x, &acc[r][6 * b]);
+                    }
+                }
             } else {
                 T dd[6];
                 cx<T> uu[15];
                 Store<P>::load_clover(d.clover, g.V, b, s, dd, uu);
-                clover_block(dd, uu, x, &acc[6 * b]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if (r < nr) {
+                        cx<T> x[6];
+                        Store<P>::load_half(tab.self[r0 + r], Vh, i, b, x);
+                        clover_block(dd, uu, x, &acc[r][6 * b]);
+                    }
+                }
             }
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
     }
     if (HOP) {
-        const void *hp = static_cast<const char *>(hop) + off;
-        hop_boundary(acc, 2);
-        parity_hops<P, 0, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
-        parity_hops<P, 1, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
-        parity_hops<P, 2, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
-        parity_hops<P, 3, DAG, ROWS>(d, g, hp, Vh, s, c, apbc != 0, fh, acc);
+        hop_boundary<T, NR>(acc, 2);
+        parity_hops<P, 0, DAG, ROWS, NR>(d, g, tab, r0, nr, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 1, DAG, ROWS, NR>(d, g, tab, r0, nr, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 2, DAG, ROWS, NR>(d, g, tab, r0, nr, Vh, s, c, apbc != 0, fh, acc);
+        parity_hops<P, 3, DAG, ROWS, NR>(d, g, tab, r0, nr, Vh, s, c, apbc != 0, fh, acc);
     }
     if (INV) {
-        cx<T> r[12];
 #pragma unroll
         for (int b = 0; b < 2; b++) {
             T dd[6];
             cx<T> uu[15];
             Store<P>::load_clover(cinv, g.V, b, s, dd, uu);
-            clover_block(dd, uu, &acc[6 * b], &r[6 * b]);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r < nr) {
+                    cx<T> y[6];
+                    clover_block(dd, uu, &acc[r][6 * b], y);
+#pragma unroll
+                    for (int k = 0; k < 6; k++) acc[r][6 * b + k] = y[k];
+                }
+            }
         }
-        Store<P>::store_spinor(o, Vh, i, r);
-    } else {
-        Store<P>::store_spinor(o, Vh, i, acc);
     }
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+        if (r < nr) Store<P>::store_spinor(tab.out[r0 + r], Vh, i, acc[r]);
 }
 
 template <int P, bool DAG, int SELF, bool HOP, bool INV>
-hipError_t launch_mode(const dirac_op *op, int parity, void *out, const void *self, const void *hop, double fh,
-                       int nrhs, hipStream_t st) {
+hipError_t launch_mode(const dirac_op *op, int parity, const std::vector<ParityItem> &items, double fh,
+                       hipStream_t st) {
     using T = typename Store<P>::T;
     const int Vh = op->g.V >> 1;
     const int hs = Vh / op->g.n[0];                 // half-lattice sites per T-slice
     const int tpr = ((hs + 7) / 8 + 255) / 256;     // 256-site tiles per eighth of a slice
-    const dim3 grid(op->g.n[0] * 8 * tpr, nrhs);
     const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
-    if (op->link_rows == 2 || !HOP)
-        hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2>), grid, dim3(256), 0, st, out, self, hop,
-                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh), tpr);
-    else
-        hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 3>), grid, dim3(256), 0, st, out, self, hop,
-                           op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, field_rhs_bytes(P, Vh), tpr);
-    return hipGetLastError();
+    const bool rows2 = op->link_rows == 2 || !HOP;
+    for (size_t a = 0; a < items.size(); a += kParMax) {
+        ParityTable tab;
+        tab.n = (int)std::min<size_t>(kParMax, items.size() - a);
+        for (int q = 0; q < tab.n; q++) {
+            tab.out[q] = items[a + q].out;
+            tab.self[q] = items[a + q].self;
+            tab.hop[q] = items[a + q].hop;
+        }
+        // one instantiation (pairs) for every count, a lone last right-hand side included: a single-RHS
+        // instantiation rounds differently, and results must not depend on how right-hand sides are grouped
+        const dim3 grid(op->g.n[0] * 8 * tpr, (tab.n + kParNr - 1) / kParNr);
+        if (rows2)
+            hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2, kParNr>), grid, dim3(256), 0, st, tab,
+                               op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpr);
+        else
+            hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 3, kParNr>), grid, dim3(256), 0, st, tab,
+                               op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int P>
-hipError_t launch_p(int mode, bool dag, const dirac_op *op, int parity, void *out, const void *self, const void *hop,
-                    int nrhs, hipStream_t st) {
+hipError_t launch_p(int mode, bool dag, const dirac_op *op, int parity, const std::vector<ParityItem> &it,
+                    hipStream_t st) {
     switch (mode) {
     case kParHopInv:
-        return dag ? launch_mode<P, true, 0, true, true>(op, parity, out, self, hop, -0.5, nrhs, st)
-                   : launch_mode<P, false, 0, true, true>(op, parity, out, self, hop, -0.5, nrhs, st);
+        return dag ? launch_mode<P, true, 0, true, true>(op, parity, it, -0.5, st)
+                   : launch_mode<P, false, 0, true, true>(op, parity, it, -0.5, st);
     case kParCloverSub:
-        return dag ? launch_mode<P, true, 2, true, false>(op, parity, out, self, hop, 0.5, nrhs, st)
-                   : launch_mode<P, false, 2, true, false>(op, parity, out, self, hop, 0.5, nrhs, st);
-    case kParApply: return launch_mode<P, false, 2, true, false>(op, parity, out, self, hop, -0.5, nrhs, st);
-    case kParInvSelf: return launch_mode<P, false, 1, false, true>(op, parity, out, self, hop, 0.0, nrhs, st);
-    case kParSelfSub: return launch_mode<P, false, 1, true, false>(op, parity, out, self, hop, 0.5, nrhs, st);
-    case kParInvSelfSub: return launch_mode<P, false, 1, true, true>(op, parity, out, self, hop, 0.5, nrhs, st);
+        return dag ? launch_mode<P, true, 2, true, false>(op, parity, it, 0.5, st)
+                   : launch_mode<P, false, 2, true, false>(op, parity, it, 0.5, st);
+    case kParApply: return launch_mode<P, false, 2, true, false>(op, parity, it, -0.5, st);
+    case kParInvSelf: return launch_mode<P, false, 1, false, true>(op, parity, it, 0.0, st);
+    case kParSelfSub: return launch_mode<P, false, 1, true, false>(op, parity, it, 0.5, st);
+    case kParInvSelfSub: return launch_mode<P, false, 1, true, true>(op, parity, it, 0.5, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -321,15 +384,38 @@ __global__ __launch_bounds__(256) void clover_invert_kernel(double2 *__restrict_
 
 }  // namespace
 
-hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int parity, void *out, const void *self,
-                         const void *hop, int nrhs, hipStream_t st) {
-    if (nrhs < 1) return hipSuccess;
+hipError_t parity_launch_list(int mode, int prec, bool dag, const dirac_op *op, int parity,
+                              const std::vector<ParityItem> &items, hipStream_t st) {
+    if (items.empty()) return hipSuccess;
     switch (prec) {
-    case WDIRAC_F64: return launch_p<WDIRAC_F64>(mode, dag, op, parity, out, self, hop, nrhs, st);
-    case WDIRAC_F32: return launch_p<WDIRAC_F32>(mode, dag, op, parity, out, self, hop, nrhs, st);
-    case WDIRAC_F16S: return launch_p<WDIRAC_F16S>(mode, dag, op, parity, out, self, hop, nrhs, st);
+    case WDIRAC_F64: return launch_p<WDIRAC_F64>(mode, dag, op, parity, items, st);
+    case WDIRAC_F32: return launch_p<WDIRAC_F32>(mode, dag, op, parity, items, st);
+    case WDIRAC_F16S: return launch_p<WDIRAC_F16S>(mode, dag, op, parity, items, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int parity, void *out, const void *self,
+                         const void *hop, int nrhs, hipStream_t st) {
+    const size_t rb = field_rhs_bytes(prec, op->g.V / 2);
+    std::vector<ParityItem> items;
+    for (int r = 0; r < nrhs; r++)
+        items.push_back({static_cast<char *>(out) + r * rb,
+                         self ? static_cast<const char *>(self) + r * rb : nullptr,
+                         hop ? static_cast<const char *>(hop) + r * rb : nullptr});
+    return parity_launch_list(mode, prec, dag, op, parity, items, st);
+}
+
+hipError_t schur_apply_list(int prec, bool dag, const dirac_op *op, const std::vector<SchurItem> &items,
+                            hipStream_t st) {
+    std::vector<ParityItem> a, b;
+    for (const SchurItem &it : items) {
+        a.push_back({it.tmp, nullptr, it.in});
+        b.push_back({it.out, it.in, it.tmp});
+    }
+    hipError_t e = parity_launch_list(kParHopInv, prec, dag, op, 1, a, st);
+    if (e != hipSuccess) return e;
+    return parity_launch_list(kParCloverSub, prec, dag, op, 0, b, st);
 }
 
 hipError_t schur_apply(int prec, bool dag, const dirac_op *op, void *out, const void *in, void *tmp, int nrhs,
