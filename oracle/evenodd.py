@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import clover_term, dirac_apply, volume
+from . import clover_term, clover_term_sites, dirac_apply, dirac_apply_sites, volume
 
 
 def parity(dims) -> np.ndarray:
@@ -62,7 +62,11 @@ def site_matrices(dims, links, m0: float, csw: float, clover=None) -> np.ndarray
     V = volume(dims)
     if clover is None:
         clover = clover_term(dims, links) if csw != 0.0 else np.zeros((V, 42), np.complex128)
-    C = np.asarray(clover, np.complex128).reshape(V, 42)
+    return _matrices_from_rows(np.asarray(clover, np.complex128).reshape(V, 42), m0, csw)
+
+
+def _matrices_from_rows(C, m0: float, csw: float) -> np.ndarray:
+    V = C.shape[0]
     A = np.zeros((V, 12, 12), np.complex128)
     iu = np.triu_indices(6, 1)
     for blk in range(2):
@@ -126,3 +130,38 @@ class EvenOdd:
     def reconstruct(self, xe, bo):
         """x_o = A_oo^{-1} (b_o - H_oe x_e)."""
         return self.ainv_o(bo - self.hop_oe(xe))
+
+
+def neighbours(dims, sites) -> np.ndarray:
+    """[n, 8] lexicographic neighbours (x + mu, x - mu for mu = T, Z, Y, X) of the listed sites."""
+    n = np.asarray(dims, np.int64)
+    s = np.asarray(sites, np.int64)
+    c = np.stack([s // (n[1] * n[2] * n[3]), (s // (n[2] * n[3])) % n[1], (s // n[3]) % n[2], s % n[3]], -1)
+    out = []
+    for mu in range(4):
+        for d in (1, -1):
+            cc = c.copy()
+            cc[:, mu] = (cc[:, mu] + d) % n[mu]
+            out.append(((cc[:, 0] * n[1] + cc[:, 1]) * n[2] + cc[:, 2]) * n[3] + cc[:, 3])
+    return np.stack(out, -1)
+
+
+def schur_sites(dims, links, xe, sites, m0: float, csw: float, antiperiodic_t: bool = False) -> np.ndarray:
+    """(S x_e) at the listed even sites (full-lattice indices), [n, 12], computed
+    from their neighbourhood only: t_o = A_oo^{-1} (H x_e) at the odd
+    neighbours, then A(x) x_e(x) - (H t_o)(x).  For lattices too large for the
+    whole-lattice class above."""
+    V = volume(dims)
+    sites = np.asarray(sites, np.int64)
+    assert np.all(parity(dims)[sites] == 0)
+    full = np.zeros((V, 12), np.complex128)
+    full[sites_of(dims, 0)] = xe
+    odd = np.unique(neighbours(dims, sites))
+    h = dirac_apply_sites(dims, links, full, odd, -4.0, 0.0, antiperiodic_t=antiperiodic_t)
+    Co = clover_term_sites(dims, links, odd) if csw != 0.0 else np.zeros((len(odd), 42), np.complex128)
+    t = np.linalg.solve(_matrices_from_rows(Co, m0, csw), h[..., None])[..., 0]
+    tf = np.zeros((V, 12), np.complex128)
+    tf[odd] = t
+    ht = dirac_apply_sites(dims, links, tf, sites, -4.0, 0.0, antiperiodic_t=antiperiodic_t)
+    Ce = clover_term_sites(dims, links, sites) if csw != 0.0 else np.zeros((len(sites), 42), np.complex128)
+    return np.einsum("sij,sj->si", _matrices_from_rows(Ce, m0, csw), full[sites]) - ht

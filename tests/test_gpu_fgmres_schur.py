@@ -133,3 +133,61 @@ def test_reduced_argument_errors():
     with pytest.raises(WdiracError) as e:
         op2.solve(op2.pack(to_dev(b), "f64"), schur=True, mode="mixed_f16s")
     assert e.value.code in (-1, -4) and "not materialised" in str(e.value)
+
+
+def test_full_size_reduced_operator_sampled():
+    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links and compact clover (the
+    benchmark's operator): S applied to two right-hand sides in one paired
+    launch, checked at 192 sampled even sites against the oracle's
+    neighbourhood evaluation (FP64 to 1e-13, FP16S to 5e-3)."""
+    need_gpu()
+    dims = (96, 48, 48, 48)
+    m0, csw = -0.35, 1.0
+    Ud = synth.smooth_links(dims, 1006, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f16s"), compress_links=True, compress_clover=True,
+                 even_odd=True)
+    psi = synth.gaussian_spinor(dims, 2600, nrhs=2, device="cuda")
+    even_sites = evenodd.sites_of(dims, 0)
+    rng = np.random.default_rng(12)
+    pick = np.sort(rng.choice(len(even_sites), 192, replace=False))
+    for prec, tol in (("f64", 1e-13), ("f16s", 5e-3)):
+        e, o = op.split(op.pack(psi, prec), prec, 2)
+        out, tmp = op.empty_parity(prec, 2), op.empty_parity(prec, 2)
+        out.zero_()
+        op.apply_schur_native(out, e, tmp, 2, prec)
+        z = op.empty_parity(prec, 2)
+        z.zero_()
+        got = op.unpack(op.merge(out, z, prec, 2), prec, 2)[:, torch.from_numpy(even_sites[pick]).cuda()].cpu().numpy()
+        del e, o, out, tmp, z
+        for r in range(2):
+            xe = psi[r].cpu().numpy()[even_sites]
+            want = evenodd.schur_sites(dims, U, xe, even_sites[pick], m0, csw)
+            assert np.linalg.norm(got[r] - want) / np.linalg.norm(want) < tol, (prec, r)
+    del op
+    torch.cuda.empty_cache()
+
+
+def test_full_size_reduced_mixed_fgmres_bench_configuration():
+    """The benchmark's mixed solver on the even-odd reduced system at 48^3 x 96
+    to 1e-10: the full system's true residual of the returned solution,
+    computed by the oracle operator over the whole lattice."""
+    need_gpu()
+    dims = (96, 48, 48, 48)
+    m0, csw = -0.35, 1.0
+    Ud = synth.smooth_links(dims, 1004, device="cuda")
+    bd = synth.gaussian_spinor(dims, 2400, nrhs=1, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f16s"), compress_links=True, compress_clover=True,
+                 even_odd=True)
+    bn = op.pack(bd, "f64")
+    x, st, rc = op.solve(bn, restart=8, tol=1e-10, maxit=500, mode="mixed_f16s", inner_restart=10, inner_tol=0.1,
+                         inner_maxit=10, schur=True)
+    assert rc == 0 and st[0]["converged"], st[0]
+    assert st[0]["true_residual"] < 1e-10
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    del op, x, bn
+    torch.cuda.empty_cache()
+    assert true_relres(dims, U, m0, csw, xg, bd.cpu().numpy()[0]) <= 1e-10 * 1.01

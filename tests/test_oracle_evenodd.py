@@ -110,3 +110,18 @@ def test_reduced_fgmres_solves_the_full_system():
     x = evenodd.merge(dims, xe, eo.reconstruct(xe, bo))
     r = b - oracle.dirac_apply(dims, U, x, m0, csw)
     assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-10
+
+
+def test_schur_at_sites_equals_whole_lattice():
+    """The neighbourhood-only evaluation used at full size agrees with the
+    whole-lattice definition (also anti-periodic, and with extent 2)."""
+    for dims, ap in [((4, 6, 2, 4), True), ((2, 4, 4, 2), False)]:
+        U = synth.smooth_links(dims, 3).numpy()
+        eo = evenodd.EvenOdd(dims, U, -0.3, 1.0, antiperiodic_t=ap)
+        Vh = synth.volume(dims) // 2
+        rng = np.random.default_rng(1)
+        xe = rng.standard_normal((Vh, 12)) + 1j * rng.standard_normal((Vh, 12))
+        want = eo.schur(xe)
+        pick = np.array([0, 5, Vh // 2, Vh - 1])
+        got = evenodd.schur_sites(dims, U, xe, evenodd.sites_of(dims, 0)[pick], -0.3, 1.0, antiperiodic_t=ap)
+        assert rel(got, want[pick]) < 1e-14
