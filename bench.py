@@ -15,6 +15,7 @@ timed steps (reported under "extra"):
   * single FP32 and FP16S applies;
   * one FP32 launch over uneven batches {1, 4, 12, 24} (autotuned: tile order,
     register blocks or the link-stationary kernel);
+  * the even-odd reduced operator S alone (one right-hand side, and pairs);
   * 12 right-hand sides solved to 1e-10 by plain FP64 FGMRES(30) and by the
     mixed solver (FP64 outer FGMRES(8) whose preconditioner is an inner
     GMRES(10) on the FP16S operator, relative tolerance 0.1), in memory-sized
@@ -121,6 +122,39 @@ def time_launches(torch, fn, steps, warmup, stream):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / steps        # ms per launch
+
+
+# Algorithmic bytes per full-lattice site of one application of the even-odd
+# reduced operator S (two launches over V/2 sites: A_oo^-1 H_oe, then
+# A_ee - H_eo), with two-row links, compact A on the even sites and packed
+# A^-1 on the odd ones; per half-site: FP64 192 in + 8 x 96 links + 576 A^-1 +
+# 192 out, then 192 self + 192 in + 768 links + 448 A + 192 out (3520, i.e.
+# 1760 per site); in pairs the links and A / A^-1 are shared by two right-hand
+# sides (1120 per site per RHS).  FP32 / FP16S likewise with 96 / 52 B spinors,
+# 48 / 24 B links, 288 / 144 B A^-1 and 224 / 112 B compact A.
+SCHUR_BYTES_SITE = {"f64": (1760, 1120), "f32": (880, 560), "f16s": (450, 290)}
+
+
+def schur_apply_run(torch, op, psid, stream, steps=20):
+    """The reduced operator S: ms per application for one right-hand side and
+    per right-hand side of a pair, at every precision."""
+    res = {}
+    V = op.V
+    for p in ("f64", "f32", "f16s"):
+        nat = op.pack(torch.cat([psid, psid]), p)
+        e, o = op.split(nat, p, 2)
+        del nat, o
+        out, tmp = op.empty_parity(p, 2), op.empty_parity(p, 2)
+        rb = op.parity_field_bytes(p, 1)
+        one = time_launches(torch, lambda: op.apply_schur_native(out[:rb], e[:rb], tmp[:rb], 1, p), steps, 3,
+                            stream)
+        two = time_launches(torch, lambda: op.apply_schur_native(out, e, tmp, 2, p), steps, 3, stream) / 2
+        b1, b2 = SCHUR_BYTES_SITE[p]
+        res[p] = {"ms_single": one, "ms_per_rhs_pair": two, "alg_bytes_per_site": [b1, b2],
+                  "alg_GBps_single": b1 * V / (one * 1e-3) / 1e9, "alg_GBps_pair": b2 * V / (two * 1e-3) / 1e9}
+        del e, out, tmp
+    torch.cuda.empty_cache()
+    return res
 
 
 def batched_run(torch, op, dims, stream, steps):
@@ -424,6 +458,10 @@ def main():
         extra["batched"] = batched_run(torch, op, dims, stream, 10)
         extra["batched"]["per_rhs_rate_vs_fp64_single"] = extra["batched"]["rhs_applies_per_s"] / apps
         log(f"[bench] batched: {extra['batched']['rhs_applies_per_s']:.0f} RHS-applies/s")
+    if not a.no_extra:
+        extra["even_odd_apply"] = schur_apply_run(torch, op, psid, stream)
+        log("[bench] even-odd S: " + ", ".join(f"{p} {v['ms_single']:.3f} ms ({v['ms_per_rhs_pair']:.3f} per RHS of a "
+                                                f"pair)" for p, v in extra["even_odd_apply"].items()))
     if not a.no_extra and not a.no_fgmres and a.fgmres_rhs > 0:
         extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs)
     if not a.no_extra:

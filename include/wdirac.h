@@ -344,8 +344,8 @@ int dirac_parity_merge(const dirac_op *op, void *full, const void *even, const v
 int dirac_apply_schur(const dirac_op *op, void *out, const void *in, void *tmp, int nrhs, int prec, int dagger,
                       void *stream);
 /* bhat = b_even - H_eo A_oo^{-1} b_odd (the reduced right-hand side); tmp:
- * nrhs odd fields receiving A_oo^{-1} b_odd (may be b_odd itself); bhat may
- * be b_even itself and must not overlap tmp. */
+ * nrhs odd fields receiving A_oo^{-1} b_odd (may be b_odd itself, must not
+ * overlap b_even); bhat may be b_even itself and must not overlap tmp. */
 int dirac_schur_prepare(const dirac_op *op, void *bhat, const void *b_even, const void *b_odd, void *tmp, int nrhs,
                         int prec, void *stream);
 /* x_odd = A_oo^{-1} (b_odd - H_oe x_even); x_odd may be b_odd itself and

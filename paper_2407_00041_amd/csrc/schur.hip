@@ -543,6 +543,7 @@ int dirac_schur_prepare(const dirac_op *op, void *bhat, const void *b_even, cons
     if (rc) return rc;
     rc = check_out(bhat, b_even, tmp, nh);
     if (rc) return rc;
+    if (overlaps(tmp, nh, b_even, nh)) return fail(WDIRAC_EINVAL, "tmp overlaps b_even (written before it is read)");
     hipStream_t st = (hipStream_t)stream;
     rc = hip_result(parity_launch(kParInvSelf, prec, false, op, 1, tmp, b_odd, nullptr, nrhs, st), "prepare launch");
     if (rc) return rc;

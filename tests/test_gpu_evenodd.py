@@ -151,6 +151,10 @@ def test_even_odd_errors():
     # the output may not overlap the field read at neighbours
     assert op2.lib.dirac_schur_reconstruct(op2.handle, e.data_ptr(), e.data_ptr(), o.data_ptr(), 1, 0, s) == \
         _lib.EINVAL
+    # prepare: tmp is written before b_even is read
+    bh = op2.empty_parity("f64")
+    assert op2.lib.dirac_schur_prepare(op2.handle, bh.data_ptr(), e.data_ptr(), o.data_ptr(), e.data_ptr(), 1, 0,
+                                       s) == _lib.EINVAL
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
