@@ -442,8 +442,6 @@ hipError_t clover_invert_launch(double2 *inv_can, const double2 *can, int V, dou
     return hipGetLastError();
 }
 
-int check_apply(const dirac_op *op, const void *out, const void *in, int nrhs, int prec);
-
 }  // namespace wd
 
 using namespace wd;

@@ -69,6 +69,16 @@ def test_argument_errors_without_device():
     assert lib.dirac_field_bytes(None, 0, 1) == 0
     assert lib.dirac_pack(None, None, None, 1, 0, None) == _lib.EINVAL
     assert lib.dirac_clover_term(None, None, None, None) == _lib.EINVAL
+    # even-odd entry points and the force: a null operator is rejected before any device call
+    assert lib.dirac_parity_field_bytes(None, 0, 1) == 0
+    assert lib.dirac_parity_split(None, None, None, None, 1, 0, None) == _lib.EINVAL
+    assert lib.dirac_parity_merge(None, None, None, None, 1, 0, None) == _lib.EINVAL
+    assert lib.dirac_apply_schur(None, None, None, None, 1, 0, 0, None) == _lib.EINVAL
+    assert lib.dirac_schur_prepare(None, None, None, None, None, 1, 0, None) == _lib.EINVAL
+    assert lib.dirac_schur_reconstruct(None, None, None, None, 1, 0, None) == _lib.EINVAL
+    assert b"null operator" in lib.dirac_last_error()
+    assert lib.dirac_force_workspace_bytes(None) == 0
+    assert lib.dirac_force(None, None, None, None, 1, 0, None, 0, None) == _lib.EINVAL
 
 
 def test_product_path_has_no_fallback(monkeypatch, tmp_path):
