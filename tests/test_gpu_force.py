@@ -35,9 +35,9 @@ def test_force_matches_oracle_every_link(dims, csw, ap, kind):
 
 
 def test_force_full_size_24_48_sampled_and_fd():
-    """24^3 x 48, c_sw = 1: 64 random links against the oracle; 6 of them also
-    against central differences (h = 1e-6) of L = Re<eta, D(U) x> formed site
-    by site through the GPU apply."""
+    """24^3 x 48, c_sw = 1: 64 random links against the oracle and against
+    central differences (h = 1e-6) of L = Re<eta, D(U) x> through the GPU
+    apply (the link moved along a random su(3) generator each time)."""
     need_gpu()
     dims = (48, 24, 24, 24)
     V = synth.volume(dims)
@@ -57,7 +57,7 @@ def test_force_full_size_24_48_sampled_and_fd():
     assert rel_l2(G[s_t, d_t].cpu().numpy(), Go) < 1e-12
     assert rel_l2(F[s_t, d_t].cpu().numpy(), Fo) < 1e-12
     h = 1e-6
-    for k in range(6):
+    for k in range(64):
         a = int(rng.integers(0, 8))
         T = 0.5j * synth.GELL_MANN[a]
         ev, W = np.linalg.eigh(-1j * T)                   # T = i W diag(ev) W^H
