@@ -378,8 +378,8 @@ def main():
     a = parse()
     TUNE_FIXED = bool(a.fixed_launch)
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU halo exchange "
-                                   "is not part of this build"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no multi-GPU "
+                                   "halo exchange"}))
         sys.exit(2)
     import torch
 
