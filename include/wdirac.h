@@ -269,7 +269,8 @@ typedef struct {
     int schur;          /* 1 = solve the even-odd reduced system S x_e = bhat */
                         /* (operator created with WDIRAC_EVEN_ODD) and       */
                         /* reconstruct x_o; tol stays relative to the full   */
-                        /* |b - D x0|; applies count applications of S       */
+                        /* |b - D x0|; only the even sites of x0 start the   */
+                        /* iteration; applies count applications of S       */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096
