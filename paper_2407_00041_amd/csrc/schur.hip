@@ -223,7 +223,10 @@ __global__ __launch_bounds__(256) void parity_kernel(ParityTable tab, OpData d, 
 // U_T(t+1)^H (1 + s gamma_T) psi(t+1) is formed once and carried in registers
 // (one spinor load per site saved).  Work-groups are dealt as in the T-sweep
 // above: each XCD takes 1/8 of the columns of every T-chunk.
-constexpr int kParChunk = 4;
+#ifndef WD_PARITY_CHUNK
+#define WD_PARITY_CHUNK 4
+#endif
+constexpr int kParChunk = WD_PARITY_CHUNK;  // T-slices per chunk (kParChunk / 2 sites per lane)
 
 template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS, int NR>
 __global__ __launch_bounds__(256) void parity_column_kernel(ParityTable tab, OpData d, const void *cinv, Geom g,
