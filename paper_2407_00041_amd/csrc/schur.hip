@@ -73,6 +73,9 @@ constexpr int kParNr = 2;  // right-hand sides per lane
 #ifndef WD_PARITY_COLUMN
 #define WD_PARITY_COLUMN 1
 #endif
+#ifndef WD_PARITY_COLUMN_F16
+#define WD_PARITY_COLUMN_F16 0
+#endif
 constexpr bool kParColumnWalk = WD_PARITY_COLUMN != 0;
 struct ParityTable {
     void *out[kParMax];
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void parity_kernel(ParityTable tab, OpData d, 
 #endif
 constexpr int kParChunk = WD_PARITY_CHUNK;  // T-slices per chunk (kParChunk / 2 sites per lane)
 
-template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS, int NR>
+template <int P, bool DAG, int SELF, bool HOP, bool INV, int ROWS, int NR, int CH>
 __global__ __launch_bounds__(256) void parity_column_kernel(ParityTable tab, OpData d, const void *cinv, Geom g,
                                                             int parity, int apbc, typename Store<P>::T fh,
                                                             int tpr) {
@@ -244,9 +247,9 @@ __global__ __launch_bounds__(256) void parity_column_kernel(ParityTable tab, OpD
         const int q0 = (int)(((long long)k * C) >> 3), q1 = (int)(((long long)(k + 1) * C) >> 3);
         col = q0 + tile * (int)blockDim.x + (int)threadIdx.x;
         if (col >= q1) return;
-        t0 = tc * kParChunk;
+        t0 = tc * CH;
     }
-    const int t1 = min(t0 + kParChunk, nT);
+    const int t1 = min(t0 + CH, nT);
     const int r0 = (int)blockIdx.y * NR;
     const int nr = min(NR, tab.n - r0);
     int c[4];
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(256) void parity_column_kernel(ParityTable tab, OpD
             const bool wrap = (t == nT - 1);
             const int tp = wrap ? 0 : t + 1;
             const T ff = (apbc && wrap) ? -fh : fh;
-            const bool next = t + 2 < t1;
+            const bool next = CH > 2 && t + 2 < t1;  // chunks of 2 slices: one site per lane, nothing carried
             cx<T> U[9], Un[9];
             Store<P>::load_link(d.links, g.V, 0, s, U, ROWS);
             if (next) Store<P>::load_link(d.links, g.V, 0, tp * C + col, Un, ROWS);
@@ -386,19 +389,19 @@ hipError_t launch_mode(const dirac_op *op, int parity, const std::vector<ParityI
         // one instantiation (pairs) for every count, a lone last right-hand side included: a single-RHS
         // instantiation rounds differently, and results must not depend on how right-hand sides are grouped
         const dim3 grid(op->g.n[0] * 8 * tpr, (tab.n + kParNr - 1) / kParNr);
-        if constexpr (HOP && P != WDIRAC_F16S) {
-            // FP64/FP32 only: at FP16S the site kernel measured faster (1.23 vs 1.30 ms per S at 48^3 x 96)
+        if constexpr (HOP && (P != WDIRAC_F16S || WD_PARITY_COLUMN_F16)) {
             if (kParColumnWalk) {
-                // the column walk: T-chunks of kParChunk slices, each XCD 1/8 of the columns
+                // the column walk: T-chunks of CH slices, each XCD 1/8 of the columns
+                constexpr int CH = P == WDIRAC_F16S ? 2 : kParChunk;
                 const int C = op->g.stride[0];
                 const int tpc = ((C + 7) / 8 + 255) / 256;
-                const dim3 gc((op->g.n[0] + kParChunk - 1) / kParChunk * 8 * tpc, grid.y);
+                const dim3 gc((op->g.n[0] + CH - 1) / CH * 8 * tpc, grid.y);
                 if (rows2)
-                    hipLaunchKernelGGL((parity_column_kernel<P, DAG, SELF, HOP, INV, 2, kParNr>), gc, dim3(256), 0,
-                                       st, tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpc);
+                    hipLaunchKernelGGL((parity_column_kernel<P, DAG, SELF, HOP, INV, 2, kParNr, CH>), gc, dim3(256),
+                                       0, st, tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpc);
                 else
-                    hipLaunchKernelGGL((parity_column_kernel<P, DAG, SELF, HOP, INV, 3, kParNr>), gc, dim3(256), 0,
-                                       st, tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpc);
+                    hipLaunchKernelGGL((parity_column_kernel<P, DAG, SELF, HOP, INV, 3, kParNr, CH>), gc, dim3(256),
+                                       0, st, tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpc);
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
                 continue;
