@@ -49,8 +49,13 @@
  *                  Entry points documented "asynchronous" only enqueue work.
  *   Ownership    : the handle owns every device buffer it allocates;
  *                  dirac_destroy frees them.  Caller buffers stay the caller's.
- *   Threads      : a handle is immutable after dirac_create, so concurrent
- *                  applies on different streams are safe.
+ *   Threads      : a handle is immutable after dirac_create, so applies of
+ *                  one handle may be issued from several host threads onto
+ *                  different streams.  The process-wide launch knobs
+ *                  (dirac_tune_set) and the autotuner's table are guarded by
+ *                  locks; a launch uses the values current when it is
+ *                  issued.  Calls that share caller-owned buffers (outputs,
+ *                  workspaces) must not overlap.
  */
 #ifndef WDIRAC_H
 #define WDIRAC_H
@@ -68,6 +73,8 @@ extern "C" {
 #define WDIRAC_EHIP (-3)         /* a HIP runtime call or launch failed     */
 #define WDIRAC_EUNSUPPORTED (-4) /* precision not materialised, no device   */
 #define WDIRAC_ENOTCONV 1        /* solver hit maxit; result still valid    */
+#define WDIRAC_ENONFINITE 2      /* solver met NaN/Inf in some right-hand   */
+                                 /* side's b, x0 or residuals; see stats    */
 
 /* precisions */
 #define WDIRAC_F64 0
@@ -123,7 +130,8 @@ const char *dirac_version(void);
  *            precision) for the even-odd functions below.
  * Synchronous.  Copies everything into device memory owned by the handle;
  * the caller may free its arrays on return.  Errors: EINVAL (null pointer,
- * dims < 2, non-SU(3) links with WDIRAC_COMPRESS_LINKS, a clover without the
+ * dims < 2, a NaN or Inf entry in the links or in the clover passed in,
+ * non-SU(3) links with WDIRAC_COMPRESS_LINKS, a clover without the
  * structure above with WDIRAC_COMPRESS_CLOVER, an odd extent or a (nearly)
  * singular block of A with WDIRAC_EVEN_ODD), ENOMEM, EHIP, EUNSUPPORTED
  * (no HIP device).
@@ -144,8 +152,12 @@ size_t dirac_field_bytes(const dirac_op *op, int prec, int nrhs);
 /*
  * out = D in (Eq. (1.13)), for nrhs right-hand sides in native layout at
  * precision prec, on device buffers of dirac_field_bytes(op, prec, nrhs)
- * bytes each.  Reads each link and clover entry once per site and block of
- * right-hand sides.  Asynchronous on `stream`; no allocation, no host sync.
+ * bytes each.  Each lane loads the links and clover entries its site needs
+ * once per block of right-hand sides; a link or neighbour spinor that
+ * several sites use is loaded by each of them, and the caches absorb only
+ * part of those repeats (at 48^3 x 96 the FP64 apply reads about 1.6x its
+ * algorithmic bytes from the memory side of the L2).  Asynchronous on
+ * `stream`; no allocation, no host sync.
  * Errors: EINVAL (null, nrhs < 1, out overlapping in, unknown prec),
  * EUNSUPPORTED (prec not materialised by dirac_create), EHIP (launch).
  */
@@ -225,7 +237,10 @@ int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_out[5], doubl
 int dirac_tune_clear(void);
 
 /*
- * Canonical <-> native conversion of device fields.
+ * Canonical <-> native conversion of device fields: the reordering of a
+ * site's consecutive components into component-major arrays of the paper's
+ * componentwise storage (Sec. 4.5, Eq. (4.1), and the reordering step of
+ * Listing 4.4), here with one 16-, 8- or 4-byte vector per (block, site).
  *   dirac_pack   : native[prec] <- canonical complex128 [nrhs][V][12]
  *                  (F32: round to nearest even; F16S: per-site scale as
  *                  documented above, round to nearest even).
@@ -265,7 +280,12 @@ typedef struct {
                         /* 0 = issue it step by step                         */
     int wave;           /* right-hand sides solved together (lockstep, one   */
                         /* batched apply per step); nrhs is processed in     */
-                        /* consecutive waves of this size; 0 = all at once   */
+                        /* consecutive waves of this size.  0 = chosen by    */
+                        /* the library: fgmres_workspace_bytes sizes the     */
+                        /* wave from the free device memory (minus a reserve */
+                        /* of max(1/16 of the device, 4 GiB)), fgmres_solve  */
+                        /* fits as many right-hand sides per wave as its     */
+                        /* workspace holds; the wave used is in the stats    */
     int schur;          /* 1 = solve the even-odd reduced system S x_e = bhat */
                         /* (operator created with WDIRAC_EVEN_ODD) and       */
                         /* reconstruct x_o; tol stays relative to the full   */
@@ -281,6 +301,13 @@ typedef struct {
     long long restarts;         /* outer cycles                              */
     int converged;              /* 1 if the tolerance was met                */
     int breakdown;              /* 1 if |h_{j+1,j}| < tol/10 ended a cycle   */
+    int nonfinite;              /* 1 if a NaN/Inf appeared in ||b - D x0||,  */
+                                /* a restart residual or a Hessenberg column */
+                                /* (b, x0 or the operator data not finite):  */
+                                /* the right-hand side stops, converged = 0, */
+                                /* true_residual = NaN, and x holds x0 or    */
+                                /* the iterate of its last completed cycle   */
+    int wave;                   /* right-hand sides of the wave it ran in    */
     double true_residual;       /* final ||b - D x|| / ||b - D x0||, FP64    */
     double seconds;             /* wall time of the solve (of its wave)      */
     double seconds_apply;       /* of which FP64 operator applications,      */
@@ -291,8 +318,10 @@ typedef struct {
     double hist[FGMRES_HIST_MAX]; /* relative residual estimate per step    */
 } fgmres_stats;
 
-/* Workspace bytes fgmres_solve needs for `nrhs` right-hand sides (for one
- * wave of min(p->wave, nrhs) of them when p->wave > 0). */
+/* Workspace bytes fgmres_solve needs for `nrhs` right-hand sides: for one
+ * wave of min(p->wave, nrhs) of them when p->wave > 0, or for a wave sized
+ * from the free device memory when p->wave == 0 (at least one right-hand
+ * side).  0 on bad arguments. */
 size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nrhs);
 
 /*
@@ -304,11 +333,19 @@ size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nr
  *          entry (x0) and the solution on return.
  *   st   : host array of nrhs stats records (may be NULL); `seconds` is the
  *          wall time of the wave that solved the right-hand side.
- *   work : device workspace of at least fgmres_workspace_bytes(op, p, nrhs),
- *          reused by every wave.
+ *   work : device workspace (256-byte aligned) of at least
+ *          fgmres_workspace_bytes(op, p, nrhs) bytes for p->wave > 0; with
+ *          p->wave == 0 every wave takes as many right-hand sides as
+ *          work_bytes can hold (at least one).  Reused by every wave.
  * Blocks until done (one host synchronisation per outer Arnoldi step to read
- * the residual estimates, plus one per inner step unless p->graph is set).  Returns WDIRAC_ENOTCONV (> 0) when some right-hand
- * side reached maxit (x still holds its last iterate); errors: EINVAL,
+ * the residual estimates, plus one per inner step unless p->graph is set).
+ * Each call also allocates a small pinned host staging buffer (a few KB) and
+ * four HIP events for the phase timers, and, with p->graph, its graphs; all
+ * are released before it returns.
+ * Returns WDIRAC_ENONFINITE (> 0) when some right-hand side met a NaN or Inf
+ * (its stats record has nonfinite = 1; the other right-hand sides are solved
+ * as if it were absent), else WDIRAC_ENOTCONV (> 0) when some right-hand side
+ * reached maxit (x still holds its last iterate); errors: EINVAL,
  * EUNSUPPORTED (mixed-mode precision not materialised), EHIP.
  */
 int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs,
@@ -317,7 +354,11 @@ int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs,
 
 /* ------------------------------------------------------------------------ */
 /*
- * Even-odd (red-black) reduction.  With D = A + H (A(x) the site-local term,
+ * Even-odd (red-black) reduction.  Red-black ordering is one of the
+ * splittings the paper's solver library uses in its Schwarz smoothers
+ * (Sec. 1.3); here it is applied to the whole system as a Schur complement
+ * (sites coloured by (t + z + y + x) mod 2, the odd sites eliminated).
+ * With D = A + H (A(x) the site-local term,
  * H the hopping sum of Eq. (1.13), which only couples sites of opposite
  * parity (t + z + y + x) mod 2), eliminating the odd sites gives
  *     S x_e = b_e - H_eo A_oo^{-1} b_o,   S = A_ee - H_eo A_oo^{-1} H_oe,

@@ -58,9 +58,9 @@ def fgmres(apply_A, b, m: int, tol: float, maxit: int, x0=None, precond=None,
     breakdown = False
     relres = np.inf
     while True:
-        r = b - apply_A(x)                               # line 4
+        r = b - apply_A(x)                               # restart: residual
         applies += 1
-        beta = _norm(r)                                  # line 5
+        beta = _norm(r)                                  # its norm beta
         if r0norm is None:
             r0norm = beta
             if r0norm == 0.0:
@@ -74,21 +74,21 @@ def fgmres(apply_A, b, m: int, tol: float, maxit: int, x0=None, precond=None,
         if applies >= maxit or breakdown:
             break
         restarts += 1
-        V = [r / beta]                                   # line 6
+        V = [r / beta]                                   # first basis vector
         Z = []
-        H = np.zeros((m + 1, m), np.complex128)          # line 2
+        H = np.zeros((m + 1, m), np.complex128)          # Hessenberg matrix
         e1 = np.zeros(m + 1, np.complex128)
         e1[0] = beta
         ncols = 0
-        for j in range(m):                               # line 7
-            z = V[j] if precond is None else precond(V[j], j)   # line 8
+        for j in range(m):                               # Arnoldi steps
+            z = V[j] if precond is None else precond(V[j], j)   # preconditioned direction z_j
             Z.append(z)
-            w = apply_A(z)                               # line 9
+            w = apply_A(z)                               # w = A z_j
             applies += 1
-            for i in range(j + 1):                       # lines 10-13
+            for i in range(j + 1):                       # modified Gram-Schmidt
                 H[i, j] = _dot(V[i], w)
                 w = w - H[i, j] * V[i]
-            H[j + 1, j] = _norm(w)                       # line 14
+            H[j + 1, j] = _norm(w)                       # h_{j+1,j}
             ncols = j + 1
             y, *_ = np.linalg.lstsq(H[:j + 2, :j + 1], e1[:j + 2], rcond=None)
             est = float(np.linalg.norm(e1[:j + 2] - H[:j + 2, :j + 1] @ y)) / r0norm
@@ -99,9 +99,9 @@ def fgmres(apply_A, b, m: int, tol: float, maxit: int, x0=None, precond=None,
                 break
             if est < tol or applies >= maxit:
                 break
-            V.append(w / H[j + 1, j])                    # line 15
-        y, *_ = np.linalg.lstsq(H[:ncols + 1, :ncols], e1[:ncols + 1], rcond=None)  # line 18
-        for k in range(ncols):                           # line 19
+            V.append(w / H[j + 1, j])                    # next basis vector
+        y, *_ = np.linalg.lstsq(H[:ncols + 1, :ncols], e1[:ncols + 1], rcond=None)  # least squares for y
+        for k in range(ncols):                           # x += Z y
             x = x + y[k] * Z[k]
     return x, {"applies": applies, "restarts": restarts, "converged": converged,
                "true_residual": relres, "breakdown": breakdown}

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EVEN_ODD, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
-                   FGMRES_F64,
+                   ENONFINITE, ENOTCONV, FGMRES_F64,
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
 PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
@@ -222,7 +222,9 @@ class DiracOp:
         ``schur``: solve the even-odd reduced system (operator built with
         even_odd=True) and reconstruct the odd sites; tol stays relative to the
         full system's initial residual.
-        Returns (x native FP64, per-RHS stats dicts, status)."""
+        Returns (x native FP64, per-RHS stats dicts, status); status is
+        ENONFINITE when a right-hand side met NaN/Inf (its stats say
+        ``nonfinite``), ENOTCONV when one reached maxit."""
         p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur)
         nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if nbytes == 0:
@@ -241,6 +243,7 @@ class DiracOp:
         for s in stats:
             out.append({"applies": s.applies, "inner_applies": s.inner_applies, "restarts": s.restarts,
                         "converged": bool(s.converged), "breakdown": bool(s.breakdown),
+                        "nonfinite": bool(s.nonfinite), "wave": s.wave,
                         "true_residual": s.true_residual, "seconds": s.seconds,
                         "seconds_apply": s.seconds_apply, "seconds_precond": s.seconds_precond,
                         "seconds_ortho": s.seconds_ortho,

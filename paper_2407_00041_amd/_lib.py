@@ -13,7 +13,7 @@ SO_PATH = os.path.join(HERE, "libwdirac.so")
 
 F64, F32, F16S = 0, 1, 2
 ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER, EVEN_ODD = 1, 2, 4, 8, 16, 32
-OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV = 0, -1, -2, -3, -4, 1
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, 1, 2
 FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S = 0, 1, 2
 FGMRES_HIST_MAX = 4096
 
@@ -34,7 +34,7 @@ class FgmresParams(ctypes.Structure):
 class FgmresStats(ctypes.Structure):
     _fields_ = [("applies", ctypes.c_longlong), ("inner_applies", ctypes.c_longlong),
                 ("restarts", ctypes.c_longlong), ("converged", _I), ("breakdown", _I),
-                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("nonfinite", _I), ("wave", _I), ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("seconds_apply", ctypes.c_double), ("seconds_precond", ctypes.c_double),
                 ("seconds_ortho", ctypes.c_double),
                 ("nhist", _I), ("hist", ctypes.c_double * FGMRES_HIST_MAX)]

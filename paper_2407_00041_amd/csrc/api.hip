@@ -16,6 +16,7 @@ hipError_t operator_to_native(dirac_op *op, const double *links_can_dev, const d
 hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStream_t st);
 hipError_t clover_structure_deviation(const double *clover_can_dev, int V, double *out, hipStream_t st);
 hipError_t clover_inverse_to_native(dirac_op *op, const double *inv_can_dev, hipStream_t st);
+hipError_t nonfinite_any(const double *dev, size_t n, bool *out, hipStream_t st);
 
 static thread_local std::string g_err;
 constexpr double kSu3Tol = 1e-12;  // largest |U U^H - 1|, |det U - 1| accepted for two-row storage
@@ -152,6 +153,17 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
             rc = fail(WDIRAC_EHIP, "copy of links to the device failed");
             break;
         }
+        {
+            bool nf = false;
+            if (nonfinite_any(lc, nl / sizeof(double), &nf, st) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "finiteness check of the links failed to run");
+                break;
+            }
+            if (nf) {
+                rc = fail(WDIRAC_EINVAL, "the links contain a NaN or Inf entry");
+                break;
+            }
+        }
         if (op->link_rows == 2) {
             double dev = 0;
             if (su3_deviation(lc, (int)V, &dev, st) != hipSuccess) {
@@ -167,6 +179,15 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
         if (clover) {
             if (hipMemcpy(cc, clover, nc, hipMemcpyHostToDevice) != hipSuccess) {
                 rc = fail(WDIRAC_EHIP, "copy of clover to the device failed");
+                break;
+            }
+            bool nf = false;
+            if (nonfinite_any(cc, nc / sizeof(double), &nf, st) != hipSuccess) {
+                rc = fail(WDIRAC_EHIP, "finiteness check of the clover failed to run");
+                break;
+            }
+            if (nf) {
+                rc = fail(WDIRAC_EINVAL, "the clover term contains a NaN or Inf entry");
                 break;
             }
         } else if (csw != 0.0) {
@@ -261,7 +282,8 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
 
 int dirac_tune_set(const char *key, int value) {
     if (!key) return fail(WDIRAC_EINVAL, "null key");
-    Tuning &t = tuning();
+    std::lock_guard<std::mutex> lk(tuning_mutex());
+    Tuning &t = tuning_unlocked();
     std::string k(key);
     if (k == "explicit") {
         t.explicit_launch = value != 0;
@@ -291,7 +313,7 @@ int dirac_tune_set(const char *key, int value) {
 
 int dirac_tune_get(const char *key, int *value) {
     if (!key || !value) return fail(WDIRAC_EINVAL, "null argument");
-    const Tuning &t = tuning();
+    const Tuning t = tuning_snapshot();
     std::string k(key);
     if (k == "block") *value = t.block;
     else if (k == "explicit") *value = t.explicit_launch ? 1 : 0;

@@ -1,6 +1,7 @@
 // Launch-side types of the stencil kernels (internal).
 #pragma once
 
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -76,7 +77,12 @@ struct Tuning {
     bool explicit_launch = false;  // set by dirac_tune_set: use these values, ignore autotuned ones
 };
 
-Tuning &tuning();
+// The process-wide parameters are guarded by tuning_mutex(): launches read a
+// consistent copy (tuning_snapshot), dirac_tune_set changes them under the
+// lock through tuning_unlocked().
+std::mutex &tuning_mutex();
+Tuning &tuning_unlocked();
+Tuning tuning_snapshot();
 
 hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int prec, bool dagger, const OpData &d,
                                  const Geom &g, int apbc, bool persistent, hipStream_t st);

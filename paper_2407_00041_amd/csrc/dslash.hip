@@ -560,8 +560,14 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
 }
 
 static Tuning g_tuning;
+static std::mutex g_tuning_mu;
 
-Tuning &tuning() { return g_tuning; }
+std::mutex &tuning_mutex() { return g_tuning_mu; }
+Tuning &tuning_unlocked() { return g_tuning; }
+Tuning tuning_snapshot() {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    return g_tuning;
+}
 
 // Work-groups of one kernel instance that fit on the device at once.
 template <int P, bool DAG, int NR>
@@ -604,7 +610,7 @@ static int resident_blocks_col(int block) {
 template <int P, bool DAG, int NR>
 static hipError_t launch_chunks(const std::vector<Chunk<NR>> &chunks, const OpData &d, const Geom &g, int apbc,
                                 bool persistent, const LaunchCfg &cfg, hipStream_t st) {
-    const Tuning &tu = g_tuning;
+    const Tuning tu = tuning_snapshot();
     const TileMap m = make_tilemap(g, cfg.order, cfg.block, cfg.tchunk);
     for (size_t c0 = 0; c0 < chunks.size(); c0 += kMaxChunks) {
         ChunkTable<NR> tab;
@@ -729,7 +735,7 @@ hipError_t dslash_launch_batches(const dirac_batch *batches, int nbatch, int pre
                                  const Geom &g, int apbc, bool persistent, hipStream_t st) {
     int total = 0;
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
-    const Tuning &tu = g_tuning;
+    const Tuning tu = tuning_snapshot();
     LaunchCfg cfg{tu.order, tu.block, tu.tchunk, (prec >= 0 && prec < 3) ? tu.nr[prec] : 1};
     if (!tu.explicit_launch) tuned_cfg(g, prec, total, d.rows, d.clover_compact, cfg);
     return dslash_launch_cfg(batches, nbatch, prec, dagger, d, g, apbc, persistent, cfg, st);

@@ -2,8 +2,9 @@
 //
 // Every right-hand side runs its own restarted FGMRES: its own Krylov basis,
 // Hessenberg matrix and termination test.  The right-hand sides advance in
-// lockstep only so that their operator applications (lines 4 and 9 of the
-// algorithm) go out as one batched stencil launch.
+// lockstep only so that their operator applications (the restart residual
+// and the product with the preconditioned vector) go out as one batched
+// stencil launch.
 //
 // Steps per right-hand side, in the algorithm's order:
 //   restart   r = b - D x (FP64 operator), beta = |r|, v_1 = r / beta
@@ -38,8 +39,11 @@
 // stay FP64, so the outer loop is an iterative refinement of the
 // low-precision solves.
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <complex>
+#include <limits>
 #include <map>
 #include <string>
 #include <vector>
@@ -329,6 +333,7 @@ struct Rhs {
     Arnoldi outer;
     double r0norm = -1, relres = 1;
     bool breakdown = false, converged = false;
+    bool nonfinite = false;  // a NaN or Inf reached a residual norm or a Hessenberg column
     long long applies = 0, inner_applies = 0, restarts = 0;
     std::vector<double> hist;
 };
@@ -624,8 +629,16 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         std::vector<std::vector<zc>> got;
         int rc = fetch(c, src, got);
         if (rc) return rc;
-        for (size_t k = 0; k < R.size(); k++)
-            R[k].r0norm = std::sqrt(std::max(got[2 * k][0].real(), 0.0) + std::max(got[2 * k + 1][0].real(), 0.0));
+        for (size_t k = 0; k < R.size(); k++) {
+            const double ne = got[2 * k][0].real(), no = got[2 * k + 1][0].real();
+            if (!std::isfinite(ne) || !std::isfinite(no)) {
+                // non-finite b or x0: no iteration can mean anything, the caller's x stays as it is
+                R[k].nonfinite = true;
+                R[k].phase = Phase::Done;
+                continue;
+            }
+            R[k].r0norm = std::sqrt(std::max(ne, 0.0) + std::max(no, 0.0));
+        }
     }
     double t_apply = 0, t_precond = 0, t_ortho = 0;
     bool any = true;
@@ -642,7 +655,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             if (rc) return rc;
         }
         WD_TRY(hipEventRecord(ev.e[1], c.st));
-        // one batched FP64 application for all of them (lines 4 and 9)
+        // one batched FP64 application for all of them (restart residuals and Arnoldi products)
         std::vector<ApplyItem> bat;
         for (Rhs *r : res) bat.push_back({r->w, r->x, r->t64});
         for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], r->t64});
@@ -681,7 +694,14 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         // restarts: convergence test on the true residual
         for (size_t k = 0; k < res.size(); k++) {
             Rhs &r = *res[k];
-            const double beta = std::sqrt(std::max(got[k][0].real(), 0.0));
+            const double n2 = got[k][0].real();
+            if (!std::isfinite(n2)) {
+                // NaN/Inf in b, x0 or the iterate: reported as its own outcome, never as convergence
+                r.nonfinite = true;
+                r.phase = Phase::Done;
+                continue;
+            }
+            const double beta = std::sqrt(std::max(n2, 0.0));
             if (r.r0norm < 0) r.r0norm = beta;
             r.relres = r.r0norm > 0 ? beta / r.r0norm : 0.0;
             if (r.r0norm == 0.0 || r.relres < p->tol) {
@@ -704,6 +724,14 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             const int j = r.outer.j;
             const std::vector<zc> &hk = got[res.size() + k];
             if (mixed) r.inner_applies += (long long)got[res.size() + arn.size() + k][0].real();
+            bool finite = true;
+            for (int i = 0; i <= j + 1; i++) finite = finite && std::isfinite(hk[i].real()) && std::isfinite(hk[i].imag());
+            if (!finite) {
+                // the cycle is abandoned without its update: x keeps the iterate of the last completed cycle
+                r.nonfinite = true;
+                r.phase = Phase::Done;
+                continue;
+            }
             std::vector<zc> col(j + 2);
             for (int i = 0; i <= j; i++) col[i] = hk[i];
             const double hn = std::sqrt(std::max(hk[j + 1].real(), 0.0));
@@ -732,7 +760,10 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     if (c.schur) {
         // x_o = A_oo^{-1} (b_o - H_oe x_e), x = (x_e, x_o), and the true residual |b - D x| over both parities
         std::vector<std::pair<const double2 *, int>> src;
+        std::vector<Rhs *> fin;
         for (Rhs &r : R) {
+            if (r.nonfinite) continue;  // the caller's x is left untouched
+            fin.push_back(&r);
             double2 *xo = static_cast<double2 *>(r.V[0]), *be = static_cast<double2 *>(r.V[1]);
             double2 *bo = static_cast<double2 *>(r.t64);
             WD_TRY(parity_split_launch(op, WDIRAC_F64, be, bo, r.bu, 1, c.st));
@@ -746,20 +777,28 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             src.emplace_back(r.hcol2, 1);
         }
         std::vector<std::vector<zc>> got;
-        int rc = fetch(c, src, got);
-        if (rc) return rc;
-        for (size_t k = 0; k < R.size(); k++) {
-            const double rn =
-                std::sqrt(std::max(got[2 * k][0].real(), 0.0) + std::max(got[2 * k + 1][0].real(), 0.0));
-            R[k].relres = R[k].r0norm > 0 ? rn / R[k].r0norm : 0.0;
+        if (!src.empty()) {
+            int rc = fetch(c, src, got);
+            if (rc) return rc;
+        }
+        for (size_t k = 0; k < fin.size(); k++) {
+            const double ne = got[2 * k][0].real(), no = got[2 * k + 1][0].real();
+            if (!std::isfinite(ne) || !std::isfinite(no)) {
+                fin[k]->nonfinite = true;
+                fin[k]->converged = false;
+                continue;
+            }
+            const double rn = std::sqrt(std::max(ne, 0.0) + std::max(no, 0.0));
+            fin[k]->relres = fin[k]->r0norm > 0 ? rn / fin[k]->r0norm : 0.0;
         }
     }
     WD_TRY(hipStreamSynchronize(stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bool all = true;
+    bool all = true, bad = false;
     for (int k = 0; k < nrhs; k++) {
         Rhs &r = R[k];
         all = all && r.converged;
+        bad = bad || r.nonfinite;
         if (!st) continue;
         fgmres_stats &s = st[k];
         s.applies = r.applies;
@@ -767,7 +806,9 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         s.restarts = r.restarts;
         s.converged = r.converged ? 1 : 0;
         s.breakdown = r.breakdown ? 1 : 0;
-        s.true_residual = r.relres;
+        s.nonfinite = r.nonfinite ? 1 : 0;
+        s.wave = nrhs;
+        s.true_residual = r.nonfinite ? std::numeric_limits<double>::quiet_NaN() : r.relres;
         s.seconds = secs;
         s.seconds_apply = t_apply;
         s.seconds_precond = t_precond;
@@ -775,6 +816,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         s.nhist = (int)std::min<size_t>(r.hist.size(), FGMRES_HIST_MAX);
         for (int i = 0; i < s.nhist; i++) s.hist[i] = r.hist[i];
     }
+    if (bad) return WDIRAC_ENONFINITE;
     return all ? WDIRAC_OK : WDIRAC_ENOTCONV;
 }
 
@@ -808,12 +850,32 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     return WDIRAC_OK;
 }
 
-// right-hand sides per wave
-static int wave_of(const fgmres_params *p, int nrhs) { return (p->wave > 0 && p->wave < nrhs) ? p->wave : nrhs; }
+// Right-hand sides per wave.  An explicit p->wave is used as given (capped at
+// nrhs).  With p->wave == 0 the library chooses: fgmres_workspace_bytes sizes
+// the wave from the device memory free at that moment (keeping a reserve for
+// the caller), and fgmres_solve takes as many right-hand sides per wave as the
+// workspace it is handed can hold, so the two calls agree whenever the caller
+// allocates what fgmres_workspace_bytes asked for.
+static int wave_explicit(const fgmres_params *p, int nrhs) { return p->wave < nrhs ? p->wave : nrhs; }
+
+static int wave_from_free_memory(const dirac_op *op, const fgmres_params *p, int nrhs) {
+    const size_t per = solver_workspace(op, p, 1);
+    size_t free_b = 0, total_b = 0;
+    if (hipSetDevice(op->device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    // headroom for the caller's own fields and the runtime: 1/16 of the device, at least 4 GiB
+    const size_t reserve = std::max(total_b / 16, (size_t)4 << 30);
+    const size_t avail = free_b > reserve ? free_b - reserve : 0;
+    const size_t w = per ? avail / per : (size_t)nrhs;
+    return (int)std::max<size_t>(1, std::min<size_t>(w, (size_t)nrhs));
+}
 
 size_t fgmres_workspace_bytes(const dirac_op *op, const fgmres_params *p, int nrhs) {
     if (nrhs < 1 || check_params(op, p)) return 0;
-    return solver_workspace(op, p, wave_of(p, nrhs));
+    const int w = p->wave > 0 ? wave_explicit(p, nrhs) : wave_from_free_memory(op, p, nrhs);
+    return solver_workspace(op, p, w);
 }
 
 int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres_params *p,
@@ -824,18 +886,29 @@ int fgmres_solve(const dirac_op *op, double *x, const double *b, int nrhs, const
     if (nrhs < 1) return fail(WDIRAC_EINVAL, "nrhs must be >= 1");
     rc = check_apply(op, x, b, nrhs, WDIRAC_F64);
     if (rc) return rc;
-    const int w = wave_of(p, nrhs);
+    int w = 0;
+    if (p->wave > 0) {
+        w = wave_explicit(p, nrhs);
+    } else {
+        const size_t per = solver_workspace(op, p, 1);
+        w = (int)std::min<size_t>(per ? work_bytes / per : (size_t)nrhs, (size_t)nrhs);
+        if (w < 1) w = 1;  // rejected just below
+    }
     if (work_bytes < solver_workspace(op, p, w)) return fail(WDIRAC_EINVAL, "workspace too small");
     if (reinterpret_cast<uintptr_t>(work) & 255) return fail(WDIRAC_EINVAL, "workspace must be 256-byte aligned");
     const size_t field = (size_t)24 * op->g.V;  // doubles per right-hand side
-    bool notconv = false;
+    bool notconv = false, nonfinite = false;
     for (int k0 = 0; k0 < nrhs; k0 += w) {
         const int nw = nrhs - k0 < w ? nrhs - k0 : w;
         rc = solve(op, x + k0 * field, b + k0 * field, nw, p, st ? st + k0 : nullptr, work, work_bytes,
                    (hipStream_t)stream);
         if (rc < 0) return rc;
         notconv = notconv || rc == WDIRAC_ENOTCONV;
+        nonfinite = nonfinite || rc == WDIRAC_ENONFINITE;
+        if (st)
+            for (int k = k0; k < k0 + nw; k++) st[k].wave = w;
     }
+    if (nonfinite) return WDIRAC_ENONFINITE;
     return notconv ? WDIRAC_ENOTCONV : WDIRAC_OK;
 }
 

@@ -6,6 +6,7 @@
 // Each thread owns one site: it reads the site's contiguous canonical record
 // (whole cache lines per wavefront) and writes each native component at
 // consecutive sites across the wavefront.
+#include <algorithm>
 #include <cstring>
 
 #include "spinor_io.h"
@@ -176,6 +177,33 @@ hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStr
     double d;
     memcpy(&d, &h, sizeof(d));
     *out = d;
+    return e;
+}
+
+// *flag becomes 1 when any of the n doubles is a NaN or an infinity
+__global__ __launch_bounds__(256) void nonfinite_check(const double *__restrict__ p, size_t n,
+                                                       unsigned int *__restrict__ flag) {
+    bool bad = false;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) bad = bad || !isfinite(p[i]);
+    if (bad) atomicOr(flag, 1u);
+}
+
+hipError_t nonfinite_any(const double *dev, size_t n, bool *out, hipStream_t st) {
+    unsigned int *f = nullptr;
+    hipError_t e = hipMalloc(&f, sizeof(*f));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(f, 0, sizeof(*f), st);
+    if (e == hipSuccess) {
+        const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL(nonfinite_check, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, st, dev, n, f);
+        e = hipGetLastError();
+    }
+    unsigned int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, f, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(f);
+    *out = h != 0;
     return e;
 }
 

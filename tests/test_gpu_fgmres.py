@@ -1,6 +1,8 @@
 """GPU FGMRES (Algorithm 2) through the C ABI against the oracle FGMRES:
 same operator-application count (the paper's regression criterion), same
 residual history, and a true residual verified with the oracle operator."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -210,3 +212,85 @@ def test_full_size_mixed_fgmres_bench_configuration():
     del op, x, bn
     torch.cuda.empty_cache()
     assert true_relres(dims, U, m0, csw, xg, bd.cpu().numpy()[0]) <= 1e-10 * 1.01
+
+
+@pytest.mark.parametrize("schur", [False, True])
+@pytest.mark.parametrize("where", ["b", "x0"])
+def test_nonfinite_input_is_reported_not_converged(schur, where):
+    """A NaN in one right-hand side's b (or x0) of a 3-RHS lockstep solve is
+    reported as its own outcome (nonfinite, not converged, true residual NaN,
+    status ENONFINITE, x left at x0), and the other two right-hand sides are
+    solved exactly as their single solves, bit for bit."""
+    need_gpu()
+    from paper_2407_00041_amd import ENONFINITE
+    dims = (4, 4, 6, 4)
+    U = synth.smooth_links(dims, 21).numpy()
+    b = synth.gaussian_spinor(dims, 22, nrhs=3)
+    op = DiracOp(dims, U, -0.3, 1.0, precisions=("f64",), even_odd=True)
+    bn = op.pack(to_dev(b), "f64")
+    rb = op.field_bytes("f64", 1)
+    x0 = torch.zeros_like(bn)
+    bad = bn.clone() if where == "b" else bn
+    tgt = bad if where == "b" else x0
+    v = tgt[rb:2 * rb].view(torch.float64)
+    v[17] = float("nan")
+    kw = dict(nrhs=3, restart=8, tol=1e-10, maxit=2000, schur=schur)
+    x0_before = x0.clone()
+    x, st, rc = op.solve(bad, x0=x0, **kw)
+    assert rc == ENONFINITE
+    assert st[1]["nonfinite"] and not st[1]["converged"]
+    assert np.isnan(st[1]["true_residual"])
+    assert torch.equal(x[rb:2 * rb].view(torch.float64).nan_to_num(123.0),
+                       x0_before[rb:2 * rb].view(torch.float64).nan_to_num(123.0))
+    for r in (0, 2):
+        assert not st[r]["nonfinite"] and st[r]["converged"]
+        xr, sr, rcr = op.solve(bn[r * rb:(r + 1) * rb], nrhs=1, restart=8, tol=1e-10, maxit=2000, schur=schur)
+        assert rcr == 0
+        assert torch.equal(x[r * rb:(r + 1) * rb], xr), r
+        assert sr[0]["applies"] == st[r]["applies"]
+        assert sr[0]["hist"] == st[r]["hist"]
+
+
+def test_library_chosen_wave():
+    """wave = 0: fgmres_workspace_bytes sizes a wave from the free device
+    memory (a whole number of right-hand sides), and fgmres_solve runs as many
+    right-hand sides per wave as the workspace it is given holds, reporting
+    the wave in the stats; the solutions equal one lockstep solve."""
+    need_gpu()
+    dims = (4, 4, 6, 4)
+    U, b, op, bn = setup(dims, 9, -0.3, 1.0, nrhs=5, precisions=("f64",))
+    per = op.workspace_bytes(1, 8, "f64", wave=1)
+    auto = op.workspace_bytes(5, 8, "f64", wave=0)
+    assert auto == 5 * per  # a tiny lattice: all five fit
+    kw = dict(nrhs=5, restart=8, tol=1e-10, maxit=2000)
+    x_all, s_all, rc = op.solve(bn, **kw)
+    assert rc == 0 and all(s["wave"] == 5 for s in s_all)
+    work = torch.empty(2 * per + 100, dtype=torch.uint8, device="cuda")
+    x_w, s_w, rc = op.solve(bn, wave=0, work=work, **kw)
+    assert rc == 0 and all(s["wave"] == 2 for s in s_w)
+    assert torch.equal(x_w, x_all)
+    # a workspace smaller than one right-hand side's is rejected
+    from paper_2407_00041_amd import _lib
+    small = torch.empty(per, dtype=torch.uint8, device="cuda")
+    x = torch.zeros_like(bn)
+    stats = (_lib.FgmresStats * 5)()
+    p = op._params(8, 1e-10, 2000, "f64", 30, 1e-2, 30)
+    rc = op.lib.fgmres_solve(op.handle, x.data_ptr(), bn.data_ptr(), 5, ctypes.byref(p), stats, small.data_ptr(),
+                             per - 256, torch.cuda.current_stream().cuda_stream)
+    assert rc == _lib.EINVAL and b"workspace too small" in op.lib.dirac_last_error()
+
+
+def test_create_rejects_nonfinite_links_and_clover():
+    need_gpu()
+    dims = (2, 2, 2, 4)
+    U = synth.smooth_links(dims, 3).numpy()
+    bad = U.copy()
+    bad[5, 2, 1, 1] = complex(np.inf, 0.0)
+    with pytest.raises(WdiracError) as e:
+        DiracOp(dims, bad, -0.3, 1.0, precisions=("f64",))
+    assert e.value.code == -1 and "NaN or Inf" in str(e.value)
+    C = oracle.clover_term(dims, U)
+    C[3, 7] = complex(0.0, np.nan)
+    with pytest.raises(WdiracError) as e:
+        DiracOp(dims, U, -0.3, 1.0, clover=C, precisions=("f64",))
+    assert e.value.code == -1 and "NaN or Inf" in str(e.value)
