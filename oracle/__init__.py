@@ -10,6 +10,9 @@ library (no code, header, table or helper), and this package never imports it.
 - ``fgmres.py`` (NumPy): Algorithm 2 (FGMRES) of Sec. 1.2.
 - ``evenodd.py`` (NumPy): the even-odd (red-black) reduction of D x = b to
   the even sites (Schur complement, right-hand side, odd-site reconstruction).
+- ``sap.py`` (NumPy): the Schwarz alternating procedure over non-overlapping
+  lattice blocks (red-black multiplicative and additive; minimal-residual or
+  exact block solves), the preconditioner of Sec. 1.3.
 
 All arrays use the canonical host layouts documented in ``oracle.c``:
 spinors [..., V, 12] complex128, links [V, 4, 3, 3] complex128, packed clover
