@@ -260,11 +260,57 @@ int dirac_unpack(const dirac_op *op, double *canonical, const void *native, int 
 int dirac_clover_term(const int dims[4], const double *links_dev, double *clover_dev, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/*
+ * Schwarz alternating procedure (SAP), the block smoother Sec. 1.3 names for
+ * the preconditioner of FGMRES (additive and red-black multiplicative
+ * Schwarz over non-overlapping lattice blocks; the paper gives no further
+ * detail, the method follows its textbook definition):
+ *   - blocks of block[0] x ... x block[3] sites (T, Z, Y, X); each extent
+ *     divides the lattice extent, every direction holds an even number of
+ *     blocks or exactly one (a block spanning a direction keeps its hops in
+ *     that direction, periodically), and a block has at most 256 sites.  A
+ *     block's colour is the sum of its block coordinates mod 2.
+ *   - D_B, the block operator, is D with the hops that leave the block
+ *     dropped; the local solve is mr_iters minimal-residual steps from 0:
+ *     q = D_B rho, alpha = <q, rho> / <q, q>, e += alpha rho, rho -= alpha q.
+ *   - a red-black cycle: for colour 0 then 1, r = b - D x and x_B += e_B on
+ *     every block of that colour; an additive cycle: one r = b - D x, then
+ *     x_B += e_B on every block.
+ * The block arithmetic runs at `prec` (FP64, or FP32 with the FP32 operator
+ * data); x and b are FP64 and the dot products accumulate in FP64.
+ */
+typedef struct {
+    int block[4];  /* block extents {bT, bZ, bY, bX}                        */
+    int cycles;    /* Schwarz cycles (>= 1), from x = 0                       */
+    int mr_iters;  /* minimal-residual steps per block solve (>= 1)          */
+    int additive;  /* 0 = red-black multiplicative, 1 = additive             */
+    int prec;      /* WDIRAC_F64 or WDIRAC_F32                               */
+} sap_params;
+
+/* Device workspace dirac_sap needs: nrhs FP64 fields for additive SAP with
+ * cycles > 1 (two iterates alternate), else 0.  0 also on bad arguments. */
+size_t dirac_sap_workspace_bytes(const dirac_op *op, const sap_params *p, int nrhs);
+
+/*
+ * x = SAP(b): `cycles` Schwarz cycles on D x = b from x = 0, for nrhs
+ * right-hand sides.  x, b: device native FP64 fields (x overwritten, must not
+ * overlap b); work: device workspace of dirac_sap_workspace_bytes bytes (may
+ * be NULL when that is 0), must not overlap x or b.  Asynchronous; no
+ * allocation.  One work-group per block and pass.  Errors: EINVAL (null
+ * pointer, overlap, a blocking that breaks the rules above, cycles or
+ * mr_iters < 1, workspace too small), EUNSUPPORTED (prec not materialised),
+ * EHIP.
+ */
+int dirac_sap(const dirac_op *op, double *x, const double *b, int nrhs, const sap_params *p, void *work,
+              size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* FGMRES (Algorithm 2, Sec. 1.2) for D x = b.                               */
 
 #define FGMRES_F64 0        /* plain FP64 FGMRES(restart), no preconditioner */
 #define FGMRES_MIXED_F32 1  /* FP64 outer FGMRES, inner GMRES on FP32 D     */
 #define FGMRES_MIXED_F16S 2 /* FP64 outer FGMRES, inner GMRES on FP16S D    */
+#define FGMRES_SAP 3        /* FP64 FGMRES, M_j^{-1} = SAP (fgmres_params.sap) */
 
 typedef struct {
     int restart;        /* outer Krylov dimension m (>= 1)                   */
@@ -291,6 +337,9 @@ typedef struct {
                         /* reconstruct x_o; tol stays relative to the full   */
                         /* |b - D x0|; only the even sites of x0 start the   */
                         /* iteration; applies count applications of S       */
+                        /* (not with FGMRES_SAP)                             */
+    sap_params sap;     /* FGMRES_SAP: the preconditioner's SAP; its work is */
+                        /* part of the solver's workspace                    */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096

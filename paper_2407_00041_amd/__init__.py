@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EVEN_ODD, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
-                   ENONFINITE, ENOTCONV, FGMRES_F64,
+                   ENONFINITE, ENOTCONV, FGMRES_F64, FGMRES_SAP,
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
 PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
@@ -194,17 +194,26 @@ class DiracOp:
         return self.unpack(b, prec, nrhs).reshape(shape)
 
     @staticmethod
-    def _params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph=False, wave=0,
-                schur=False):
-        modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S}
+    def sap_params(block=(4, 4, 4, 4), cycles: int = 1, mr_iters: int = 4, additive: bool = False, prec="f32"):
+        """SAP parameters (see dirac_sap): block extents (T, Z, Y, X), Schwarz cycles,
+        minimal-residual steps per block solve, additive or red-black, block precision."""
+        return _lib.SapParams((ctypes.c_int * 4)(*[int(b) for b in block]), int(cycles), int(mr_iters),
+                              int(bool(additive)), _prec(prec))
+
+    @classmethod
+    def _params(cls, restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph=False, wave=0,
+                schur=False, sap=None):
+        modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S,
+                 "sap": FGMRES_SAP}
+        sp = cls.sap_params(**(sap or {}))
         return _lib.FgmresParams(int(restart), float(tol), int(maxit),
                                  modes[mode] if isinstance(mode, str) else int(mode),
                                  int(inner_restart), float(inner_tol), int(inner_maxit), int(bool(graph)), int(wave),
-                                 int(bool(schur)))
+                                 int(bool(schur)), sp)
 
     def workspace_bytes(self, nrhs: int = 1, restart: int = 20, mode="f64", inner_restart: int = 30,
-                        wave: int = 0, schur: bool = False) -> int:
-        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave, schur=schur)
+                        wave: int = 0, schur: bool = False, sap=None) -> int:
+        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave, schur=schur, sap=sap)
         n = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if n == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
@@ -213,9 +222,9 @@ class DiracOp:
     def solve(self, b: torch.Tensor, nrhs: int = 1, x0: torch.Tensor | None = None, restart: int = 20,
               tol: float = 1e-10, maxit: int = 10000, mode="f64", inner_restart: int = 30,
               inner_tol: float = 1e-2, inner_maxit: int = 30, work: torch.Tensor | None = None, stream=None,
-              graph: bool = False, wave: int = 0, schur: bool = False):
+              graph: bool = False, wave: int = 0, schur: bool = False, sap=None):
         """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
-        "mixed_f16s".  ``work`` may be a reusable device buffer of at least
+        "mixed_f16s", or "sap" (M_j^{-1} = SAP with the keyword arguments of sap_params in ``sap``).  ``work`` may be a reusable device buffer of at least
         workspace_bytes(...) bytes.  ``graph``: run the inner cycles of the mixed
         modes as captured HIP graphs.  ``wave``: solve the right-hand sides in
         consecutive groups of this size (workspace for one group; 0 = all).
@@ -225,7 +234,7 @@ class DiracOp:
         Returns (x native FP64, per-RHS stats dicts, status); status is
         ENONFINITE when a right-hand side met NaN/Inf (its stats say
         ``nonfinite``), ENOTCONV when one reached maxit."""
-        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur)
+        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur, sap)
         nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if nbytes == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
@@ -249,6 +258,16 @@ class DiracOp:
                         "seconds_ortho": s.seconds_ortho,
                         "hist": [s.hist[i] for i in range(s.nhist)]})
         return x, out, rc
+
+    def sap(self, b: torch.Tensor, nrhs: int = 1, x: torch.Tensor | None = None, stream=None, **kw) -> torch.Tensor:
+        """x = SAP(b) from x = 0 (dirac_sap); b native FP64 with nrhs fields; kw: sap_params."""
+        p = self.sap_params(**kw)
+        nb = int(self.lib.dirac_sap_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
+        work = torch.empty(max(nb, 16), dtype=torch.uint8, device=b.device)
+        x = torch.empty_like(b) if x is None else x
+        check(self.lib.dirac_sap(self.handle, _ptr(x), _ptr(b), int(nrhs), ctypes.byref(p), _ptr(work), nb,
+                                 _stream(stream)), "dirac_sap")
+        return x
 
     def autotune(self, prec="f64", nrhs: int = 1, stream=None) -> dict:
         """Time candidate launch configurations and keep the fastest (dirac_autotune)."""

@@ -14,7 +14,7 @@ SO_PATH = os.path.join(HERE, "libwdirac.so")
 F64, F32, F16S = 0, 1, 2
 ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER, EVEN_ODD = 1, 2, 4, 8, 16, 32
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, 1, 2
-FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S = 0, 1, 2
+FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S, FGMRES_SAP = 0, 1, 2, 3
 FGMRES_HIST_MAX = 4096
 
 _P = ctypes.c_void_p
@@ -25,10 +25,14 @@ class DiracBatch(ctypes.Structure):
     _fields_ = [("out", _P), ("inp", _P), ("nrhs", _I)]
 
 
+class SapParams(ctypes.Structure):
+    _fields_ = [("block", _I * 4), ("cycles", _I), ("mr_iters", _I), ("additive", _I), ("prec", _I)]
+
+
 class FgmresParams(ctypes.Structure):
     _fields_ = [("restart", _I), ("tol", ctypes.c_double), ("maxit", ctypes.c_longlong),
                 ("mode", _I), ("inner_restart", _I), ("inner_tol", ctypes.c_double),
-                ("inner_maxit", _I), ("graph", _I), ("wave", _I), ("schur", _I)]
+                ("inner_maxit", _I), ("graph", _I), ("wave", _I), ("schur", _I), ("sap", SapParams)]
 
 
 class FgmresStats(ctypes.Structure):
@@ -63,6 +67,8 @@ SIGNATURES = {
     "fgmres_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(FgmresParams),
                           ctypes.POINTER(FgmresStats), _P, ctypes.c_size_t, _P]),
     "dirac_force_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "dirac_sap_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(SapParams), _I]),
+    "dirac_sap": (_I, [_P, _P, _P, _I, ctypes.POINTER(SapParams), _P, ctypes.c_size_t, _P]),
     "dirac_parity_field_bytes": (ctypes.c_size_t, [_P, _I, _I]),
     "dirac_parity_split": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_parity_merge": (_I, [_P, _P, _P, _P, _I, _I, _P]),

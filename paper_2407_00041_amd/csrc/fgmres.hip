@@ -50,6 +50,7 @@
 
 #include "blas.h"
 #include "dslash.h"
+#include "sap.h"
 #include "schur.h"
 
 namespace wd {
@@ -224,10 +225,11 @@ struct Layout {
 };
 
 int inner_prec(int mode) { return mode == FGMRES_MIXED_F32 ? WDIRAC_F32 : WDIRAC_F16S; }
+bool is_mixed(int mode) { return mode == FGMRES_MIXED_F32 || mode == FGMRES_MIXED_F16S; }
 
 // entries of each per-RHS scalar array (Hessenberg column, coefficients)
 int kmax_of(const fgmres_params *p) {
-    const int m = p->restart, mi = p->mode == FGMRES_F64 ? 0 : p->inner_restart;
+    const int m = p->restart, mi = is_mixed(p->mode) ? p->inner_restart : 0;
     return (m > mi ? m : mi) + 2;
 }
 
@@ -240,18 +242,17 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     L.f64 = align256(field_rhs_bytes(WDIRAC_F64, V));
     L.f32 = align256(field_rhs_bytes(WDIRAC_F32, V));
     L.f16 = align256(field_rhs_bytes(WDIRAC_F16S, V));
-    const int m = p->restart, mi = p->mode == FGMRES_F64 ? 0 : p->inner_restart;
+    const int m = p->restart, mi = is_mixed(p->mode) ? p->inner_restart : 0;
     const int kmax = kmax_of(p);
     L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kMdot + 1) + 3 * (size_t)kmax + 8));
-    if (p->mode != FGMRES_F64) L.scal += align256(inner_state_bytes(mi));
+    if (is_mixed(p->mode)) L.scal += align256(inner_state_bytes(mi));
     L.per_rhs = (size_t)(m + 2) * L.f64 + L.scal;  // V[0..m], w
-    if (p->mode != FGMRES_F64) {
-        L.per_rhs += (size_t)m * L.f64;                                          // Z[0..m)
-        L.per_rhs += (size_t)(mi + 1) * (p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16);  // inner W[0..mi]
-    }
+    if (p->mode != FGMRES_F64) L.per_rhs += (size_t)m * L.f64;  // Z[0..m)
+    if (is_mixed(p->mode)) L.per_rhs += (size_t)(mi + 1) * (p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16);  // inner W
+    if (p->mode == FGMRES_SAP) L.per_rhs += align256(sap_workspace(op, &p->sap, 1));
     if (p->schur) {
         L.per_rhs += 3 * L.f64;  // x_e, reduced right-hand side, odd scratch of S
-        if (p->mode != FGMRES_F64) L.per_rhs += p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;  // inner odd scratch
+        if (is_mixed(p->mode)) L.per_rhs += p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;  // inner odd scratch
     }
     return L;
 }
@@ -326,6 +327,7 @@ struct Rhs {
     std::vector<void *> V, Z;  // outer basis (F64), preconditioned vectors (F64)
     double2 *w = nullptr;
     std::vector<void *> Vi;    // inner basis, inner operator precision
+    double2 *sapw = nullptr;   // SAP preconditioner's workspace
     InnerDev in;               // device state of the inner cycle
     double2 *partial = nullptr, *hcol = nullptr, *coef = nullptr, *hcol2 = nullptr, *nrm = nullptr;
     // host
@@ -549,7 +551,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
     const long long Vs = system_sites(op, p);
     Ctx c{op, p, stream, 12LL * Vs, (int)Vs, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0, p->schur != 0, pinned,
           pinned_n};
-    const bool mixed = p->mode != FGMRES_F64;
+    const bool mixed = is_mixed(p->mode);          // preconditioner = inner GMRES
+    const bool sapm = p->mode == FGMRES_SAP;       // preconditioner = SAP
+    SapGeom sg{};
+    if (sapm) {
+        const int rc = sap_geometry(op, &p->sap, sg);
+        if (rc) return rc;
+    }
     const int m = p->restart;
     GraphCache graphs;
     graphs.launch = stream;
@@ -576,10 +584,12 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
         for (int i = 0; i <= m; i++) r.V.push_back(take(L.f64));
         r.w = reinterpret_cast<double2 *>(take(L.f64));
-        if (mixed) {
+        if (mixed || sapm) {
             for (int i = 0; i < m; i++) r.Z.push_back(take(L.f64));
             const size_t fi = p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;
-            for (int i = 0; i <= p->inner_restart; i++) r.Vi.push_back(take(fi));
+            if (mixed)
+                for (int i = 0; i <= p->inner_restart; i++) r.Vi.push_back(take(fi));
+            if (sapm) r.sapw = reinterpret_cast<double2 *>(take(align256(sap_workspace(op, &p->sap, 1))));
         } else {
             r.Z = std::vector<void *>(r.V.begin(), r.V.begin() + m);  // M = I: z_j = v_j
         }
@@ -654,6 +664,10 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             int rc = inner_solve(c, arn, p->graph ? &graphs : nullptr, R);
             if (rc) return rc;
         }
+        if (sapm)
+            for (Rhs *r : arn)
+                WD_TRY(sap_apply(op, p->sap, sg, static_cast<double2 *>(r->Z[r->outer.j]),
+                                 static_cast<const double2 *>(r->V[r->outer.j]), 1, r->sapw, c.st));
         WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (restart residuals and Arnoldi products)
         std::vector<ApplyItem> bat;
@@ -831,8 +845,15 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     if (p->restart < 1 || p->restart > 1000) return fail(WDIRAC_EINVAL, "restart must be in [1, 1000]");
     if (!(p->tol > 0.0)) return fail(WDIRAC_EINVAL, "tol must be > 0");
     if (p->maxit < 1) return fail(WDIRAC_EINVAL, "maxit must be >= 1");
-    if (p->mode != FGMRES_F64 && p->mode != FGMRES_MIXED_F32 && p->mode != FGMRES_MIXED_F16S)
+    if (p->mode != FGMRES_F64 && p->mode != FGMRES_MIXED_F32 && p->mode != FGMRES_MIXED_F16S &&
+        p->mode != FGMRES_SAP)
         return fail(WDIRAC_EINVAL, "unknown solver mode");
+    if (p->mode == FGMRES_SAP) {
+        if (p->schur) return fail(WDIRAC_EUNSUPPORTED, "the SAP preconditioner works on the full system only");
+        SapGeom sg;
+        const int rc = sap_geometry(op, &p->sap, sg);
+        if (rc) return rc;
+    }
     if (p->wave < 0) return fail(WDIRAC_EINVAL, "wave must be >= 0");
     if (p->schur != 0 && p->schur != 1) return fail(WDIRAC_EINVAL, "schur must be 0 or 1");
     if (p->schur) {
@@ -840,7 +861,7 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
         if (p->mode != FGMRES_F64 && !op->cinv(inner_prec(p->mode)))
             return fail(WDIRAC_EUNSUPPORTED, "inner precision not materialised at create");
     }
-    if (p->mode != FGMRES_F64) {
+    if (is_mixed(p->mode)) {
         if (p->inner_restart < 1 || p->inner_restart > 1000) return fail(WDIRAC_EINVAL, "inner_restart in [1, 1000]");
         if (p->inner_maxit < 1) return fail(WDIRAC_EINVAL, "inner_maxit must be >= 1");
         if (!(p->inner_tol > 0.0)) return fail(WDIRAC_EINVAL, "inner_tol must be > 0");
