@@ -20,6 +20,12 @@ struct VecList {
 struct CoefList {
     double2 c[kGS];
 };
+struct ScaleList {
+    double s[kGS];
+};
+// work-group chunks of the all-vector inner products: partial needs
+// kMdotChunks * ceil(min(nv, kGS) / kMdot) * (kMdot + 1) entries
+constexpr int kMdotChunks = kRedBlocks;
 
 // out[i] = sum over groups of partial[g][i], i < gridDim.x; stride = columns per partial row
 __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
@@ -30,10 +36,16 @@ __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restric
 template <typename S>
 hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
                 hipStream_t st);
-// w -= sum_i coef[i] v_i; norm_out[0].x = |w_new|^2 when norm_out != null
+// the same in one launch per kGS vectors (w read about once from HBM, see
+// k_mdot_all); partial as documented at kMdotChunks
 template <typename S>
-hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, void *w, long long N, double2 *partial,
-                      double2 *norm_out, hipStream_t st);
+hipError_t mdot_all(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
+                    hipStream_t st);
+// w -= sum_i coef[i] cscale[i] v_i (coef on the device, cscale on the host or
+// null for 1); norm_out[0].x = |w_new|^2 when norm_out != null
+template <typename S>
+hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, const double *cscale, void *w, long long N,
+                      double2 *partial, double2 *norm_out, hipStream_t st);
 // out = in * s * mult, s = sc[0].x or 1/sqrt(sc[0].x) (1 for null sc);
 // SI == SO == double2 (flat element order)
 template <typename SI, typename SO>

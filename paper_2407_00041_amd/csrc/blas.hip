@@ -78,6 +78,63 @@ __global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__res
     }
 }
 
+// Inner products of w with up to kGS basis vectors in ONE launch.  The grid
+// is (vector group of kMdot, element chunk) work-groups, dealt so that the
+// groups of one chunk are consecutive work-groups of the same XCD (the
+// hardware hands work-groups to the 8 XCDs round-robin): after the first
+// group, a chunk of w comes from that XCD's L2, so w crosses HBM about once
+// whatever the number of vectors.  partial[(chunk * ngroups + group) *
+// (kMdot + 1) + i] = sum conj(v_{kMdot group + i}) w over the chunk; column
+// kMdot of group 0 holds sum |w|^2.
+template <typename S>
+__global__ __launch_bounds__(kRedThreads) void k_mdot_all(VecList vl, const S *__restrict__ w,
+                                                           double2 *__restrict__ partial, long long N, int ngroups,
+                                                           int nchunks) {
+    __shared__ double2 lds[(kMdot + 1) * kRedThreads];
+    const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+    const int group = q % ngroups, chunk = (q / ngroups) * 8 + xcd;
+    const int i0 = group * kMdot;
+    double2 acc[kMdot + 1];
+#pragma unroll
+    for (int i = 0; i <= kMdot; i++) acc[i] = make_double2(0, 0);
+    const long long stride = (long long)nchunks * blockDim.x;
+    for (long long e = (long long)chunk * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double2 we = Elem<S>::ld(w, e);
+        if (group == 0) acc[kMdot].x += we.x * we.x + we.y * we.y;
+#pragma unroll
+        for (int i = 0; i < kMdot; i++) {
+            if (i0 + i < vl.n) {
+                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i0 + i]), e);
+                const double2 p = cj_mul(vi, we);
+                acc[i].x += p.x;
+                acc[i].y += p.y;
+            }
+        }
+    }
+    block_reduce<kMdot + 1>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i <= kMdot; i++) partial[((size_t)chunk * ngroups + group) * (kMdot + 1) + i] = acc[i];
+    }
+}
+
+// out[i] (i < nv) = sum over chunks of the inner-product partials of vector i, out[nv].x = |w|^2; one work-group
+// per output, chunks summed in order
+__global__ __launch_bounds__(kRedThreads) void k_colsum_groups(const double2 *__restrict__ partial, int nchunks,
+                                                                int ngroups, int nv, double2 *__restrict__ out) {
+    __shared__ double2 lds[kRedThreads];
+    const int i = blockIdx.x;
+    const int group = i < nv ? i / kMdot : 0, col = i < nv ? i % kMdot : kMdot;
+    double2 a[1] = {make_double2(0, 0)};
+    for (int c = threadIdx.x; c < nchunks; c += blockDim.x) {
+        const double2 p = partial[((size_t)c * ngroups + group) * (kMdot + 1) + col];
+        a[0].x += p.x;
+        a[0].y += p.y;
+    }
+    block_reduce<1>(a, lds);
+    if (threadIdx.x == 0) out[i] = a[0];
+}
+
 // out[i] = sum over groups of partial[g][i], i < ncols (one work-group per i);
 // stride = number of columns per partial row
 __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
@@ -96,12 +153,15 @@ __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restric
 // w -= sum_i coef[i] v_i (i < nv); partial[blk] = sum |w_new|^2 if partial
 template <typename S>
 __global__ __launch_bounds__(kRedThreads) void k_axpy_multi(VecList vl, const double2 *__restrict__ coef,
-                                                             S *__restrict__ w, double2 *__restrict__ partial,
-                                                             long long N) {
+                                                             ScaleList sl, S *__restrict__ w,
+                                                             double2 *__restrict__ partial, long long N) {
     __shared__ double2 lds[kRedThreads];
     double2 c[kGS];
 #pragma unroll
-    for (int i = 0; i < kGS; i++) c[i] = i < vl.n ? coef[i] : make_double2(0, 0);
+    for (int i = 0; i < kGS; i++) {
+        const double2 ci = i < vl.n ? coef[i] : make_double2(0, 0);
+        c[i] = make_double2(ci.x * sl.s[i], ci.y * sl.s[i]);
+    }
     double2 nrm[1] = {make_double2(0, 0)};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
@@ -203,15 +263,40 @@ hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double
 }
 
 template <typename S>
-hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, void *w, long long N, double2 *partial,
-                      double2 *norm_out, hipStream_t st) {
+hipError_t mdot_all(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
+                    hipStream_t st) {
+    const int nchunks = (red_grid(N) + 7) / 8 * 8;
+    for (int i0 = 0; i0 < nv || i0 == 0; i0 += kGS) {
+        VecList vl;
+        vl.n = nv - i0 < kGS ? nv - i0 : kGS;
+        if (vl.n < 0) vl.n = 0;
+        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        const int ngroups = vl.n > 0 ? (vl.n + kMdot - 1) / kMdot : 1;
+        hipLaunchKernelGGL(k_mdot_all<S>, dim3(nchunks * ngroups), dim3(kRedThreads), 0, st, vl,
+                           static_cast<const S *>(w), partial, N, ngroups, nchunks);
+        const bool last = i0 + kGS >= nv;
+        // outputs of this launch: its vl.n products, plus |w|^2 after the last one
+        hipLaunchKernelGGL(k_colsum_groups, dim3(vl.n + (last ? 1 : 0)), dim3(kRedThreads), 0, st, partial, nchunks,
+                           ngroups, vl.n, out + i0);
+        if (last) break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, const double *cscale, void *w, long long N,
+                      double2 *partial, double2 *norm_out, hipStream_t st) {
     const int G = red_grid(N);
     for (int i0 = 0; i0 < nv; i0 += kGS) {
         VecList vl;
+        ScaleList sl;
         vl.n = nv - i0 < kGS ? nv - i0 : kGS;
-        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
+        for (int i = 0; i < kGS; i++) {
+            vl.v[i] = i < vl.n ? v[i0 + i] : w;
+            sl.s[i] = (i < vl.n && cscale) ? cscale[i0 + i] : 1.0;
+        }
         const bool last = i0 + kGS >= nv;
-        hipLaunchKernelGGL(k_axpy_multi<S>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, static_cast<S *>(w),
+        hipLaunchKernelGGL(k_axpy_multi<S>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, sl, static_cast<S *>(w),
                            (last && norm_out) ? partial : (double2 *)nullptr, N);
         if (last && norm_out)
             hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial, G, 1, norm_out);
@@ -251,8 +336,10 @@ hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x,
 }
 
 template hipError_t mdot<double2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
-template hipError_t axpy_multi<double2>(const void *const *, int, const double2 *, void *, long long, double2 *,
-                                        double2 *, hipStream_t);
+template hipError_t mdot_all<double2>(const void *const *, int, const void *, long long, double2 *, double2 *,
+                                      hipStream_t);
+template hipError_t axpy_multi<double2>(const void *const *, int, const double2 *, const double *, void *, long long,
+                                        double2 *, double2 *, hipStream_t);
 template hipError_t scale<double2, double2>(const void *, void *, const double2 *, bool, double, long long,
                                             hipStream_t);
 template hipError_t update<double2>(const void *const *, int, const double2 *, double2 *, long long, hipStream_t);

@@ -236,6 +236,14 @@ int kmax_of(const fgmres_params *p) {
 // sites of the solved system's vectors: V, or V/2 for the even-odd reduced system
 long long system_sites(const dirac_op *op, const fgmres_params *p) { return p->schur ? op->g.V / 2 : op->g.V; }
 
+// entries of each right-hand side's partial-sum buffer: the all-vector inner products of the outer basis (up to
+// kGS vectors per launch) and the passes of the per-site kernels
+size_t partial_entries(const fgmres_params *p) {
+    const int nv = std::min(p->restart + 1, kGS);
+    const size_t outer = (size_t)kMdotChunks * ((nv + kMdot - 1) / kMdot) * (kMdot + 1);
+    return std::max(outer, (size_t)kRedBlocks * (kMdot + 1));
+}
+
 Layout layout(const dirac_op *op, const fgmres_params *p) {
     Layout L;
     const long long V = system_sites(op, p);
@@ -244,7 +252,7 @@ Layout layout(const dirac_op *op, const fgmres_params *p) {
     L.f16 = align256(field_rhs_bytes(WDIRAC_F16S, V));
     const int m = p->restart, mi = is_mixed(p->mode) ? p->inner_restart : 0;
     const int kmax = kmax_of(p);
-    L.scal = align256(sizeof(double2) * ((size_t)kRedBlocks * (kMdot + 1) + 3 * (size_t)kmax + 8));
+    L.scal = align256(sizeof(double2) * (partial_entries(p) + 3 * (size_t)kmax + 8));
     if (is_mixed(p->mode)) L.scal += align256(inner_state_bytes(mi));
     L.per_rhs = (size_t)(m + 2) * L.f64 + L.scal;  // V[0..m], w
     if (p->mode != FGMRES_F64) L.per_rhs += (size_t)m * L.f64;  // Z[0..m)
@@ -333,6 +341,9 @@ struct Rhs {
     // host
     Phase phase = Phase::Residual;
     Arnoldi outer;
+    // the outer basis is stored unnormalised: V[i] = cw[i] v_i, and Z[i] = sz[i] z_i (sz = cw when Z aliases V,
+    // 1 when the preconditioner was given v_i itself)
+    std::vector<double> cw, sz;
     double r0norm = -1, relres = 1;
     bool breakdown = false, converged = false;
     bool nonfinite = false;  // a NaN or Inf reached a residual norm or a Hessenberg column
@@ -490,7 +501,8 @@ int inner_solve(const Ctx &c, const std::vector<Rhs *> &list, GraphCache *gc, co
     const int prec = inner_prec(c.p->mode);
     const int mi = c.p->inner_restart;
     const int maxit = c.p->inner_maxit < mi ? c.p->inner_maxit : mi;
-    for (Rhs *r : list) WD_TRY(site_scale(WDIRAC_F64, prec, r->V[r->outer.j], r->Vi[0], 1.0, c.V, c.st));
+    for (Rhs *r : list)
+        WD_TRY(site_scale(WDIRAC_F64, prec, r->V[r->outer.j], r->Vi[0], 1.0 / r->cw[r->outer.j], c.V, c.st));
     if (!gc) {
         int rc = issue_inner_body(c, list, true, c.st);
         if (rc) return rc;
@@ -595,13 +607,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
         char *s = take(L.scal);
         r.partial = reinterpret_cast<double2 *>(s);
-        r.hcol = r.partial + (size_t)kRedBlocks * (kMdot + 1);
+        r.hcol = r.partial + partial_entries(p);
         r.coef = r.hcol + kmax;
         r.hcol2 = r.coef + kmax;
         r.nrm = r.hcol2 + kmax;
         char *end = reinterpret_cast<char *>(r.nrm + 1);
         if (mixed) {
-            char *ib = s + align256(sizeof(double2) * ((size_t)kRedBlocks * (kMdot + 1) + 3 * (size_t)kmax + 8));
+            char *ib = s + align256(sizeof(double2) * (partial_entries(p) + 3 * (size_t)kmax + 8));
             r.in = carve_inner(ib, p->inner_restart, r.hcol);
             end = ib + inner_state_bytes(p->inner_restart);
         }
@@ -667,12 +679,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         if (sapm)
             for (Rhs *r : arn)
                 WD_TRY(sap_apply(op, p->sap, sg, static_cast<double2 *>(r->Z[r->outer.j]),
-                                 static_cast<const double2 *>(r->V[r->outer.j]), 1, r->sapw, c.st));
+                                 static_cast<const double2 *>(r->V[r->outer.j]), 1, r->sapw,
+                                 1.0 / r->cw[r->outer.j], c.st));
         WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (restart residuals and Arnoldi products)
         std::vector<ApplyItem> bat;
         for (Rhs *r : res) bat.push_back({r->w, r->x, r->t64});
-        for (Rhs *r : arn) bat.push_back({r->w, r->Z[r->outer.j], r->t64});
+        for (Rhs *r : arn) bat.push_back({r->V[r->outer.j + 1], r->Z[r->outer.j], r->t64});
         WD_TRY(apply_many(c, WDIRAC_F64, bat, c.st));
         WD_TRY(hipEventRecord(ev.e[2], c.st));
         for (Rhs *r : res) {
@@ -680,10 +693,15 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             WD_TRY(residual(r->b, r->w, static_cast<double2 *>(r->V[0]), c.N, r->partial, r->nrm, c.st));
         }
         for (Rhs *r : arn) {
+            // classical Gram-Schmidt of w = V[j+1] = D Z[j] against V[0..j]: one launch of inner products (w read
+            // about once), then one update pass that also measures |w_new|^2; coefficients <V_i, w> / cw_i^2
             r->applies++;
             const int j = r->outer.j;
-            WD_TRY(mdot<double2>(r->V.data(), j + 1, r->w, c.N, r->partial, r->hcol, c.st));
-            WD_TRY(axpy_multi<double2>(r->V.data(), j + 1, r->hcol, r->w, c.N, r->partial, r->hcol + j + 1, c.st));
+            std::vector<double> ic2(j + 1);
+            for (int i = 0; i <= j; i++) ic2[i] = 1.0 / (r->cw[i] * r->cw[i]);
+            WD_TRY(mdot_all<double2>(r->V.data(), j + 1, r->V[j + 1], c.N, r->partial, r->hcol, c.st));
+            WD_TRY(axpy_multi<double2>(r->V.data(), j + 1, r->hcol, ic2.data(), r->V[j + 1], c.N, r->partial,
+                                       r->hcol + j + 1, c.st));
         }
         WD_TRY(hipEventRecord(ev.e[3], c.st));
         std::vector<std::pair<const double2 *, int>> src;
@@ -728,7 +746,10 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                 continue;
             }
             r.restarts++;
-            WD_TRY((scale<double2, double2>(r.V[0], r.V[0], nullptr, false, 1.0 / beta, c.N, c.st)));
+            r.cw.assign(m + 1, 0.0);
+            r.sz.assign(m, 1.0);
+            r.cw[0] = beta;  // V[0] = r = beta v_0
+            if (!mixed && !sapm) r.sz[0] = beta;
             r.outer.reset(m, beta);
             r.phase = Phase::Arnoldi;
         }
@@ -746,9 +767,12 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                 r.phase = Phase::Done;
                 continue;
             }
+            // Z[j] = sz_j z_j: h_ij = <V_i, V[j+1]> / (cw_i sz_j), |V[j+1]| = sz_j h_{j+1,j}
+            const double szj = r.sz[j];
             std::vector<zc> col(j + 2);
-            for (int i = 0; i <= j; i++) col[i] = hk[i];
-            const double hn = std::sqrt(std::max(hk[j + 1].real(), 0.0));
+            for (int i = 0; i <= j; i++) col[i] = hk[i] / (r.cw[i] * szj);
+            const double cn = std::sqrt(std::max(hk[j + 1].real(), 0.0));
+            const double hn = cn / szj;
             col[j + 1] = hn;
             const double est = r.outer.add_column(col.data()) / r.r0norm;
             r.hist.push_back(est);
@@ -760,10 +784,19 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                 end = true;
             }
             if (!end) {
-                WD_TRY((scale<double2, double2>(r.w, r.V[r.outer.j], nullptr, false, 1.0 / hn, c.N, c.st)));
+                const int jn = r.outer.j;  // = j + 1
+                r.cw[jn] = cn;
+                if (!(cn > 1e-100 && cn < 1e100)) {
+                    // keep the stored magnitudes representable: normalise explicitly (rare)
+                    WD_TRY((scale<double2, double2>(r.V[jn], r.V[jn], nullptr, false, 1.0 / cn, c.N, c.st)));
+                    r.cw[jn] = 1.0;
+                }
+                if (!mixed && !sapm) r.sz[jn] = r.cw[jn];  // Z aliases V
                 continue;
             }
-            const std::vector<double2> y = to_d2(r.outer.solve());
+            std::vector<zc> yz = r.outer.solve();
+            for (size_t i = 0; i < yz.size(); i++) yz[i] /= r.sz[i];
+            const std::vector<double2> y = to_d2(yz);
             WD_TRY(update<double2>(r.Z.data(), (int)y.size(), y.data(), r.x, c.N, c.st));
             r.phase = Phase::Residual;
         }

@@ -19,8 +19,8 @@ struct SapGeom {
 int sap_geometry(const dirac_op *op, const sap_params *p, SapGeom &sg);
 // device workspace of dirac_sap for nrhs right-hand sides (additive cycles > 1 alternate between two fields)
 size_t sap_workspace(const dirac_op *op, const sap_params *p, int nrhs);
-// x = SAP(b) from x = 0 (native FP64 fields, nrhs consecutive right-hand sides); work: sap_workspace bytes
+// x = SAP(bscale b) from x = 0 (native FP64 fields, nrhs consecutive right-hand sides); work: sap_workspace bytes
 hipError_t sap_apply(const dirac_op *op, const sap_params &p, const SapGeom &sg, double2 *x, const double2 *b,
-                     int nrhs, double2 *work, hipStream_t st);
+                     int nrhs, double2 *work, double bscale, hipStream_t st);
 
 }  // namespace wd

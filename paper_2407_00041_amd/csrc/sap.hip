@@ -124,7 +124,7 @@ template <int P, bool LDSL, bool REGC>
 __global__ __launch_bounds__(kSapMaxBlock) void sap_pass_kernel(const double2 *__restrict__ b, const double2 *xin,
                                                                 double2 *xout, size_t rhs_stride, OpData d, Geom g,
                                                                 SapGeom sg, int colour, int xzero, int own_zero,
-                                                                int nmr, int apbc) {
+                                                                int nmr, int apbc, double bscale) {
     using T = TOf<P>;
     constexpr int SF = -1, SB = +1;  // forward / backward projector signs of D
     __shared__ cx<T> rho_lds[12][kSapMaxBlock];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kSapMaxBlock) void sap_pass_kernel(const double2 *_
             cx<T> r = mk<T>(0, 0);
             if (active) {
                 const double2 a = b[(size_t)k * V + s];
-                r = mk<T>((T)a.x, (T)a.y) - acc[k];
+                r = mk<T>((T)(bscale * a.x), (T)(bscale * a.y)) - acc[k];
             }
             rho_lds[k][l] = r;
         }
@@ -353,17 +353,18 @@ __global__ __launch_bounds__(kSapMaxBlock) void sap_pass_kernel(const double2 *_
 template <int P, bool LDSL, bool REGC>
 hipError_t launch_pass(const dirac_op *op, const SapGeom &sg, int colour, int nblk, const double2 *b,
                        const double2 *xin, double2 *xout, bool xzero, bool own_zero, int nmr, int nrhs,
-                       hipStream_t st) {
+                       double bscale, hipStream_t st) {
     const int threads = (sg.bvol + 63) / 64 * 64;
     const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
     hipLaunchKernelGGL((sap_pass_kernel<P, LDSL, REGC>), dim3(nblk, nrhs), dim3(threads), 0, st, b, xin, xout,
                        (size_t)12 * op->g.V, op->data(P), op->g, sg, colour, xzero ? 1 : 0, own_zero ? 1 : 0, nmr,
-                       apbc);
+                       apbc, bscale);
     return hipGetLastError();
 }
 
 hipError_t sap_pass(const dirac_op *op, const sap_params &p, const SapGeom &sg, int colour, const double2 *b,
-                    const double2 *xin, double2 *xout, bool xzero, bool own_zero, int nrhs, hipStream_t st) {
+                    const double2 *xin, double2 *xout, bool xzero, bool own_zero, int nrhs, double bs,
+                    hipStream_t st) {
     int nblk = sg.nblocks;
     int dec = colour;
     if (colour >= 0) {
@@ -376,19 +377,19 @@ hipError_t sap_pass(const dirac_op *op, const sap_params &p, const SapGeom &sg, 
     }
     if (p.prec == WDIRAC_F64)
         return launch_pass<WDIRAC_F64, false, false>(op, sg, dec, nblk, b, xin, xout, xzero, own_zero, p.mr_iters,
-                                                     nrhs, st);
+                                                     nrhs, bs, st);
     const bool ldsl = op->link_rows == 2, regc = op->clover_compact;
     if (ldsl && regc)
         return launch_pass<WDIRAC_F32, true, true>(op, sg, dec, nblk, b, xin, xout, xzero, own_zero, p.mr_iters,
-                                                   nrhs, st);
+                                                   nrhs, bs, st);
     if (ldsl)
         return launch_pass<WDIRAC_F32, true, false>(op, sg, dec, nblk, b, xin, xout, xzero, own_zero, p.mr_iters,
-                                                    nrhs, st);
+                                                    nrhs, bs, st);
     if (regc)
         return launch_pass<WDIRAC_F32, false, true>(op, sg, dec, nblk, b, xin, xout, xzero, own_zero, p.mr_iters,
-                                                    nrhs, st);
+                                                    nrhs, bs, st);
     return launch_pass<WDIRAC_F32, false, false>(op, sg, dec, nblk, b, xin, xout, xzero, own_zero, p.mr_iters, nrhs,
-                                                 st);
+                                                 bs, st);
 }
 
 }  // namespace
@@ -428,11 +429,12 @@ size_t sap_workspace(const dirac_op *op, const sap_params *p, int nrhs) {
 }
 
 hipError_t sap_apply(const dirac_op *op, const sap_params &p, const SapGeom &sg, double2 *x, const double2 *b,
-                     int nrhs, double2 *work, hipStream_t st) {
+                     int nrhs, double2 *work, double bscale, hipStream_t st) {
     if (!p.additive) {
         for (int cyc = 0; cyc < p.cycles; cyc++)
             for (int c = 0; c < 2; c++) {
-                const hipError_t e = sap_pass(op, p, sg, c, b, x, x, cyc == 0 && c == 0, cyc == 0 && c == 1, nrhs, st);
+                const hipError_t e =
+                    sap_pass(op, p, sg, c, b, x, x, cyc == 0 && c == 0, cyc == 0 && c == 1, nrhs, bscale, st);
                 if (e != hipSuccess) return e;
             }
         return hipSuccess;
@@ -443,7 +445,7 @@ hipError_t sap_apply(const dirac_op *op, const sap_params &p, const SapGeom &sg,
     int out = (p.cycles % 2) ? 0 : 1;
     const double2 *in = nullptr;
     for (int cyc = 0; cyc < p.cycles; cyc++) {
-        const hipError_t e = sap_pass(op, p, sg, -1, b, in, bufs[out], cyc == 0, false, nrhs, st);
+        const hipError_t e = sap_pass(op, p, sg, -1, b, in, bufs[out], cyc == 0, false, nrhs, bscale, st);
         if (e != hipSuccess) return e;
         in = bufs[out];
         out ^= 1;
@@ -483,7 +485,7 @@ int dirac_sap(const dirac_op *op, double *x, const double *b, int nrhs, const sa
             return fail(WDIRAC_EINVAL, "SAP workspace overlaps x or b");
     }
     const hipError_t e = sap_apply(op, *p, sg, reinterpret_cast<double2 *>(x), reinterpret_cast<const double2 *>(b),
-                                   nrhs, static_cast<double2 *>(work), (hipStream_t)stream);
+                                   nrhs, static_cast<double2 *>(work), 1.0, (hipStream_t)stream);
     if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("SAP launch: ") + hipGetErrorString(e));
     return WDIRAC_OK;
 }
