@@ -81,6 +81,14 @@ def parse():
                          "(reproducible profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (counter calibration)")
+    ap.add_argument("--kernel-suite", metavar="MANIFEST",
+                    help="run every product kernel at the benchmark sizes (for rocprofv3), write the manifest of "
+                         "their algorithmic bytes and exit")
+    ap.add_argument("--summarize", nargs=5, metavar=("MANIFEST", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "OUT_MD"),
+                    help="join a kernel-suite manifest with rocprofv3 output into a summary and exit (no GPU)")
+    ap.add_argument("--summary-command", default="", help="command text recorded in the summary")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle FGMRES solves to convergence instead of a bounded sample")
     return ap.parse_args()
 
 
@@ -94,6 +102,41 @@ def kernel_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def all_sources_hash() -> str:
+    """Hash of every library source (kernels and host code), recorded in the kernel-suite summary."""
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2407_00041_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNELS_PROFILE = "profiles/kernels_48x96_traffic.md"
+
+
+def kernel_profile_rows():
+    """{pattern: counted bytes per launch} from the committed kernel-suite summary, when it was taken on the
+    current sources (else {})."""
+    path = os.path.join(ROOT, KERNELS_PROFILE)
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    m = re.search(r"sources_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != all_sources_hash():
+        return {}
+    rows = {}
+    for line in text.splitlines():
+        c = [x.strip() for x in line.split("|")]
+        if len(c) > 11 and c[1].startswith("`"):
+            try:
+                rows[c[1].strip("`")] = {"counted_GB_per_launch": float(c[8]) + float(c[9]),
+                                         "counted_GBps": float(c[10]), "avg_us": float(c[4])}
+            except ValueError:
+                pass
+    return rows
 
 
 def traffic_from_profile():
@@ -181,101 +224,133 @@ def batched_run(torch, op, dims, stream, steps):
     return res
 
 
+SAP_DEFAULT = {"block": (4, 4, 4, 4), "cycles": 1, "mr_iters": 4, "prec": "f32"}
+
+
+def solver_sweep(op, bn, configs):
+    """Wall time to 1e-10 of one right-hand side for each candidate configuration (best of the list is used for
+    the 12-RHS run; the sweep itself is not part of any reported time)."""
+    import torch
+    out = []
+    for name, kw in configs:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st, rc = op.solve(bn, **kw)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t, name, kw, st[0]["applies"], rc))
+    return out
+
+
 def fgmres_run(torch, op, dims, nrhs_total):
-    """Plain FP64 FGMRES(30) vs the mixed FP16S-preconditioned FGMRES on the
-    same right-hand sides, in waves sized to the free HBM, on D x = b and on
-    the even-odd reduced system."""
+    """12 right-hand sides to 1e-10, in waves sized to the free HBM, by every
+    solver: plain FP64 FGMRES(30) (the reference), plain FP64 at the restart a
+    one-RHS sweep picks, the mixed FP64/FP16S solver at its tuned restart 8 and
+    at restart 30, FGMRES with the SAP preconditioner, and FP64 and mixed on
+    the even-odd reduced system.  Times are summed over the waves; errors are
+    against the FP64 FGMRES(30) solution."""
     from paper_2407_00041_amd import synth
-    p64 = dict(restart=30, tol=1e-10, maxit=5000, mode="f64")
-    pmx = dict(restart=MIXED["restart"], tol=1e-10, maxit=500, mode=MIXED["mode"],
-               inner_restart=MIXED["inner_restart"], inner_tol=MIXED["inner_tol"], inner_maxit=MIXED["inner_restart"])
-    fb = op.field_bytes("f64", 1)
-    free, _ = torch.cuda.mem_get_info()
-    per = max(op.workspace_bytes(1, 30, "f64"),
-              op.workspace_bytes(1, pmx["restart"], pmx["mode"], pmx["inner_restart"])) + 5 * fb
-    wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
-    log(f"[bench] fgmres: {nrhs_total} RHS in waves of {wave} "
-        f"(free {free / 2**30:.0f} GiB, {per / 2**30:.1f} GiB per RHS)")
-    # one workspace for every wave and both solvers (allocation is not timed)
-    wbytes = max(op.workspace_bytes(wave, 30, "f64"),
-                 op.workspace_bytes(wave, pmx["restart"], pmx["mode"], pmx["inner_restart"]))
-    work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
-    inner = "f16s" if pmx["mode"].endswith("f16s") else "f32"
-    for n in sorted({1, wave, nrhs_total % wave or wave}):     # the solvers' batched applies
+    base = dict(tol=1e-10)
+    inner = dict(inner_restart=MIXED["inner_restart"], inner_tol=MIXED["inner_tol"], inner_maxit=MIXED["inner_restart"])
+    b1 = op.pack(synth.gaussian_spinor(dims, 3000, nrhs=1, device="cuda"), "f64")
+    for n in (1, 2, 3):       # batched applies of the solvers' waves
         if not TUNE_FIXED:
             op.autotune("f64", n)
-            op.autotune(inner, n)
-    t64 = tmx = t64r = tmxr = 0.0
-    ph64 = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
-    phmx = {"apply": 0.0, "precond": 0.0, "ortho": 0.0}
-    a64, amx, ainner, errs, res64, resmx = [], [], [], [], [], []
-    a64r, amxr, ainr, errsr, res64r, resmxr = [], [], [], [], [], []
+            op.autotune("f16s", n)
+    sweep64 = solver_sweep(op, b1, [(f"r{m}", dict(base, restart=m, maxit=5000, mode="f64"))
+                                    for m in (10, 16, 20, 30, 50)])
+    best64 = min(sweep64)
+    sweep_sap = solver_sweep(op, b1, [(f"r{m} c{c} mr{k}", dict(base, restart=m, maxit=500, mode="sap",
+                                                                sap=dict(SAP_DEFAULT, cycles=c, mr_iters=k)))
+                                      for m in (10, 16) for c, k in ((1, 4), (2, 4), (1, 6))])
+    best_sap = min(sweep_sap)
+    log("[bench] fp64 restart sweep " + ", ".join(f"{n} {t:.2f}s/{a}" for t, n, _, a, _ in sweep64))
+    log("[bench] sap sweep " + ", ".join(f"{n} {t:.3f}s/{a}" for t, n, _, a, _ in sweep_sap))
+    del b1
+    solvers = [
+        ("fp64", "FGMRES(30), FP64", dict(base, restart=30, maxit=5000, mode="f64")),
+        ("fp64_best_restart", f"FGMRES({best64[2]['restart']}), FP64 (fastest restart of 10/16/20/30/50 on one RHS)",
+         best64[2]),
+        ("mixed", f"FP64 FGMRES({MIXED['restart']}), preconditioner inner GMRES({MIXED['inner_restart']}) on the "
+                  f"FP16S operator (relative tol {MIXED['inner_tol']})",
+         dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], **inner)),
+        ("mixed_restart30", "the mixed solver with outer FGMRES(30)",
+         dict(base, restart=30, maxit=500, mode=MIXED["mode"], **inner)),
+        ("sap", f"FP64 FGMRES({best_sap[2]['restart']}), preconditioner SAP (FP32, 4^4 blocks, red-black, "
+                f"{best_sap[2]['sap']['cycles']} cycle(s), {best_sap[2]['sap']['mr_iters']} MR steps)", best_sap[2]),
+        ("even_odd_fp64", "FGMRES(30), FP64, on S = A_ee - H_eo A_oo^-1 H_oe",
+         dict(base, restart=30, maxit=5000, mode="f64", schur=True)),
+        ("even_odd_mixed", "the mixed solver on S (FP16S S in the inner GMRES)",
+         dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], schur=True, **inner)),
+    ]
+    fb = op.field_bytes("f64", 1)
+    free, _ = torch.cuda.mem_get_info()
+    per = max(op.workspace_bytes(1, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=1,
+                                 schur=kw.get("schur", False), sap=kw.get("sap")) for _, _, kw in solvers) + 6 * fb
+    wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
+    log(f"[bench] fgmres: {nrhs_total} RHS in waves of {wave} (free {free / 2**30:.0f} GiB, "
+        f"{per / 2**30:.1f} GiB per RHS)")
+    wbytes = max(op.workspace_bytes(wave, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=wave,
+                                    schur=kw.get("schur", False), sap=kw.get("sap")) for _, _, kw in solvers)
+    work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    rec = {k: {"solver": d, "seconds": 0.0, "applies": [], "inner_applies": [], "true_residual": [], "err": [],
+               "phase_seconds": {"apply": 0.0, "precond": 0.0, "ortho": 0.0}} for k, d, _ in solvers}
     for w0 in range(0, nrhs_total, wave):
         nw = min(wave, nrhs_total - w0)
         b = op.pack(synth.gaussian_spinor(dims, 3000 + w0, nrhs=nw, device="cuda"), "f64")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        x64, st64, _ = op.solve(b, nrhs=nw, work=work, **p64)
-        torch.cuda.synchronize()
-        t64 += time.perf_counter() - t
-        t = time.perf_counter()
-        xmx, stmx, _ = op.solve(b, nrhs=nw, work=work, **pmx)
-        torch.cuda.synchronize()
-        tmx += time.perf_counter() - t
-        xmx_keep = xmx
-        for k in ph64:  # GPU time per phase of this wave (shared by its right-hand sides)
-            ph64[k] += st64[0]["seconds_" + k]
-            phmx[k] += stmx[0]["seconds_" + k]
-        del xmx
-        t = time.perf_counter()
-        x64r, st64r, _ = op.solve(b, nrhs=nw, work=work, schur=True, **p64)
-        torch.cuda.synchronize()
-        t64r += time.perf_counter() - t
-        t = time.perf_counter()
-        xmxr, stmxr, _ = op.solve(b, nrhs=nw, work=work, schur=True, **pmx)
-        torch.cuda.synchronize()
-        tmxr += time.perf_counter() - t
-        for r in range(nw):
-            u = x64[r * fb:(r + 1) * fb].view(torch.float64)
-            nu = torch.linalg.vector_norm(u)
-            for xs, e in ((xmx_keep, errs), (x64r, errsr), (xmxr, errsr)):
-                v = xs[r * fb:(r + 1) * fb].view(torch.float64)
-                e.append(float(torch.linalg.vector_norm(u - v) / nu))
-            a64.append(st64[r]["applies"])
-            amx.append(stmx[r]["applies"])
-            ainner.append(stmx[r]["inner_applies"])
-            res64.append(st64[r]["true_residual"])
-            resmx.append(stmx[r]["true_residual"])
-            a64r.append(st64r[r]["applies"])
-            amxr.append(stmxr[r]["applies"])
-            ainr.append(stmxr[r]["inner_applies"])
-            res64r.append(st64r[r]["true_residual"])
-            resmxr.append(stmxr[r]["true_residual"])
-        log(f"[bench] fgmres after RHS {w0 + nw}: fp64 {t64:.2f}s mixed {tmx:.2f}s; even-odd reduced: "
-            f"fp64 {t64r:.2f}s mixed {tmxr:.2f}s")
-        del b, x64, xmx_keep, x64r, xmxr
+        ref = None
+        for key, _, kw in solvers:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, st, _ = op.solve(b, nrhs=nw, work=work, wave=wave, **kw)
+            torch.cuda.synchronize()
+            r = rec[key]
+            r["seconds"] += time.perf_counter() - t
+            for ph in r["phase_seconds"]:
+                r["phase_seconds"][ph] += st[0]["seconds_" + ph]
+            if ref is None:
+                ref = x
+            for k in range(nw):
+                u = ref[k * fb:(k + 1) * fb].view(torch.float64)
+                v = x[k * fb:(k + 1) * fb].view(torch.float64)
+                r["err"].append(float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(u)))
+                r["applies"].append(st[k]["applies"])
+                r["inner_applies"].append(st[k]["inner_applies"])
+                r["true_residual"].append(st[k]["true_residual"])
+            if x is not ref:
+                del x
+        log(f"[bench] fgmres after RHS {w0 + nw}: " + ", ".join(f"{k} {rec[k]['seconds']:.2f}s" for k in rec))
+        del b, ref
         torch.cuda.empty_cache()
-    return {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
-            "fp64": {"solver": "FGMRES(30), FP64", "seconds": t64, "phase_seconds": ph64, "applies": a64,
-                     "true_residual_max": max(res64), "converged": all(r < 1e-10 for r in res64)},
-            "mixed": {"solver": f"FP64 FGMRES({pmx['restart']}), preconditioner inner GMRES({pmx['inner_restart']}) "
-                                f"on the {pmx['mode'][6:].upper()} operator (relative tol {pmx['inner_tol']})",
-                      "seconds": tmx, "phase_seconds": phmx, "fp64_applies": amx, "fp16s_applies": ainner,
-                      "true_residual_max": max(resmx), "converged": all(r < 1e-10 for r in resmx)},
-            "speedup_mixed_vs_fp64": t64 / tmx if tmx > 0 else None,
-            "error_vs_fp64_max": max(errs),
-            "even_odd": {
-                "fp64": {"solver": "FGMRES(30), FP64, on S = A_ee - H_eo A_oo^-1 H_oe", "seconds": t64r,
-                         "applies_of_S": a64r, "true_residual_max": max(res64r),
-                         "converged": all(r < 1e-10 for r in res64r)},
-                "mixed": {"solver": "the mixed solver above on S (FP16S S in the inner GMRES)", "seconds": tmxr,
-                          "fp64_applies_of_S": amxr, "fp16s_applies_of_S": ainr,
-                          "true_residual_max": max(resmxr), "converged": all(r < 1e-10 for r in resmxr)},
-                "speedup_mixed_vs_fp64": t64r / tmxr if tmxr > 0 else None,
-                "speedup_vs_full_system": {"fp64": t64 / t64r if t64r > 0 else None,
-                                           "mixed": tmx / tmxr if tmxr > 0 else None},
-                "speedup_mixed_even_odd_vs_plain_fp64": t64 / tmxr if tmxr > 0 else None,
-                "error_vs_plain_fp64_max": max(errsr)}}
+    out = {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
+           "sweeps_one_rhs_seconds": {"fp64": {n: t for t, n, *_ in sweep64},
+                                      "sap": {n: t for t, n, *_ in sweep_sap}}}
+    for k, r in rec.items():
+        out[k] = {"solver": r["solver"], "seconds": r["seconds"], "phase_seconds": r["phase_seconds"],
+                  "applies": r["applies"], "true_residual_max": max(r["true_residual"]),
+                  "converged": all(x < 1e-10 for x in r["true_residual"]),
+                  "error_vs_fp64_max": max(r["err"])}
+        if any(r["inner_applies"]):
+            out[k]["inner_applies"] = r["inner_applies"]
+    t64 = rec["fp64"]["seconds"]
+    out["speedup_vs_fp64"] = {k: t64 / r["seconds"] for k, r in rec.items() if r["seconds"] > 0}
+    out["speedup_vs_fp64_best_restart"] = {k: rec["fp64_best_restart"]["seconds"] / r["seconds"]
+                                           for k, r in rec.items() if r["seconds"] > 0}
+    return out
+
+
+def sap_run(torch, op, psid, stream, steps=10):
+    """One SAP application (FP32 4^4 blocks, one red-black cycle, 4 MR steps) on one right-hand side: time,
+    algorithmic bytes and flops per cycle (model in the design notes)."""
+    bn = op.pack(psid, "f64")
+    x = torch.empty_like(bn)
+    ms = time_launches(torch, lambda: op.sap(bn, x=x, **SAP_DEFAULT), steps, 2, stream)
+    V = op.V
+    ab = SAP_BYTES_SITE_CYCLE * V
+    fl = SAP_FLOP_SITE_CYCLE * V
+    del bn, x
+    return {"ms_per_cycle": ms, "params": {k: list(v) if isinstance(v, tuple) else v for k, v in SAP_DEFAULT.items()},
+            "alg_bytes_per_cycle": ab, "alg_GBps": ab / (ms * 1e-3) / 1e9, "frac_hbm": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "flop_per_cycle": fl, "TFLOPs": fl / (ms * 1e-3) / 1e12, "frac_fp32_vector": fl / (ms * 1e-3) / 157.3e12}
 
 
 def config32_run(torch, stream):
@@ -338,11 +413,301 @@ def differentiation_run(torch):
     return res
 
 
+# ---------------------------------------------------------------------------
+# Per-kernel measurement.  Every product kernel runs at the benchmark sizes in
+# `kernel_suite` (for rocprofv3 kernel traces and FETCH_SIZE / WRITE_SIZE
+# counter runs); the suite writes a manifest of the algorithmic bytes of its
+# dispatches, kernel by kernel, which `summarize_profile` joins with the
+# profiler's CSV output into the committed summaries.
+
+FIELD = {"f64": 192, "f32": 96, "f16s": 52}           # bytes per site of one native field
+SAP_BYTES_SITE_CYCLE = 992   # FP32 SAP (two-row links, compact clover), first cycle from x = 0, per site
+SAP_FLOP_SITE_CYCLE = 9000   # with 4 MR steps per block solve (model in the design notes)
+FORCE_BYTES_SITE = {"insert": 384 + 480, "link": 576 + 384 + 480 + 576}
+# even-odd reduced operator, two right-hand sides per launch: bytes per half-lattice site of each launch
+SCHUR_PAIR_BYTES_HALF = {"f64": (2112, 2368), "f32": (1056, 1184), "f16s": (544, 616)}
+PREC_ID = {"f64": 0, "f32": 1, "f16s": 2}
+
+
+def _fixed(wd, order, block, tchunk, nr):
+    for k, v in (("order", order), ("block", block), ("tchunk", tchunk), ("nr_f64", nr), ("nr_f32", nr),
+                 ("nr_f16s", nr)):
+        wd.tune_set(k, v)
+
+
+def site_pass_bytes(nv, field, extra_w):
+    """Bytes of the per-site Gram-Schmidt launches for nv basis vectors (passes of 8): every pass reads its
+    vectors and w; extra_w adds w's write per pass."""
+    passes = max(1, -(-nv // 8))
+    return [(min(8, nv - 8 * k) + 1 + extra_w) * field for k in range(passes)]
+
+
+def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
+    """Every product kernel at the benchmark sizes, with fixed launch
+    configurations (no autotuning inside the profiled region); writes the
+    manifest {pattern: {"dispatches": n, "alg_bytes": total, "note": ...}}."""
+    import paper_2407_00041_amd as wd
+    from paper_2407_00041_amd import synth
+    V = int(np.prod(dims))
+    Ud = synth.smooth_links(dims, 1003, device="cuda")
+    psid = synth.gaussian_spinor(dims, 2000, nrhs=2, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    op = wd.DiracOp(dims, U, -0.35, 1.0, precisions=("f64", "f32", "f16s"), compress_links=True,
+                    compress_clover=True, even_odd=True)
+    man = {}
+
+    def add(pattern, n, nbytes, note):
+        e = man.setdefault(pattern, {"dispatches": 0, "alg_bytes": 0.0, "note": note})
+        e["dispatches"] += n
+        e["alg_bytes"] += float(nbytes)
+
+    st = torch.cuda.current_stream()
+    reps = 5
+    # single applies (the benchmark's launches: column sweep FP64/FP32, T-sweep site kernel FP16S)
+    for p, cfg, pat in (("f64", (3, 256, 2, 1), r"dslash_column_kernel<0, false, 1>"),
+                        ("f32", (3, 256, 2, 1), r"dslash_column_kernel<1, false, 1>"),
+                        ("f16s", (2, 256, 4, 1), r"dslash_kernel<2, false, 1>")):
+        _fixed(wd, *cfg)
+        x = op.pack(psid[:1], p)
+        y = op.empty(p, 1)
+        for _ in range(reps):
+            op.apply_native(y, x, 1, p, stream=st)
+        add(pat, reps, reps * BYTES_SITE[p] * V, f"D apply {p}, 1 RHS")
+        del x, y
+    torch.cuda.synchronize()
+    # one FP32 launch over batches {1, 4, 12, 24}: the link-stationary kernel
+    _fixed(wd, 5, 128, 1, 1)
+    sizes = [1, 4, 12, 24]
+    n = sum(sizes)
+    nat = op.pack(synth.gaussian_spinor(dims, 2100, nrhs=n, device="cuda"), "f32")
+    rb = op.field_bytes("f32", 1)
+    outs, batches, r0 = [], [], 0
+    for k in sizes:
+        o = op.empty("f32", k)
+        outs.append(o)
+        batches.append((o, nat[r0 * rb:(r0 + k) * rb], k))
+        r0 += k
+    for _ in range(2):
+        op.apply_batched(batches, "f32", stream=st)
+    add(r"dslash_stationary_kernel<1, false>", 2, 2 * (LINK_BYTES["f32"] + CLOVER_BYTES["f32"] + 192 * n) * V,
+        "batched FP32 apply, 41 RHS in batches {1,4,12,24}")
+    del outs, batches, nat
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # even-odd reduced operator S on pairs of right-hand sides
+    for p in ("f64", "f32", "f16s"):
+        e, o = op.split(op.pack(psid, p), p, 2)
+        out, tmp = op.empty_parity(p, 2), op.empty_parity(p, 2)
+        for _ in range(3):
+            op.apply_schur_native(out, e, tmp, 2, p, stream=st)
+        bo, be = SCHUR_PAIR_BYTES_HALF[p]
+        kern = "parity_column_kernel" if p != "f16s" else "parity_kernel"
+        i = PREC_ID[p]
+        add(kern + rf"<(P,DAG,SELF,HOP,INV,ROWS = )?{i}, false, 0, true, true", 3, 3 * bo * V / 2,
+            f"S (pair), odd launch A_oo^-1 H_oe, {p}")
+        add(kern + rf"<(P,DAG,SELF,HOP,INV,ROWS = )?{i}, false, 2, true, false", 3, 3 * be * V / 2,
+            f"S (pair), even launch A_ee - H_eo, {p}")
+        del e, o, out, tmp
+    torch.cuda.synchronize()
+    # SAP, FP32 blocks of 4^4, one red-black cycle, 4 MR steps (two launches per cycle)
+    bn = op.pack(psid[:1], "f64")
+    for _ in range(3):
+        op.sap(bn, block=(4, 4, 4, 4), cycles=1, mr_iters=4, prec="f32")
+    add(r"sap_pass_kernel<1, true, true>", 6, 3 * SAP_BYTES_SITE_CYCLE * V, "SAP cycle FP32 4^4 blocks (2 passes)")
+    torch.cuda.synchronize()
+    # one cycle of plain FP64 FGMRES(30) (the outer Gram-Schmidt kernels), and the mixed solver's inner cycles
+    _fixed(wd, 3, 256, 2, 1)
+    x, stt, _ = op.solve(bn, restart=30, tol=1e-14, maxit=31)
+    assert stt[0]["applies"] == 32, stt[0]["applies"]
+    vec = 192.0 * V
+    add(r"dslash_column_kernel<0, false, 1>", 32, 32 * BYTES_SITE["f64"] * V, "D apply inside FGMRES")
+    add(r"k_mdot_all", 30, sum(j + 2 for j in range(30)) * vec, "outer inner products, nv = 1..30 (w once)")
+    add(r"k_axpy_multi", 30, sum(j + 3 for j in range(30)) * vec, "outer CGS update, nv = 1..30")
+    add(r"k_residual", 2, 2 * 3 * vec, "restart residual b - D x")
+    add(r"k_update", 1, 32 * vec, "x += Z y, 30 vectors")
+    del x
+    torch.cuda.synchronize()
+    _fixed(wd, 2, 256, 4, 1)   # inner FP16S applies: the T-sweep site kernel
+    x, stm, _ = op.solve(bn, restart=8, tol=1e-14, maxit=9, mode="mixed_f16s", inner_restart=10, inner_tol=1e-14,
+                         inner_maxit=10)
+    steps = stm[0]["applies"] - 2
+    assert stm[0]["inner_applies"] == 10 * steps, stm[0]
+    f16 = 52.0 * V
+    mdot = sum(sum(site_pass_bytes(k + 1, f16, 0)) for k in range(10)) * steps
+    axpy = sum(sum(site_pass_bytes(k + 1, f16, 1)) for k in range(10)) * steps
+    nmd = sum(len(site_pass_bytes(k + 1, f16, 0)) for k in range(10)) * steps
+    add(r"dslash_kernel<2, false, 1>", 10 * steps, 10 * steps * BYTES_SITE["f16s"] * V, "inner FP16S applies")
+    add(r"k_site_mdot<2>", nmd, mdot, "inner inner products (FP16S fields)")
+    add(r"k_site_axpy<2>", nmd, axpy, "inner orthogonalisation (FP16S fields)")
+    add(r"k_site_combine<2>", 2 * steps, steps * (10 * 52 + 192 + 2 * 192) * V, "inner solution into Z (FP64)")
+    add(r"k_site_scale<0, 2>", steps, steps * (192 + 52) * V, "outer v_j to the inner FP16S start vector")
+    del x, bn
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    del op
+    # the link derivative at 24^3 x 48
+    fd = (48, 24, 24, 24)
+    Vf = int(np.prod(fd))
+    Uf = synth.smooth_links(fd, 1005, device="cuda").cpu().numpy()
+    opf = wd.DiracOp(fd, Uf, -0.3, 1.0, precisions=("f64",))
+    en = opf.pack(synth.gaussian_spinor(fd, 3002, nrhs=1, device="cuda"), "f64")
+    xn = opf.pack(synth.gaussian_spinor(fd, 3001, nrhs=1, device="cuda"), "f64")
+    for _ in range(3):
+        opf.force(en, xn, 1)
+    add(r"force_insert_kernel", 3, 3 * FORCE_BYTES_SITE["insert"] * Vf, "force pass 1 at 24^3x48")
+    add(r"force_link_kernel", 3, 3 * FORCE_BYTES_SITE["link"] * Vf, "force pass 2 at 24^3x48")
+    torch.cuda.synchronize()
+    del opf, en, xn
+    # copy probe of known size (counter calibration): 1 GiB read, 1 GiB written, 5 times
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    add(r"vectorized_elementwise_kernel<4, at::native::BUnaryFunctor<float", 5, 5 * 2 * (1 << 30),
+        "copy probe (torch.mul), 1 GiB in + 1 GiB out")
+    wd.tune_set("explicit", 0)
+    with open(manifest_path, "w") as f:
+        json.dump(man, f, indent=1)
+    log(f"[bench] kernel suite done; manifest {manifest_path}")
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, command):
+    """Join the suite's manifest with rocprofv3 output: per kernel pattern the
+    dispatch count, average duration, algorithmic GB/s, and the counter bytes
+    (FETCH_SIZE scaled by the copy probe's calibration, WRITE_SIZE likewise)."""
+    man = json.load(open(manifest_path))
+    kt = _read_csv(_find(trace_dir, "kernel_trace.csv"))
+
+    def counters(d, name):
+        rows = _read_csv(_find(d, "counter_collection.csv"))
+        out = []
+        for r in rows:
+            if r.get("Counter_Name", "") == name:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    fetch = counters(fetch_dir, "FETCH_SIZE")
+    write = counters(write_dir, "WRITE_SIZE")
+    res = {}
+    for pat, e in man.items():
+        rx = re.compile(pat)
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in kt if rx.search(r["Kernel_Name"])]
+        fk = [v for k, v in fetch if rx.search(k)]
+        wk = [v for k, v in write if rx.search(k)]
+        res[pat] = {"note": e["note"], "dispatches": e["dispatches"], "seen": len(durs),
+                    "seconds": sum(durs), "alg_bytes": e["alg_bytes"],
+                    "fetch_kib": sum(fk), "write_kib": sum(wk), "counted": (len(fk), len(wk))}
+    probe = next(p for p in res if "BUnaryFunctor" in p)
+    cal_f = res[probe]["alg_bytes"] / 2 / max(res[probe]["fetch_kib"] * 1024, 1)
+    cal_w = res[probe]["alg_bytes"] / 2 / max(res[probe]["write_kib"] * 1024, 1)
+    lines = ["# Product kernels at the benchmark sizes: time, algorithmic and counted HBM traffic", "",
+             "Commands (repo root, MI355X; three separate runs of the same kernel suite, then the join):", "",
+             "```", command, "```", "",
+             f"Calibration: the suite's copy probe (1 GiB read + 1 GiB written per dispatch) reads as FETCH_SIZE x "
+             f"{cal_f:.3f} and WRITE_SIZE x {cal_w:.3f}; both factors are applied below.  Counter bytes are measured "
+             f"at the L2's memory side (Infinity Cache hits included), an upper bound on HBM bytes.", "",
+             "| kernel (pattern) | what | dispatches | avg us | alg GB/launch | alg GB/s | frac of 8 TB/s | "
+             "counted read GB/launch | counted write GB/launch | counted GB/s | counted / alg |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for pat, r in res.items():
+        n = max(r["seen"], 1)
+        avg = r["seconds"] / n
+        ab = r["alg_bytes"] / max(r["dispatches"], 1)
+        rd = r["fetch_kib"] * 1024 * cal_f / max(r["counted"][0], 1)
+        wr = r["write_kib"] * 1024 * cal_w / max(r["counted"][1], 1)
+        ag = ab / avg / 1e9 if avg > 0 else 0.0
+        cg = (rd + wr) / avg / 1e9 if avg > 0 else 0.0
+        lines.append(f"| `{pat}` | {r['note']} | {r['seen']} (expected {r['dispatches']}) | {avg * 1e6:.1f} | "
+                     f"{ab / 1e9:.4f} | {ag:.0f} | {ag / HBM_PEAK_GBS:.3f} | {rd / 1e9:.4f} | {wr / 1e9:.4f} | "
+                     f"{cg:.0f} | {(rd + wr) / ab if ab else 0:.2f} |")
+    lines += ["", f"sources_sha256_16: {all_sources_hash()}", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    log(f"[bench] wrote {out_md}")
+
+
+def kernel_table(extra, V):
+    """One roofline entry per product kernel measured in this run (HIP events on the launch stream), with the
+    counted traffic of the committed kernel-suite summary when it matches the sources."""
+    prof = kernel_profile_rows()
+    rows = []
+
+    def row(kernel, what, ms, alg_bytes, pattern, flops=None):
+        r = {"kernel": kernel, "what": what, "ms": ms, "alg_bytes": alg_bytes,
+             "alg_GBps": alg_bytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "counted": prof.get(pattern)}
+        if flops:
+            r["TFLOPs"] = flops / (ms * 1e-3) / 1e12
+        rows.append(r)
+
+    for p, pat in (("f64", "dslash_column_kernel<0, false, 1>"), ("f32", "dslash_column_kernel<1, false, 1>"),
+                   ("f16s", "dslash_kernel<2, false, 1>")):
+        if p in extra:
+            row(pat, f"D apply {p}, 1 RHS", extra[p]["ms"], BYTES_SITE[p] * V, pat)
+    if "batched" in extra:
+        b = extra["batched"]
+        n = sum(b["batches"])
+        row("dslash_stationary_kernel<1, false>", f"FP32 apply, {n} RHS in batches {b['batches']}",
+            b["ms_per_launch"], (LINK_BYTES["f32"] + CLOVER_BYTES["f32"] + 192 * n) * V,
+            "dslash_stationary_kernel<1, false>")
+    for p, e in extra.get("even_odd_apply", {}).items():
+        row(f"parity kernels {p}", f"S = A_ee - H_eo A_oo^-1 H_oe, {p}, per RHS of a pair (two launches)",
+            e["ms_per_rhs_pair"], e["alg_bytes_per_site"][1] * V, None)
+    if "sap" in extra:
+        row("sap_pass_kernel<1, true, true>", "SAP cycle, FP32 4^4 blocks, 4 MR steps (two launches)",
+            extra["sap"]["ms_per_cycle"], extra["sap"]["alg_bytes_per_cycle"], "sap_pass_kernel<1, true, true>",
+            extra["sap"]["flop_per_cycle"])
+    if "differentiation" in extra:
+        d = extra["differentiation"]
+        Vf = int(np.prod(d["dims"]))
+        row("force_insert_kernel + force_link_kernel", "link derivative at 24^3x48 (two passes)",
+            d["force_kernel_ms"], (FORCE_BYTES_SITE["insert"] + FORCE_BYTES_SITE["link"]) * Vf, None)
+    return rows
+
+
+def cpu_info():
+    """CPU model and identification numbers from /proc/cpuinfo, and the CPU set this process may use."""
+    info = {"logical_cpus_in_affinity": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("model name", "vendor_id", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                info[k] = v.strip()
+    except OSError:
+        pass
+    return info
+
+
+def _oracle_threads():
+    import oracle
+    n = len(os.sched_getaffinity(0))
+    oracle.set_threads(n)
+    return oracle.num_threads()
+
+
 def cpu_baseline_run(dims, U, psi, m0, csw, target_s=3.0):
     """Oracle apply on a contiguous slab of T-slices (clover rows built first,
     outside the timed call); the slab is sized from a one-slice calibration so
     the timed apply takes about target_s seconds."""
     import oracle
+    threads = _oracle_threads()
     V = int(np.prod(dims))
     slab = int(np.prod(dims[1:]))
     s1 = np.arange(slab, dtype=np.int64)
@@ -357,26 +722,67 @@ def cpu_baseline_run(dims, U, psi, m0, csw, target_s=3.0):
     oracle.dirac_apply_sites(dims, U, psi, sites, m0, csw, clover_rows=Cs)
     dt = time.perf_counter() - t
     apps = len(sites) / (dt * V)
-    return {"value": apps, "unit": "Dirac apps/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": apps, "unit": "Dirac apps/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle apply on {nsl} of {dims[0]} T-slices ({len(sites)} of {V} sites, "
-                      f"clover rows precomputed), {dt:.2f} s, scaled to the whole lattice",
-            "cpu": _cpu_model()}
+                      f"clover rows precomputed), {dt:.2f} s, scaled to the whole lattice; threads = the "
+                      f"process's CPU affinity set, OMP_PROC_BIND=close",
+            "cpu": cpu_info()}
 
 
-def _cpu_model():
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+def oracle_fgmres_model(dims, U, m0, csw, steps, seed, full=False, restart=20):
+    """The oracle FGMRES (Algorithm 2, modified Gram-Schmidt) timed on the host.
+
+    Bounded sample (default): the oracle's own building blocks are timed at the
+    lattice size (two operator applications, and three modified Gram-Schmidt
+    inner iterations: an inner product and a vector update) and the solve is
+    extrapolated from the iteration structure the GPU solve of the same system
+    reported (applications, Arnoldi step index of every application).  With
+    full=True the oracle FGMRES runs to 1e-10 and is timed whole."""
+    import oracle
+    from paper_2407_00041_amd import synth
+    V = int(np.prod(dims))
+    b = synth.gaussian_spinor(dims, seed)
+    C = oracle.clover_term(dims, U)
+    A = lambda v: oracle.dirac_apply(dims, U, v, m0, csw, clover=C)
+    if full:
+        t = time.perf_counter()
+        _, info = oracle.fgmres(A, b, m=restart, tol=1e-10, maxit=10 * steps)
+        return {"seconds": time.perf_counter() - t, "applies": info["applies"], "extrapolated": False}
+    t = time.perf_counter()
+    w = A(b)
+    w = A(w)
+    t_apply = (time.perf_counter() - t) / 2
+    v = b / np.linalg.norm(b)
+    t = time.perf_counter()
+    for _ in range(3):
+        h = np.vdot(v.ravel(), w.ravel())
+        w = w - h * v
+    t_gs = (time.perf_counter() - t) / 3
+    # restart cycles of `restart` steps: one residual application per cycle, and step j of a cycle
+    # costs j + 1 Gram-Schmidt inner iterations
+    cycles = -(-(steps - 1) // (restart + 1))   # each ends with the next cycle's (or the final) residual
+    arnoldi = steps - cycles - 1
+    gs = 0
+    left = arnoldi
+    while left > 0:
+        k = min(restart, left)
+        gs += k * (k + 1) // 2
+        left -= k
+    est = steps * t_apply + gs * t_gs
+    return {"seconds": est, "applies": steps, "extrapolated": True, "t_apply_s": t_apply, "t_gs_inner_s": t_gs,
+            "model": f"{steps} applications x {t_apply:.3f} s + {gs} Gram-Schmidt inner iterations x {t_gs:.3f} s "
+                     f"(restart {restart}, iteration counts of the GPU solve)"}
 
 
 def main():
     global TUNE_FIXED
+    # the oracle's OpenMP threads stay on the CPUs of this process's affinity set, packed
+    os.environ.setdefault("OMP_PROC_BIND", "close")
     a = parse()
     TUNE_FIXED = bool(a.fixed_launch)
+    if a.summarize:
+        summarize_profile(*a.summarize, command=a.summary_command)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no multi-GPU "
                                    "halo exchange"}))
@@ -385,6 +791,11 @@ def main():
 
     import paper_2407_00041_amd as wd
     from paper_2407_00041_amd import synth
+
+    if a.kernel_suite:
+        torch.cuda.set_device(0)
+        kernel_suite(torch, a.kernel_suite)
+        return
 
     dims = tuple(a.dims)
     V = int(np.prod(dims))
@@ -435,13 +846,17 @@ def main():
         extra["f64"]["copy_GBps"] = copy_gbs
         extra["f64"]["alg_frac_of_copy"] = gbs / copy_gbs
         log(f"[bench] device copy {copy_gbs:.0f} GB/s; FP64 apply at {gbs / copy_gbs:.3f} of it")
+        y64 = op.unpack(out["f64"], "f64")
+        n64 = torch.linalg.vector_norm(y64)
         for p in ("f32", "f16s"):
             m = time_launches(torch, lambda: op.apply_native(out[p], inp[p], 1, p, stream=stream),
                               max(10, a.steps // 2), a.warmup, stream)
+            err = float(torch.linalg.vector_norm(op.unpack(out[p], p) - y64) / n64)
             extra[p] = {"ms": m, "apps_per_s": 1000.0 / m, "alg_GBps": BYTES_SITE[p] * V / (m * 1e-3) / 1e9,
-                        "launch": tuned[p],
-                        "GFLOPs_1320": FLOP_HOP * V / (m * 1e-3) / 1e9}
-            log(f"[bench] {p}: {m:.4f} ms/apply")
+                        "launch": tuned[p], "GFLOPs_1320": FLOP_HOP * V / (m * 1e-3) / 1e9,
+                        "rel_error_vs_fp64_apply": err}
+            log(f"[bench] {p}: {m:.4f} ms/apply, error vs FP64 {err:.2e}")
+        del y64
     if a.copy_probe:
         n = 1 << 28
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -462,6 +877,10 @@ def main():
         extra["even_odd_apply"] = schur_apply_run(torch, op, psid, stream)
         log("[bench] even-odd S: " + ", ".join(f"{p} {v['ms_single']:.3f} ms ({v['ms_per_rhs_pair']:.3f} per RHS of a "
                                                 f"pair)" for p, v in extra["even_odd_apply"].items()))
+    if not a.no_extra:
+        extra["sap"] = sap_run(torch, op, psid, stream)
+        log(f"[bench] SAP cycle (FP32, 4^4 blocks, 4 MR): {extra['sap']['ms_per_cycle']:.3f} ms, "
+            f"{extra['sap']['alg_GBps']:.0f} GB/s, {extra['sap']['TFLOPs']:.1f} TFLOP/s")
     if not a.no_extra and not a.no_fgmres and a.fgmres_rhs > 0:
         extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs)
     if not a.no_extra:
@@ -473,6 +892,8 @@ def main():
         extra["differentiation"] = differentiation_run(torch)
         log(f"[bench] 24^3x48: forward+backward {extra['differentiation']['forward_backward_ms']:.2f} ms")
 
+    if not a.no_extra:
+        extra["kernels"] = kernel_table(extra, V)
     res = {
         "metric": "Dirac apps/s & HBM GB/s; mixed vs FP64 FGMRES time to 1e-10 at 48^3x96",
         "value": apps,
@@ -504,6 +925,26 @@ def main():
         psi = psid.reshape(V, 12).cpu().numpy()
         res["cpu_baseline"] = cpu_baseline_run(dims, U, psi, a.m0, a.csw)
         log(f"[bench] cpu baseline {res['cpu_baseline']['value']:.4f} apps/s")
+        if not a.no_extra:
+            # the oracle FGMRES beside the GPU solves: FGMRES(20) at 32^4, and one right-hand side of the
+            # 48^3 x 96 FP64 FGMRES(30) run extrapolated to the 12 right-hand sides
+            c32 = extra.get("config_32", {}).get("fgmres20_fp64", {})
+            U32 = synth.smooth_links((32, 32, 32, 32), 1002, device="cuda").cpu().numpy() if c32 else None
+            if c32:
+                o32 = oracle_fgmres_model((32, 32, 32, 32), U32, -0.3, 1.0, c32["applies"], 2000, full=a.cpu_full)
+                o32["gpu_seconds"] = c32["seconds"]
+                res["cpu_baseline"]["fgmres20_32^4"] = o32
+                log(f"[bench] oracle FGMRES(20) 32^4: {o32['seconds']:.1f} s (GPU {c32['seconds']:.2f} s)")
+            del U32
+            f64 = extra.get("fgmres", {}).get("fp64")
+            if f64:
+                o48 = oracle_fgmres_model(dims, U, a.m0, a.csw, int(f64["applies"][0]), 3000, restart=30)
+                o48["rhs"] = 12
+                o48["seconds_12_rhs_extrapolated"] = 12 * o48["seconds"]
+                o48["gpu_seconds_12_rhs"] = f64["seconds"]
+                res["cpu_baseline"]["fgmres30_48^3x96"] = o48
+                log(f"[bench] oracle FGMRES(30) 48^3x96, 12 RHS (extrapolated): "
+                    f"{o48['seconds_12_rhs_extrapolated']:.0f} s (GPU {f64['seconds']:.1f} s)")
     print(json.dumps(res), flush=True)
 
 

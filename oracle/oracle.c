@@ -425,6 +425,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* thread count of the site loops (n >= 1); for timing runs pinned to a CPU set */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Link derivative of L = Re sum_x eta(x)^H (D psi)(x) (a new quantity; the
  * paper has no force).  For a link U = U_rho(y) the derivative is

@@ -224,10 +224,13 @@ class DiracOp:
               inner_tol: float = 1e-2, inner_maxit: int = 30, work: torch.Tensor | None = None, stream=None,
               graph: bool = False, wave: int = 0, schur: bool = False, sap=None):
         """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
-        "mixed_f16s", or "sap" (M_j^{-1} = SAP with the keyword arguments of sap_params in ``sap``).  ``work`` may be a reusable device buffer of at least
-        workspace_bytes(...) bytes.  ``graph``: run the inner cycles of the mixed
-        modes as captured HIP graphs.  ``wave``: solve the right-hand sides in
-        consecutive groups of this size (workspace for one group; 0 = all).
+        "mixed_f16s", or "sap" (M_j^{-1} = SAP with the keyword arguments of
+        sap_params in ``sap``).  ``work`` may be a reusable device buffer of at
+        least workspace_bytes(...) bytes.  ``graph``: run the inner cycles of the
+        mixed modes as captured HIP graphs.  ``wave``: solve the right-hand sides
+        in consecutive groups of this size (workspace for one group); 0 lets the
+        library size the groups from the free device memory, or from ``work``
+        when it is given.
         ``schur``: solve the even-odd reduced system (operator built with
         even_odd=True) and reconstruct the odd sites; tol stays relative to the
         full system's initial residual.
@@ -240,9 +243,10 @@ class DiracOp:
             raise WdiracError(-1, "fgmres_workspace_bytes")
         if work is None:
             work = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
-        elif work.numel() * work.element_size() < nbytes:
+        elif wave > 0 and work.numel() * work.element_size() < nbytes:
             raise ValueError(f"workspace of {work.numel()} bytes is smaller than {nbytes}")
         else:
+            # wave = 0 with a given workspace: the library fits as many right-hand sides per wave as it holds
             nbytes = work.numel() * work.element_size()
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         stats = (_lib.FgmresStats * int(nrhs))()
