@@ -13,6 +13,9 @@ library (no code, header, table or helper), and this package never imports it.
 - ``sap.py`` (NumPy): the Schwarz alternating procedure over non-overlapping
   lattice blocks (red-black multiplicative and additive; minimal-residual or
   exact block solves), the preconditioner of Sec. 1.3.
+- ``amg.py`` (NumPy): the two-level aggregation multigrid of Sec. 1.3
+  (test-vector setup, interpolation P, Galerkin coarse operator D_c = P^H D P,
+  coarse-grid correction followed by SAP post-smoothing).
 
 All arrays use the canonical host layouts documented in ``oracle.c``:
 spinors [..., V, 12] complex128, links [V, 4, 3, 3] complex128, packed clover
