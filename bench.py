@@ -225,6 +225,10 @@ def batched_run(torch, op, dims, stream, steps):
 
 
 SAP_DEFAULT = {"block": (4, 4, 4, 4), "cycles": 1, "mr_iters": 4, "prec": "f32"}
+# two-level multigrid preconditioner: aggregates of 4^4 sites (a 24 x 12^3 coarse lattice at 48^3 x 96), 8 test
+# vectors, SAP smoother as above, coarse GMRES(30) to 5e-2
+AMG_DEFAULT = {"agg": (4, 4, 4, 4), "ntv": 8, "init_iters": 3, "setup_iters": 1, "smoother": SAP_DEFAULT,
+               "coarse_restart": 30, "coarse_maxit": 300, "coarse_tol": 0.05}
 
 
 def solver_sweep(op, bn, configs):

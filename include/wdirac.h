@@ -305,12 +305,105 @@ int dirac_sap(const dirac_op *op, double *x, const double *b, int nrhs, const sa
               size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/*
+ * Two-level aggregation multigrid (AMG), the preconditioner Sec. 1.3
+ * outlines: a coarse operator D_c that acts like D on the near kernel (the
+ * eigenvectors of small |eigenvalue|, which the Schwarz smoother reduces
+ * poorly) and keeps D's nearest-neighbour structure, a restriction R and a
+ * prolongation P, and the subspace correction z <- z + P D_c^{-1} R r,
+ * which with the smoother approximates D z = v; the setup approximates
+ * right eigenvectors of small eigenvalues (Sec. 5.1 / Table 5.2: the
+ * coarse lattice, 24 test vectors, 4 setup iterations in the paper's runs).
+ * The paper gives no formulas; this library reads the outline as:
+ *   - aggregates of agg[0] x ... x agg[3] sites (T, Z, Y, X; each extent
+ *     divides the lattice extent); one coarse site per aggregate, coarse
+ *     sites lexicographic in the aggregate coordinates (x fastest);
+ *   - P from the N = ntv test vectors: on every (aggregate, chirality) --
+ *     chirality 0 = spins 0, 1 (gamma_5 = +1), 1 = spins 2, 3 -- the test
+ *     vectors restricted there are orthonormalised in order (Gram-Schmidt:
+ *     the Q of a QR factorisation with positive real diag(R)); column
+ *     (a, s, k) of P is the k-th of them.  R = P^H, D_c = P^H D P;
+ *   - coarse vectors: device complex128 [Vc][2][N] (coarse site, chirality,
+ *     test vector), Vc = product of the coarse extents; nrhs of them back
+ *     to back;
+ *   - M r = e + SAP(r - D e) with e = P D_c^{-1} P^H r, D_c^{-1} by GMRES
+ *     (restart coarse_restart, from 0, to |b - D_c x| <= coarse_tol |b| or
+ *     coarse_maxit applications of D_c), SAP as in dirac_sap;
+ *   - setup: init_iters passes of v_k <- SAP(v_k) / |SAP(v_k)| over the
+ *     caller's test vectors, build P and D_c; then setup_iters passes of
+ *     v_k <- M v_k / |M v_k| with the current two-level method, each
+ *     followed by a rebuild.
+ * Everything runs in FP64 except the smoother (its own precision).
+ */
+typedef struct {
+    int agg[4];            /* aggregate extents {aT, aZ, aY, aX}              */
+    int ntv;               /* test vectors N, 1..32 (2N unknowns per coarse   */
+                           /* site); at most 6 x the sites of an aggregate    */
+    int init_iters;        /* smoother passes over the test vectors (>= 0)    */
+    int setup_iters;       /* two-level passes over the test vectors (>= 0)   */
+    sap_params smoother;   /* post-smoother of M and smoother of the setup    */
+    int coarse_restart;    /* GMRES restart on D_c, 1..1000                   */
+    long long coarse_maxit;/* D_c applications per coarse solve (>= 1)        */
+    double coarse_tol;     /* relative residual of a coarse solve, (0, 1)     */
+} amg_params;
+
+typedef struct dirac_amg dirac_amg;
+
+/* what dirac_amg_export copies */
+#define WDIRAC_AMG_TEST_VECTORS 0    /* the N test vectors: N native FP64 fields          */
+#define WDIRAC_AMG_INTERPOLATION 1   /* P as N native FP64 fields q_k (q_k on (a, s) =    */
+                                     /* column (a, s, k))                                 */
+#define WDIRAC_AMG_COARSE_OPERATOR 2 /* D_c blocks: complex128 [Vc][5][2N][2N], per       */
+                                     /* coarse site its block with itself, then with its  */
+                                     /* +T, +Z, +Y, +X neighbour (rows = output unknowns  */
+                                     /* s N + k; hops gathered by direction, so a block   */
+                                     /* to a neighbour that is also the -mu neighbour     */
+                                     /* holds the +mu hops only; zero where one aggregate */
+                                     /* spans the direction); the -mu blocks follow from  */
+                                     /* D_c[a, a - mu] = G5 D_c[a - mu, a]^H G5, G5 = +1  */
+                                     /* on chirality 0 and -1 on chirality 1              */
+
+/*
+ * Run the setup and create the two-level method for `op` (which must hold
+ * the FP64 operator and the smoother's precision).  testvecs: device, N
+ * native FP64 fields, the initial test vectors (drawn by the caller, e.g.
+ * Gaussian); copied, the caller keeps ownership.  The handle owns its
+ * device memory (2N fields for test vectors and P, D_c, the coarse GMRES
+ * basis and two fine temporaries) and a small pinned staging buffer, and
+ * keeps a pointer to `op`, which must outlive it.  Blocks until the setup
+ * is done.  Calls that use one handle must not overlap (they share its
+ * workspace).  Errors: EINVAL (parameters, test vectors dependent on some
+ * aggregate), ENOMEM, EUNSUPPORTED (precision not materialised), EHIP.
+ */
+int dirac_amg_create(dirac_amg **amg, const dirac_op *op, const amg_params *p, const double *testvecs,
+                     void *stream);
+int dirac_amg_destroy(dirac_amg *amg);
+/* Coarse extents, unknowns per coarse site (2N) and, in coarse_stats when not
+ * NULL, {coarse solves, D_c applications} since create. */
+int dirac_amg_sizes(const dirac_amg *amg, int coarse_dims[4], int *unknowns_per_site, long long *coarse_stats);
+/* coarse = P^H fine (nrhs native FP64 fields -> nrhs coarse vectors).  Asynchronous. */
+int dirac_amg_restrict(const dirac_amg *amg, double *coarse, const double *fine, int nrhs, void *stream);
+/* fine = P coarse.  Asynchronous. */
+int dirac_amg_prolong(const dirac_amg *amg, double *fine, const double *coarse, int nrhs, void *stream);
+/* out = D_c in (coarse vectors; out must not overlap in).  Asynchronous. */
+int dirac_amg_coarse_apply(const dirac_amg *amg, double *out, const double *in, int nrhs, void *stream);
+/* x = D_c^{-1} b by the coarse GMRES of M (one coarse vector); iters (may be
+ * NULL) = D_c applications.  Blocking. */
+int dirac_amg_coarse_solve(const dirac_amg *amg, double *x, const double *b, long long *iters, void *stream);
+/* z = M r for nrhs native FP64 fields (z must not overlap r).  Blocking. */
+int dirac_amg_precond(const dirac_amg *amg, double *z, const double *r, int nrhs, void *stream);
+/* Copy the test vectors, P or D_c (WDIRAC_AMG_*) into device memory at out. */
+int dirac_amg_export(const dirac_amg *amg, int what, double *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* FGMRES (Algorithm 2, Sec. 1.2) for D x = b.                               */
 
 #define FGMRES_F64 0        /* plain FP64 FGMRES(restart), no preconditioner */
 #define FGMRES_MIXED_F32 1  /* FP64 outer FGMRES, inner GMRES on FP32 D     */
 #define FGMRES_MIXED_F16S 2 /* FP64 outer FGMRES, inner GMRES on FP16S D    */
 #define FGMRES_SAP 3        /* FP64 FGMRES, M_j^{-1} = SAP (fgmres_params.sap) */
+#define FGMRES_AMG 4        /* FP64 FGMRES, M_j^{-1} = the two-level method   */
+                            /* of fgmres_params.amg                            */
 
 typedef struct {
     int restart;        /* outer Krylov dimension m (>= 1)                   */
@@ -340,6 +433,10 @@ typedef struct {
                         /* (not with FGMRES_SAP)                             */
     sap_params sap;     /* FGMRES_SAP: the preconditioner's SAP; its work is */
                         /* part of the solver's workspace                    */
+    const dirac_amg *amg; /* FGMRES_AMG: the two-level preconditioner (made  */
+                        /* by dirac_amg_create for the same operator; its    */
+                        /* own workspace is used, one right-hand side at a   */
+                        /* time; full system only)                           */
 } fgmres_params;
 
 #define FGMRES_HIST_MAX 4096

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import (ANTIPERIODIC_T, COMPRESS_CLOVER, COMPRESS_LINKS, EVEN_ODD, EUNSUPPORTED, F16S, F32, F64,  # noqa: F401
-                   ENONFINITE, ENOTCONV, FGMRES_F64, FGMRES_SAP,
+                   ENONFINITE, ENOTCONV, FGMRES_AMG, FGMRES_F64, FGMRES_SAP,
                    FGMRES_MIXED_F16S, FGMRES_MIXED_F32, WITH_F16, WITH_F32, WdiracError, check)
 
 PRECS = {"f64": F64, "f32": F32, "f16s": F16S}
@@ -202,18 +202,18 @@ class DiracOp:
 
     @classmethod
     def _params(cls, restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph=False, wave=0,
-                schur=False, sap=None):
+                schur=False, sap=None, amg=None):
         modes = {"f64": FGMRES_F64, "mixed_f32": FGMRES_MIXED_F32, "mixed_f16s": FGMRES_MIXED_F16S,
-                 "sap": FGMRES_SAP}
+                 "sap": FGMRES_SAP, "amg": FGMRES_AMG}
         sp = cls.sap_params(**(sap or {}))
         return _lib.FgmresParams(int(restart), float(tol), int(maxit),
                                  modes[mode] if isinstance(mode, str) else int(mode),
                                  int(inner_restart), float(inner_tol), int(inner_maxit), int(bool(graph)), int(wave),
-                                 int(bool(schur)), sp)
+                                 int(bool(schur)), sp, amg.handle if amg is not None else None)
 
     def workspace_bytes(self, nrhs: int = 1, restart: int = 20, mode="f64", inner_restart: int = 30,
-                        wave: int = 0, schur: bool = False, sap=None) -> int:
-        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave, schur=schur, sap=sap)
+                        wave: int = 0, schur: bool = False, sap=None, amg=None) -> int:
+        p = self._params(restart, 1e-10, 1, mode, inner_restart, 1e-2, 1, wave=wave, schur=schur, sap=sap, amg=amg)
         n = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if n == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
@@ -222,7 +222,7 @@ class DiracOp:
     def solve(self, b: torch.Tensor, nrhs: int = 1, x0: torch.Tensor | None = None, restart: int = 20,
               tol: float = 1e-10, maxit: int = 10000, mode="f64", inner_restart: int = 30,
               inner_tol: float = 1e-2, inner_maxit: int = 30, work: torch.Tensor | None = None, stream=None,
-              graph: bool = False, wave: int = 0, schur: bool = False, sap=None):
+              graph: bool = False, wave: int = 0, schur: bool = False, sap=None, amg=None):
         """FGMRES for D x = b (b native FP64, nrhs fields).  mode: "f64", "mixed_f32",
         "mixed_f16s", or "sap" (M_j^{-1} = SAP with the keyword arguments of
         sap_params in ``sap``).  ``work`` may be a reusable device buffer of at
@@ -234,10 +234,12 @@ class DiracOp:
         ``schur``: solve the even-odd reduced system (operator built with
         even_odd=True) and reconstruct the odd sites; tol stays relative to the
         full system's initial residual.
+        ``amg``: a TwoLevel of this operator, the preconditioner of mode "amg".
         Returns (x native FP64, per-RHS stats dicts, status); status is
         ENONFINITE when a right-hand side met NaN/Inf (its stats say
         ``nonfinite``), ENOTCONV when one reached maxit."""
-        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur, sap)
+        p = self._params(restart, tol, maxit, mode, inner_restart, inner_tol, inner_maxit, graph, wave, schur, sap,
+                         amg)
         nbytes = int(self.lib.fgmres_workspace_bytes(self.handle, ctypes.byref(p), int(nrhs)))
         if nbytes == 0:
             raise WdiracError(-1, "fgmres_workspace_bytes")
@@ -290,6 +292,100 @@ class DiracOp:
         work = torch.empty(max(nb, 1), dtype=torch.uint8, device=x.device)
         check(self.lib.dirac_force(self.handle, _ptr(out), _ptr(eta), _ptr(x), int(nrhs), int(bool(raw)),
                                    _ptr(work), nb, _stream(stream)), "dirac_force")
+        return out
+
+
+class TwoLevel:
+    """The two-level multigrid of an operator (dirac_amg_*): setup at
+    construction from the caller's initial test vectors (device, native FP64,
+    ntv fields), then restriction, prolongation, the coarse operator, the
+    coarse solve and the preconditioner M.  ``smoother`` holds sap_params
+    keywords."""
+
+    def __init__(self, op: DiracOp, testvecs: torch.Tensor, agg=(4, 4, 4, 4), ntv: int = 8, init_iters: int = 3,
+                 setup_iters: int = 1, smoother=None, coarse_restart: int = 30, coarse_maxit: int = 1000,
+                 coarse_tol: float = 0.05, stream=None):
+        self.lib = _lib.load()
+        self.op = op
+        self.N = int(ntv)
+        sp = DiracOp.sap_params(**(smoother or {}))
+        self.params = _lib.AmgParams((ctypes.c_int * 4)(*[int(a) for a in agg]), self.N, int(init_iters),
+                                     int(setup_iters), sp, int(coarse_restart), int(coarse_maxit), float(coarse_tol))
+        h = ctypes.c_void_p()
+        check(self.lib.dirac_amg_create(ctypes.byref(h), op.handle, ctypes.byref(self.params), _ptr(testvecs),
+                                        _stream(stream)), "dirac_amg_create")
+        self.handle = h
+        cd = (ctypes.c_int * 4)()
+        nu = ctypes.c_int()
+        check(self.lib.dirac_amg_sizes(self.handle, cd, ctypes.byref(nu), None), "dirac_amg_sizes")
+        self.coarse_dims = tuple(int(c) for c in cd)
+        self.Vc = int(np.prod(self.coarse_dims))
+        self.unknowns = int(nu.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dirac_amg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        st = (ctypes.c_longlong * 2)()
+        check(self.lib.dirac_amg_sizes(self.handle, None, None, st), "dirac_amg_sizes")
+        return {"coarse_solves": int(st[0]), "coarse_applies": int(st[1])}
+
+    def empty_coarse(self, nrhs: int = 1, device="cuda") -> torch.Tensor:
+        """Coarse vectors [nrhs, Vc, 2, N] complex128."""
+        return torch.empty((int(nrhs), self.Vc, 2, self.N), dtype=torch.complex128, device=device)
+
+    def restrict(self, fine: torch.Tensor, nrhs: int = 1, stream=None) -> torch.Tensor:
+        out = self.empty_coarse(nrhs, fine.device)
+        check(self.lib.dirac_amg_restrict(self.handle, _ptr(out), _ptr(fine), int(nrhs), _stream(stream)),
+              "dirac_amg_restrict")
+        return out
+
+    def prolong(self, coarse: torch.Tensor, nrhs: int = 1, stream=None) -> torch.Tensor:
+        out = self.op.empty("f64", nrhs, coarse.device)
+        check(self.lib.dirac_amg_prolong(self.handle, _ptr(out), _ptr(coarse.contiguous()), int(nrhs),
+                                         _stream(stream)), "dirac_amg_prolong")
+        return out
+
+    def coarse_apply(self, coarse: torch.Tensor, nrhs: int = 1, stream=None) -> torch.Tensor:
+        x = coarse.contiguous()
+        out = torch.empty_like(x)
+        check(self.lib.dirac_amg_coarse_apply(self.handle, _ptr(out), _ptr(x), int(nrhs), _stream(stream)),
+              "dirac_amg_coarse_apply")
+        return out
+
+    def coarse_solve(self, b: torch.Tensor, stream=None):
+        bb = b.contiguous()
+        x = torch.empty_like(bb)
+        it = ctypes.c_longlong()
+        check(self.lib.dirac_amg_coarse_solve(self.handle, _ptr(x), _ptr(bb), ctypes.byref(it), _stream(stream)),
+              "dirac_amg_coarse_solve")
+        return x, int(it.value)
+
+    def precond(self, r: torch.Tensor, nrhs: int = 1, stream=None) -> torch.Tensor:
+        z = torch.empty_like(r)
+        check(self.lib.dirac_amg_precond(self.handle, _ptr(z), _ptr(r), int(nrhs), _stream(stream)),
+              "dirac_amg_precond")
+        return z
+
+    def export(self, what: str, stream=None) -> torch.Tensor:
+        """"test_vectors" / "interpolation" (ntv native FP64 fields) or "coarse_operator"
+        ([Vc, 5, 2N, 2N] complex128)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if what == "coarse_operator":
+            out = torch.empty((self.Vc, 5, 2 * self.N, 2 * self.N), dtype=torch.complex128, device=dev)
+            code = _lib.AMG_COARSE_OPERATOR
+        else:
+            out = self.op.empty("f64", self.N, dev)
+            code = _lib.AMG_TEST_VECTORS if what == "test_vectors" else _lib.AMG_INTERPOLATION
+        check(self.lib.dirac_amg_export(self.handle, code, _ptr(out), _stream(stream)), "dirac_amg_export")
         return out
 
 

@@ -14,7 +14,8 @@ SO_PATH = os.path.join(HERE, "libwdirac.so")
 F64, F32, F16S = 0, 1, 2
 ANTIPERIODIC_T, WITH_F32, WITH_F16, COMPRESS_LINKS, COMPRESS_CLOVER, EVEN_ODD = 1, 2, 4, 8, 16, 32
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, 1, 2
-FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S, FGMRES_SAP = 0, 1, 2, 3
+FGMRES_F64, FGMRES_MIXED_F32, FGMRES_MIXED_F16S, FGMRES_SAP, FGMRES_AMG = 0, 1, 2, 3, 4
+AMG_TEST_VECTORS, AMG_INTERPOLATION, AMG_COARSE_OPERATOR = 0, 1, 2
 FGMRES_HIST_MAX = 4096
 
 _P = ctypes.c_void_p
@@ -29,10 +30,16 @@ class SapParams(ctypes.Structure):
     _fields_ = [("block", _I * 4), ("cycles", _I), ("mr_iters", _I), ("additive", _I), ("prec", _I)]
 
 
+class AmgParams(ctypes.Structure):
+    _fields_ = [("agg", _I * 4), ("ntv", _I), ("init_iters", _I), ("setup_iters", _I), ("smoother", SapParams),
+                ("coarse_restart", _I), ("coarse_maxit", ctypes.c_longlong), ("coarse_tol", ctypes.c_double)]
+
+
 class FgmresParams(ctypes.Structure):
     _fields_ = [("restart", _I), ("tol", ctypes.c_double), ("maxit", ctypes.c_longlong),
                 ("mode", _I), ("inner_restart", _I), ("inner_tol", ctypes.c_double),
-                ("inner_maxit", _I), ("graph", _I), ("wave", _I), ("schur", _I), ("sap", SapParams)]
+                ("inner_maxit", _I), ("graph", _I), ("wave", _I), ("schur", _I), ("sap", SapParams),
+                ("amg", _P)]
 
 
 class FgmresStats(ctypes.Structure):
@@ -76,6 +83,15 @@ SIGNATURES = {
     "dirac_schur_prepare": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
     "dirac_schur_reconstruct": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_force": (_I, [_P, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),
+    "dirac_amg_create": (_I, [ctypes.POINTER(_P), _P, ctypes.POINTER(AmgParams), _P, _P]),
+    "dirac_amg_destroy": (_I, [_P]),
+    "dirac_amg_sizes": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_longlong)]),
+    "dirac_amg_restrict": (_I, [_P, _P, _P, _I, _P]),
+    "dirac_amg_prolong": (_I, [_P, _P, _P, _I, _P]),
+    "dirac_amg_coarse_apply": (_I, [_P, _P, _P, _I, _P]),
+    "dirac_amg_coarse_solve": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_longlong), _P]),
+    "dirac_amg_precond": (_I, [_P, _P, _P, _I, _P]),
+    "dirac_amg_export": (_I, [_P, _I, _P, _P]),
 }
 
 _lib = None

@@ -48,6 +48,7 @@
 #include <string>
 #include <vector>
 
+#include "amg.h"
 #include "blas.h"
 #include "dslash.h"
 #include "sap.h"
@@ -565,6 +566,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
           pinned_n};
     const bool mixed = is_mixed(p->mode);          // preconditioner = inner GMRES
     const bool sapm = p->mode == FGMRES_SAP;       // preconditioner = SAP
+    const bool amgm = p->mode == FGMRES_AMG;       // preconditioner = two-level multigrid
     SapGeom sg{};
     if (sapm) {
         const int rc = sap_geometry(op, &p->sap, sg);
@@ -596,7 +598,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
         for (int i = 0; i <= m; i++) r.V.push_back(take(L.f64));
         r.w = reinterpret_cast<double2 *>(take(L.f64));
-        if (mixed || sapm) {
+        if (mixed || sapm || amgm) {
             for (int i = 0; i < m; i++) r.Z.push_back(take(L.f64));
             const size_t fi = p->mode == FGMRES_MIXED_F32 ? L.f32 : L.f16;
             if (mixed)
@@ -681,6 +683,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                 WD_TRY(sap_apply(op, p->sap, sg, static_cast<double2 *>(r->Z[r->outer.j]),
                                  static_cast<const double2 *>(r->V[r->outer.j]), 1, r->sapw,
                                  1.0 / r->cw[r->outer.j], c.st));
+        if (amgm)
+            for (Rhs *r : arn) {
+                const int rc = amg_precond_one(p->amg, static_cast<double2 *>(r->Z[r->outer.j]),
+                                               static_cast<const double2 *>(r->V[r->outer.j]),
+                                               1.0 / r->cw[r->outer.j], c.st);
+                if (rc) return rc;
+            }
         WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (restart residuals and Arnoldi products)
         std::vector<ApplyItem> bat;
@@ -879,8 +888,13 @@ static int check_params(const dirac_op *op, const fgmres_params *p) {
     if (!(p->tol > 0.0)) return fail(WDIRAC_EINVAL, "tol must be > 0");
     if (p->maxit < 1) return fail(WDIRAC_EINVAL, "maxit must be >= 1");
     if (p->mode != FGMRES_F64 && p->mode != FGMRES_MIXED_F32 && p->mode != FGMRES_MIXED_F16S &&
-        p->mode != FGMRES_SAP)
+        p->mode != FGMRES_SAP && p->mode != FGMRES_AMG)
         return fail(WDIRAC_EINVAL, "unknown solver mode");
+    if (p->mode == FGMRES_AMG) {
+        if (!p->amg) return fail(WDIRAC_EINVAL, "FGMRES_AMG needs fgmres_params.amg");
+        if (p->amg->op != op) return fail(WDIRAC_EINVAL, "the AMG was made for another operator");
+        if (p->schur) return fail(WDIRAC_EUNSUPPORTED, "the AMG preconditioner works on the full system only");
+    }
     if (p->mode == FGMRES_SAP) {
         if (p->schur) return fail(WDIRAC_EUNSUPPORTED, "the SAP preconditioner works on the full system only");
         SapGeom sg;

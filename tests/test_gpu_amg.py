@@ -1,0 +1,261 @@
+"""The two-level multigrid on the GPU (dirac_amg_*) against the oracle's
+(oracle/amg.py): interpolation, restriction, prolongation, the Galerkin
+coarse operator and its apply (coarse extents 1, 2 and > 2, anti-periodic T,
+compressed operator storage), the coarse GMRES, the preconditioner M, the
+setup iterations, FGMRES with M (apply counts and the oracle's true
+residual), the exact-inverse case of single-site aggregates, argument
+errors, and the 48^3 x 96 benchmark configuration (coarse operator columns at
+sampled coarse sites from the oracle operator, and the solve's true residual
+over the whole lattice)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import amg as oamg
+from paper_2407_00041_amd import DiracOp, TwoLevel, WdiracError, synth
+from util import need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def make(dims, agg, N, seed, ap=False, compress=False, init=0, setup=0, ctol=1e-12, sap_block=(2, 2, 2, 2),
+         sap_prec="f64", m0=-0.3, csw=1.0):
+    U = synth.smooth_links(dims, seed).numpy()
+    T = synth.gaussian_spinor(dims, seed + 1, nrhs=N)
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32"), antiperiodic_t=ap, compress_links=compress,
+                 compress_clover=compress)
+    tv = op.pack(to_dev(T), "f64")
+    mg = TwoLevel(op, tv, agg=agg, ntv=N, init_iters=init, setup_iters=setup,
+                  smoother=dict(block=sap_block, cycles=1, mr_iters=4, prec=sap_prec), coarse_restart=30,
+                  coarse_maxit=20000, coarse_tol=ctol)
+    return U, T, op, mg
+
+
+# lattice, aggregates, test vectors, anti-periodic T, compressed operator storage, SAP blocks of the smoother
+CASES = [((4, 4, 4, 4), (2, 2, 2, 2), 8, False, False, (2, 2, 2, 2)),  # coarse extents 2: +mu, -mu coincide
+         ((8, 4, 6, 4), (2, 2, 3, 2), 6, True, True, (2, 2, 3, 2)),     # coarse T extent 4, anti-periodic
+         ((4, 6, 4, 8), (4, 3, 2, 2), 5, False, True, (2, 3, 2, 2))]    # coarse T extent 1 (one aggregate spans T)
+
+
+@pytest.mark.parametrize("dims,agg,N,ap,compress,sap_block", CASES)
+def test_interpolation_and_coarse_operator_match_oracle(dims, agg, N, ap, compress, sap_block):
+    need_gpu()
+    U, T, op, mg = make(dims, agg, N, 60, ap=ap, compress=compress, sap_block=sap_block)
+    tl = oamg.TwoLevel(dims, U, -0.3, 1.0, agg, T, antiperiodic_t=ap)
+    assert mg.coarse_dims == tl.cdims and mg.unknowns == 2 * N
+    q = op.unpack(mg.export("interpolation"), "f64", N).cpu().numpy()
+    assert rel(q, tl.q) < 1e-12
+    assert rel(op.unpack(mg.export("test_vectors"), "f64", N).cpu().numpy(), T) < 1e-15
+    f = synth.gaussian_spinor(dims, 61, nrhs=2)
+    c = mg.restrict(op.pack(to_dev(f), "f64"), 2).cpu().numpy()
+    for r in range(2):
+        assert rel(c[r], tl.restrict(f[r])) < 1e-12
+    cr = synth.gaussian_spinor((1, 1, 1, tl.Vc * 2 * N), 62, nrhs=2).reshape(2, -1)[:, :tl.Vc * 2 * N]
+    cr = cr.reshape(2, tl.Vc, 2, N)
+    pf = op.unpack(mg.prolong(to_dev(cr), 2), "f64", 2).cpu().numpy()
+    ya = mg.coarse_apply(to_dev(cr), 2).cpu().numpy()
+    for r in range(2):
+        assert rel(pf[r], tl.prolong(cr[r])) < 1e-12
+        assert rel(ya[r], tl.coarse_apply(cr[r])) < 1e-12
+    # stored blocks: the self block always equals the dense diagonal block; a forward block equals the dense
+    # block to the +mu neighbour where that neighbour is not also the -mu one
+    Dc = tl.coarse_matrix()
+    n2 = 2 * N
+    blocks = mg.export("coarse_operator").cpu().numpy()
+    nc = tl.cdims
+    for a in range(tl.Vc):
+        assert rel(blocks[a, 0], Dc[a * n2:(a + 1) * n2, a * n2:(a + 1) * n2]) < 1e-12
+        ca = np.unravel_index(a, nc)
+        for mu in range(4):
+            if nc[mu] >= 3:
+                cb = list(ca)
+                cb[mu] = (cb[mu] + 1) % nc[mu]
+                b = np.ravel_multi_index(cb, nc)
+                assert rel(blocks[a, 1 + mu], Dc[a * n2:(a + 1) * n2, b * n2:(b + 1) * n2]) < 1e-12
+            elif nc[mu] == 1:
+                assert not blocks[a, 1 + mu].any()
+    mg.close()
+    op.close()
+
+
+def test_coarse_solve_and_preconditioner_match_oracle():
+    need_gpu()
+    dims, agg, N = (4, 4, 4, 8), (2, 2, 2, 2), 6
+    U, T, op, mg = make(dims, agg, N, 63)
+    tl = oamg.TwoLevel(dims, U, -0.3, 1.0, agg, T, sap_block=(2, 2, 2, 2), sap_cycles=1, sap_mr=4)
+    rc = synth.gaussian_spinor((1, 1, 1, tl.Vc * 2 * N), 64).reshape(-1)[:tl.Vc * 2 * N].reshape(tl.Vc, 2, N)
+    x, it = mg.coarse_solve(to_dev(rc))
+    assert it > 0
+    assert rel(x.cpu().numpy(), tl.coarse_solve(rc)) < 1e-10
+    r = synth.gaussian_spinor(dims, 65, nrhs=2)
+    z = op.unpack(mg.precond(op.pack(to_dev(r), "f64"), 2), "f64", 2).cpu().numpy()
+    for k in range(2):
+        assert rel(z[k], tl.precond(r[k])) < 1e-9
+    st = mg.stats()
+    assert st["coarse_solves"] == 3 and st["coarse_applies"] >= it
+    mg.close()
+    op.close()
+
+
+def test_setup_iterations_match_oracle():
+    """init_iters SAP passes and setup_iters two-level passes over the test vectors, FP64 smoother, tight
+    coarse solves: the test vectors and P after the setup equal the oracle's."""
+    need_gpu()
+    dims, agg, N = (4, 4, 4, 4), (2, 2, 2, 2), 6
+    U, T, op, mg = make(dims, agg, N, 66, init=2, setup=1)
+    tl = oamg.setup(dims, U, -0.3, 1.0, agg, T, init_iters=2, setup_iters=1, sap_block=(2, 2, 2, 2),
+                    sap_cycles=1, sap_mr=4)
+    assert rel(op.unpack(mg.export("test_vectors"), "f64", N).cpu().numpy(), tl.test) < 1e-9
+    assert rel(op.unpack(mg.export("interpolation"), "f64", N).cpu().numpy(), tl.q) < 1e-9
+    mg.close()
+    op.close()
+
+
+def test_fgmres_with_two_level_preconditioner_matches_oracle():
+    need_gpu()
+    dims, agg, N = (8, 8, 8, 8), (4, 4, 4, 4), 8
+    m0 = -0.4
+    U, T, op, mg = make(dims, agg, N, 67, init=3, setup=1, m0=m0)
+    tl = oamg.setup(dims, U, m0, 1.0, agg, T, init_iters=3, setup_iters=1, sap_block=(2, 2, 2, 2), sap_cycles=1,
+                    sap_mr=4)
+    b = synth.gaussian_spinor(dims, 68)
+    bn = op.pack(to_dev(b), "f64")
+    x, st, rc = op.solve(bn, restart=20, tol=1e-10, maxit=500, mode="amg", amg=mg)
+    assert rc == 0 and st[0]["converged"], st[0]
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    assert rel(oracle.dirac_apply(dims, U, xg, m0, 1.0), b) <= 1.01e-10
+    xo, info = oracle.fgmres(tl.D, b, m=20, tol=1e-10, maxit=500, precond=lambda v, j: tl.precond(v))
+    assert abs(st[0]["applies"] - info["applies"]) <= 2, (st[0]["applies"], info["applies"])
+    _, st0, _ = op.solve(bn, restart=20, tol=1e-10, maxit=5000)
+    assert st[0]["applies"] < st0[0]["applies"] / 3, (st[0]["applies"], st0[0]["applies"])
+    mg.close()
+    op.close()
+
+
+def test_single_site_aggregates_make_fgmres_exact():
+    """Aggregates of one site with 6 test vectors: P is unitary, M = D^{-1} up to the coarse tolerance, and
+    FGMRES stops after one Arnoldi step (three operator applications), the optimal preconditioner of Sec. 1.3."""
+    need_gpu()
+    dims = (2, 2, 2, 4)
+    U, T, op, mg = make(dims, (1, 1, 1, 1), 6, 69, ctol=1e-13)
+    b = synth.gaussian_spinor(dims, 70)
+    x, st, rc = op.solve(op.pack(to_dev(b), "f64"), restart=10, tol=1e-10, maxit=50, mode="amg", amg=mg)
+    assert rc == 0 and st[0]["converged"] and st[0]["applies"] == 3, st[0]
+    mg.close()
+    op.close()
+
+
+def test_amg_argument_errors():
+    need_gpu()
+    dims = (4, 4, 4, 4)
+    U = synth.smooth_links(dims, 71).numpy()
+    op = DiracOp(dims, U, -0.3, 1.0, precisions=("f64",))
+    T = synth.gaussian_spinor(dims, 72, nrhs=4)
+    tv = op.pack(to_dev(T), "f64")
+    sm = dict(block=(2, 2, 2, 2), prec="f64")
+    for kw in (dict(agg=(3, 2, 2, 2)), dict(ntv=33), dict(agg=(1, 1, 1, 1), ntv=7), dict(coarse_tol=0.0),
+               dict(coarse_restart=0)):
+        args = dict(agg=(2, 2, 2, 2), ntv=4, smoother=sm)
+        args.update(kw)
+        with pytest.raises(WdiracError) as e:
+            TwoLevel(op, tv, init_iters=0, setup_iters=0, **args)
+        assert e.value.code == -1, kw
+    with pytest.raises(WdiracError) as e:   # f32 smoother on an FP64-only operator
+        TwoLevel(op, tv, agg=(2, 2, 2, 2), ntv=4, smoother=dict(block=(2, 2, 2, 2), prec="f32"))
+    assert e.value.code == -4
+    dup = T.copy()
+    dup[1] = 2.0 * dup[0]
+    with pytest.raises(WdiracError) as e:
+        TwoLevel(op, op.pack(to_dev(dup), "f64"), agg=(2, 2, 2, 2), ntv=4, init_iters=0, setup_iters=0, smoother=sm)
+    assert e.value.code == -1 and "dependent" in str(e.value)
+    mg = TwoLevel(op, tv, agg=(2, 2, 2, 2), ntv=4, init_iters=0, setup_iters=0, smoother=sm)
+    bn = op.pack(to_dev(synth.gaussian_spinor(dims, 73)), "f64")
+    with pytest.raises(WdiracError) as e:
+        op.solve(bn, mode="amg")
+    assert e.value.code == -1
+    other = DiracOp(dims, U, -0.3, 1.0, precisions=("f64",), even_odd=True)
+    with pytest.raises(WdiracError) as e:
+        other.solve(other.pack(to_dev(synth.gaussian_spinor(dims, 73)), "f64"), mode="amg", amg=mg)
+    assert e.value.code == -1 and "another operator" in str(e.value)
+    mg2 = TwoLevel(other, other.pack(to_dev(T), "f64"), agg=(2, 2, 2, 2), ntv=4, init_iters=0, setup_iters=0,
+                   smoother=sm)
+    with pytest.raises(WdiracError) as e:
+        other.solve(other.pack(to_dev(synth.gaussian_spinor(dims, 73)), "f64"), mode="amg", amg=mg2, schur=True)
+    assert "full system only" in str(e.value)
+    mg.close()
+    mg2.close()
+    other.close()
+    op.close()
+
+
+def test_full_size_amg_bench_configuration():
+    """48^3 x 96, c_sw = 1, m0 = -0.35, two-row links and compact clover, the benchmark's two-level setup:
+    (1) D_c applied to unit coarse vectors at three sampled coarse sites equals P^H D P computed with the
+    oracle operator on the affected aggregates; (2) FGMRES with M reaches 1e-10, checked by the oracle's
+    residual over the whole lattice."""
+    need_gpu()
+    from bench import AMG_DEFAULT
+    dims = (96, 48, 48, 48)
+    m0, csw = -0.35, 1.0
+    Ud = synth.smooth_links(dims, 1004, device="cuda")
+    U = Ud.cpu().numpy()
+    del Ud
+    op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32"), compress_links=True, compress_clover=True)
+    N = AMG_DEFAULT["ntv"]
+    tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=N, device="cuda"), "f64")
+    mg = TwoLevel(op, tv, **AMG_DEFAULT)
+    del tv
+    agg = AMG_DEFAULT["agg"]
+    nc = mg.coarse_dims
+    q = op.unpack(mg.export("interpolation"), "f64", N)          # [N, V, 12] on the device
+    rng = np.random.default_rng(74)
+    for a in rng.choice(mg.Vc, 3, replace=False):
+        ca = np.array(np.unravel_index(a, nc))
+        nbrs = [a]
+        for mu in range(4):
+            for d in (1, -1):
+                cb = ca.copy()
+                cb[mu] = (cb[mu] + d) % nc[mu]
+                nbrs.append(int(np.ravel_multi_index(cb, nc)))
+        nbrs = sorted(set(nbrs))
+
+        def sites_of(b):
+            cb = np.array(np.unravel_index(b, nc))
+            loc = np.stack(np.meshgrid(*[np.arange(x) for x in agg], indexing="ij"), -1).reshape(-1, 4)
+            c = cb * np.array(agg) + loc
+            return ((c[:, 0] * dims[1] + c[:, 1]) * dims[2] + c[:, 2]) * dims[3] + c[:, 3]
+
+        for col in rng.choice(2 * N, 2, replace=False):
+            e = torch.zeros((1, mg.Vc, 2, N), dtype=torch.complex128, device="cuda")
+            e[0, a, col // N, col % N] = 1.0
+            got = mg.coarse_apply(e).cpu().numpy()[0]
+            # oracle: f = P e (supported on aggregate a), D f at the sites of a and its neighbours, then P^H there
+            sa = sites_of(a)
+            f = np.zeros((op.V, 12), np.complex128)
+            comps = np.arange(6) + 6 * (col // N)
+            f[np.ix_(sa, comps)] = q[col % N][torch.from_numpy(sa).cuda()][:, comps].cpu().numpy()
+            for b in nbrs:
+                sb = sites_of(b)
+                Df = oracle.dirac_apply_sites(dims, U, f, sb, m0, csw)
+                qb = q[:, torch.from_numpy(sb).cuda()].cpu().numpy()       # [N, n_a, 12]
+                want = np.stack([np.einsum("kic,ic->k", qb[:, :, 6 * s:6 * s + 6].conj(), Df[:, 6 * s:6 * s + 6])
+                                 for s in range(2)])
+                assert rel(got[b], want) < 1e-11, (a, col, b)
+    del q, f
+    torch.cuda.empty_cache()
+    bd = synth.gaussian_spinor(dims, 2400, nrhs=1, device="cuda")
+    x, st, rc = op.solve(op.pack(bd, "f64"), restart=20, tol=1e-10, maxit=500, mode="amg", amg=mg)
+    assert rc == 0 and st[0]["converged"], st[0]
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    del x
+    mg.close()
+    op.close()
+    torch.cuda.empty_cache()
+    r = bd.cpu().numpy()[0] - oracle.dirac_apply(dims, U, xg, m0, csw)
+    assert np.linalg.norm(r) / np.linalg.norm(bd.cpu().numpy()[0]) <= 1.01e-10
