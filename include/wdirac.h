@@ -531,6 +531,22 @@ int dirac_parity_merge(const dirac_op *op, void *full, const void *even, const v
  * A_oo^{-1} H_oe in).  out, tmp and in must not overlap. */
 int dirac_apply_schur(const dirac_op *op, void *out, const void *in, void *tmp, int nrhs, int prec, int dagger,
                       void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out = S in (or S^H in) as dirac_apply_schur, with the odd-parity
+ * intermediate A_oo^{-1} H_oe in kept in a static device array of the
+ * library (128 MiB per device, held until the process ends) instead of a
+ * caller's tmp.  nrhs odd fields must fit in it: at most 134217728 bytes of
+ * dirac_parity_field_bytes(op, prec, nrhs), i.e. about 1.4 M lattice sites
+ * per FP64 right-hand side; larger requests fail with EINVAL.  Calls no
+ * allocating routine (device, pinned or host).  Every call on one device
+ * shares that scratch, so calls that overlap on a device (concurrent
+ * streams or threads) race; the scratch keeps the last call's values.
+ * Results are bit-identical to dirac_apply_schur.  Errors as for
+ * dirac_apply_schur, plus EHIP when the scratch was not set up (the
+ * operator's create resolves it on its device). */
+int dirac_apply_schur_noalloc(const dirac_op *op, void *out, const void *in, int nrhs, int prec, int dagger,
+                              void *stream);
 /* bhat = b_even - H_eo A_oo^{-1} b_odd (the reduced right-hand side); tmp:
  * nrhs odd fields receiving A_oo^{-1} b_odd (may be b_odd itself, must not
  * overlap b_even); bhat may be b_even itself and must not overlap tmp. */

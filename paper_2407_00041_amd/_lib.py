@@ -80,6 +80,7 @@ SIGNATURES = {
     "dirac_parity_split": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_parity_merge": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_apply_schur": (_I, [_P, _P, _P, _P, _I, _I, _I, _P]),
+    "dirac_apply_schur_noalloc": (_I, [_P, _P, _P, _I, _I, _I, _P]),
     "dirac_schur_prepare": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
     "dirac_schur_reconstruct": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "dirac_force": (_I, [_P, _P, _P, _P, _I, _I, _P, ctypes.c_size_t, _P]),

@@ -240,6 +240,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
     if (cc) (void)hipFree(cc);
     if (ic) (void)hipFree(ic);
     if (bad) (void)hipFree(bad);
+    // the static scratch of the allocation-free even-odd entry point, resolved once on this (current) device
+    if (rc == WDIRAC_OK && (flags & WDIRAC_EVEN_ODD)) rc = schur_scratch_init(op->device);
     if (rc != WDIRAC_OK) {
         dirac_destroy(op);
         return rc;

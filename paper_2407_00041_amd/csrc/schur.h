@@ -38,6 +38,14 @@ hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int p
                          const void *hop, int nrhs, hipStream_t st);
 hipError_t parity_launch_list(int mode, int prec, bool dag, const dirac_op *op, int parity,
                               const std::vector<ParityItem> &items, hipStream_t st);
+// the same from a plain array of n items (no host allocation)
+hipError_t parity_launch_items(int mode, int prec, bool dag, const dirac_op *op, int parity, const ParityItem *items,
+                               size_t n, hipStream_t st);
+
+// Static device scratch of dirac_apply_schur_noalloc: resolve its address on the current device (once per device;
+// called by dirac_create with the operator's device current).
+int schur_scratch_init(int device);
+void *schur_scratch_addr(int device);
 
 // S x (or S^H x) for nrhs even fields: tmp (nrhs odd fields) receives A_oo^{-1} H_oe x.
 hipError_t schur_apply(int prec, bool dag, const dirac_op *op, void *out, const void *in, void *tmp, int nrhs,

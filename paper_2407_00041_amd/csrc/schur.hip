@@ -24,6 +24,7 @@
 // slices are still in the Infinity Cache and Z/Y neighbours mostly in the
 // same XCD's L2.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "schur.h"
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(256) void parity_column_kernel(ParityTable tab, OpD
 }
 
 template <int P, bool DAG, int SELF, bool HOP, bool INV>
-hipError_t launch_mode(const dirac_op *op, int parity, const std::vector<ParityItem> &items, double fh,
+hipError_t launch_mode(const dirac_op *op, int parity, const ParityItem *items, size_t nitems, double fh,
                        hipStream_t st) {
     using T = typename Store<P>::T;
     const int Vh = op->g.V >> 1;
@@ -378,9 +379,9 @@ hipError_t launch_mode(const dirac_op *op, int parity, const std::vector<ParityI
     const int tpr = ((hs + 7) / 8 + 255) / 256;     // 256-site tiles per eighth of a slice
     const int apbc = (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
     const bool rows2 = op->link_rows == 2 || !HOP;
-    for (size_t a = 0; a < items.size(); a += kParMax) {
+    for (size_t a = 0; a < nitems; a += kParMax) {
         ParityTable tab;
-        tab.n = (int)std::min<size_t>(kParMax, items.size() - a);
+        tab.n = (int)std::min<size_t>(kParMax, nitems - a);
         for (int q = 0; q < tab.n; q++) {
             tab.out[q] = items[a + q].out;
             tab.self[q] = items[a + q].self;
@@ -420,19 +421,19 @@ hipError_t launch_mode(const dirac_op *op, int parity, const std::vector<ParityI
 }
 
 template <int P>
-hipError_t launch_p(int mode, bool dag, const dirac_op *op, int parity, const std::vector<ParityItem> &it,
+hipError_t launch_p(int mode, bool dag, const dirac_op *op, int parity, const ParityItem *it, size_t n,
                     hipStream_t st) {
     switch (mode) {
     case kParHopInv:
-        return dag ? launch_mode<P, true, 0, true, true>(op, parity, it, -0.5, st)
-                   : launch_mode<P, false, 0, true, true>(op, parity, it, -0.5, st);
+        return dag ? launch_mode<P, true, 0, true, true>(op, parity, it, n, -0.5, st)
+                   : launch_mode<P, false, 0, true, true>(op, parity, it, n, -0.5, st);
     case kParCloverSub:
-        return dag ? launch_mode<P, true, 2, true, false>(op, parity, it, 0.5, st)
-                   : launch_mode<P, false, 2, true, false>(op, parity, it, 0.5, st);
-    case kParApply: return launch_mode<P, false, 2, true, false>(op, parity, it, -0.5, st);
-    case kParInvSelf: return launch_mode<P, false, 1, false, true>(op, parity, it, 0.0, st);
-    case kParSelfSub: return launch_mode<P, false, 1, true, false>(op, parity, it, 0.5, st);
-    case kParInvSelfSub: return launch_mode<P, false, 1, true, true>(op, parity, it, 0.5, st);
+        return dag ? launch_mode<P, true, 2, true, false>(op, parity, it, n, 0.5, st)
+                   : launch_mode<P, false, 2, true, false>(op, parity, it, n, 0.5, st);
+    case kParApply: return launch_mode<P, false, 2, true, false>(op, parity, it, n, -0.5, st);
+    case kParInvSelf: return launch_mode<P, false, 1, false, true>(op, parity, it, n, 0.0, st);
+    case kParSelfSub: return launch_mode<P, false, 1, true, false>(op, parity, it, n, 0.5, st);
+    case kParInvSelfSub: return launch_mode<P, false, 1, true, true>(op, parity, it, n, 0.5, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -559,15 +560,20 @@ __global__ __launch_bounds__(256) void clover_invert_kernel(double2 *__restrict_
 
 }  // namespace
 
-hipError_t parity_launch_list(int mode, int prec, bool dag, const dirac_op *op, int parity,
-                              const std::vector<ParityItem> &items, hipStream_t st) {
-    if (items.empty()) return hipSuccess;
+hipError_t parity_launch_items(int mode, int prec, bool dag, const dirac_op *op, int parity, const ParityItem *items,
+                               size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
     switch (prec) {
-    case WDIRAC_F64: return launch_p<WDIRAC_F64>(mode, dag, op, parity, items, st);
-    case WDIRAC_F32: return launch_p<WDIRAC_F32>(mode, dag, op, parity, items, st);
-    case WDIRAC_F16S: return launch_p<WDIRAC_F16S>(mode, dag, op, parity, items, st);
+    case WDIRAC_F64: return launch_p<WDIRAC_F64>(mode, dag, op, parity, items, n, st);
+    case WDIRAC_F32: return launch_p<WDIRAC_F32>(mode, dag, op, parity, items, n, st);
+    case WDIRAC_F16S: return launch_p<WDIRAC_F16S>(mode, dag, op, parity, items, n, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t parity_launch_list(int mode, int prec, bool dag, const dirac_op *op, int parity,
+                              const std::vector<ParityItem> &items, hipStream_t st) {
+    return parity_launch_items(mode, prec, dag, op, parity, items.data(), items.size(), st);
 }
 
 hipError_t parity_launch(int mode, int prec, bool dag, const dirac_op *op, int parity, void *out, const void *self,
@@ -608,6 +614,36 @@ hipError_t parity_split_launch(const dirac_op *op, int prec, void *even, void *o
 hipError_t parity_merge_launch(const dirac_op *op, int prec, void *full, const void *even, const void *odd,
                                int nrhs, hipStream_t st) {
     return parity_copy<true>(op, prec, full, const_cast<void *>(even), const_cast<void *>(odd), nrhs, st);
+}
+
+// Device scratch of dirac_apply_schur_noalloc: the odd-parity intermediate A_oo^{-1} H_oe x of nrhs fields,
+// at most kSchurScratchBytes.  Every device that runs the library holds one copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that device (schur_scratch_init).
+constexpr size_t kSchurScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) char schur_scratch[kSchurScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kScratchDevices] = {};
+}  // namespace
+
+int schur_scratch_init(int device) {
+    if (device < 0 || device >= kScratchDevices) return fail(WDIRAC_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_addr[device]) return WDIRAC_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(schur_scratch));
+    if (e != hipSuccess || !p)
+        return fail(WDIRAC_EHIP, std::string("hipGetSymbolAddress of the Schur scratch: ") + hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+    return WDIRAC_OK;
+}
+
+void *schur_scratch_addr(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_addr[device];
 }
 
 hipError_t clover_invert_launch(double2 *inv_can, const double2 *can, int V, double diag, double csw, int *bad,
@@ -704,6 +740,39 @@ int dirac_apply_schur(const dirac_op *op, void *out, const void *in, void *tmp, 
     if (rc) return rc;
     if (overlaps(out, nh, tmp, nh)) return fail(WDIRAC_EINVAL, "out overlaps tmp");
     return hip_result(schur_apply(prec, dagger != 0, op, out, in, tmp, nrhs, (hipStream_t)stream), "schur launch");
+}
+
+int dirac_apply_schur_noalloc(const dirac_op *op, void *out, const void *in, int nrhs, int prec, int dagger,
+                              void *stream) {
+    int rc = check_parity(op, prec, nrhs);
+    if (rc) return rc;
+    if (!in) return fail(WDIRAC_EINVAL, "null field pointer");
+    const size_t rb = field_rhs_bytes(prec, op->g.V / 2), nh = rb * nrhs;
+    if (nh > kSchurScratchBytes)
+        return fail(WDIRAC_EINVAL, "the odd-parity intermediate needs " + std::to_string(nh) +
+                                       " bytes, more than the static scratch of " +
+                                       std::to_string(kSchurScratchBytes) + " bytes");
+    rc = check_out(out, nullptr, in, nh);
+    if (rc) return rc;
+    char *tmp = static_cast<char *>(schur_scratch_addr(op->device));
+    if (!tmp) return fail(WDIRAC_EHIP, "the Schur scratch of this device was not set up at create");
+    hipStream_t st = (hipStream_t)stream;
+    // chunks of right-hand sides with their tables on the stack: nothing is allocated
+    constexpr int kChunk = 16;
+    ParityItem a[kChunk], b[kChunk];
+    for (int r0 = 0; r0 < nrhs; r0 += kChunk) {
+        const int n = std::min(kChunk, nrhs - r0);
+        for (int q = 0; q < n; q++) {
+            const size_t off = (size_t)(r0 + q) * rb;
+            a[q] = {tmp + off, nullptr, static_cast<const char *>(in) + off};
+            b[q] = {static_cast<char *>(out) + off, static_cast<const char *>(in) + off, tmp + off};
+        }
+        rc = hip_result(parity_launch_items(kParHopInv, prec, dagger != 0, op, 1, a, n, st), "schur launch");
+        if (rc) return rc;
+        rc = hip_result(parity_launch_items(kParCloverSub, prec, dagger != 0, op, 0, b, n, st), "schur launch");
+        if (rc) return rc;
+    }
+    return WDIRAC_OK;
 }
 
 int dirac_schur_prepare(const dirac_op *op, void *bhat, const void *b_even, const void *b_odd, void *tmp, int nrhs,
