@@ -22,7 +22,8 @@ timed steps (reported under "extra"):
     waves: wall time, applications and the difference between the two
     solutions; then both again on the even-odd reduced system (half-lattice
     vectors, odd sites reconstructed; the same tolerance relative to the full
-    system's |b|);
+    system's |b|); FGMRES with the SAP preconditioner and with the two-level
+    multigrid (its setup timed on its own);
   * 32^4: FP64 apply rate and plain FP64 FGMRES(20) to 1e-10;
   * 24^3 x 48: forward + backward through the autograd Function and the force
     kernel alone.
@@ -139,9 +140,21 @@ def kernel_profile_rows():
     return rows
 
 
-def traffic_from_profile():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def traffic_from_profile(pattern="dslash_column_kernel<0, false, 1>"):
+    """HBM bytes per launch of the FP64 stencil from the committed counter summaries (the kernel-suite summary,
+    else the stencil's own), if they were taken on the current stencil sources (else None)."""
+    suite = os.path.join(ROOT, KERNELS_PROFILE)
+    if os.path.exists(suite):
+        text = open(suite).read()
+        m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+        if m and m.group(1) == kernel_hash():
+            for line in text.splitlines():
+                c = [x.strip() for x in line.split("|")]
+                if len(c) > 11 and c[1].strip("`") == pattern:
+                    try:
+                        return (float(c[8]) + float(c[9])) * 1e9
+                    except ValueError:
+                        pass
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
@@ -245,13 +258,53 @@ def solver_sweep(op, bn, configs):
     return out
 
 
-def fgmres_run(torch, op, dims, nrhs_total):
+def amg_run(torch, op, dims, stream, steps=10):
+    """The two-level multigrid of the benchmark: setup time (from seeded Gaussian test vectors), then its kernels
+    (restriction, prolongation, coarse operator) and one application of M timed on one right-hand side.  Returns
+    the results and the handle (reused by the solver comparison)."""
+    from paper_2407_00041_amd import TwoLevel, synth
+    N = AMG_DEFAULT["ntv"]
+    V = op.V
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=N, device="cuda"), "f64")
+    mg = TwoLevel(op, tv, **AMG_DEFAULT)
+    del tv
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    b = op.pack(synth.gaussian_spinor(dims, 4001, nrhs=1, device="cuda"), "f64")
+    c = mg.restrict(b)
+    ms_r = time_launches(torch, lambda: mg.restrict(b, stream=stream), steps, 2, stream)
+    ms_p = time_launches(torch, lambda: mg.prolong(c, stream=stream), steps, 2, stream)
+    ms_c = time_launches(torch, lambda: mg.coarse_apply(c, stream=stream), steps, 2, stream)
+    s0 = mg.stats()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        mg.precond(b, stream=stream)
+    torch.cuda.synchronize()
+    ms_m = (time.perf_counter() - t) / 3 * 1e3
+    s1 = mg.stats()
+    rp = (N + 1) * 192 * V
+    rc = mg.Vc * (5 * 4 * N * N + 4 * N) * 16
+    res = {"params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in AMG_DEFAULT.items() if k != "smoother"},
+           "smoother": {k: (list(v) if isinstance(v, tuple) else v) for k, v in AMG_DEFAULT["smoother"].items()},
+           "coarse_dims": list(mg.coarse_dims), "unknowns_per_coarse_site": mg.unknowns, "setup_seconds": setup_s,
+           "restrict_ms": ms_r, "prolong_ms": ms_p, "coarse_apply_ms": ms_c,
+           "restrict_alg_bytes": rp, "coarse_apply_alg_bytes": rc,
+           "precond_ms": ms_m, "coarse_applies_per_precond": (s1["coarse_applies"] - s0["coarse_applies"]) / 3}
+    del b, c
+    return res, mg
+
+
+def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
     """12 right-hand sides to 1e-10, in waves sized to the free HBM, by every
     solver: plain FP64 FGMRES(30) (the reference), plain FP64 at the restart a
     one-RHS sweep picks, the mixed FP64/FP16S solver at its tuned restart 8 and
-    at restart 30, FGMRES with the SAP preconditioner, and FP64 and mixed on
-    the even-odd reduced system.  Times are summed over the waves; errors are
-    against the FP64 FGMRES(30) solution."""
+    at restart 30, FGMRES with the SAP preconditioner, FP64 and mixed on the
+    even-odd reduced system, and FGMRES with the two-level multigrid (one
+    setup for all right-hand sides).  Times are summed over the waves; errors
+    are against the FP64 FGMRES(30) solution."""
     from paper_2407_00041_amd import synth
     base = dict(tol=1e-10)
     inner = dict(inner_restart=MIXED["inner_restart"], inner_tol=MIXED["inner_tol"], inner_maxit=MIXED["inner_restart"])
@@ -286,51 +339,75 @@ def fgmres_run(torch, op, dims, nrhs_total):
         ("even_odd_mixed", "the mixed solver on S (FP16S S in the inner GMRES)",
          dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], schur=True, **inner)),
     ]
+    # two-level multigrid: one setup serves every right-hand side (its time is reported on its own)
+    if mg is None:
+        from paper_2407_00041_amd import TwoLevel
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=AMG_DEFAULT["ntv"], device="cuda"), "f64")
+        mg = TwoLevel(op, tv, **AMG_DEFAULT)
+        del tv
+        torch.cuda.synchronize()
+        amg_setup_s = time.perf_counter() - t
+    log(f"[bench] AMG setup {amg_setup_s:.2f} s (coarse lattice {mg.coarse_dims}, {mg.unknowns} unknowns per site)")
+    solvers.append(("amg", f"FP64 FGMRES(16), preconditioner two-level multigrid ({AMG_DEFAULT['agg']} aggregates, "
+                           f"{AMG_DEFAULT['ntv']} test vectors, {AMG_DEFAULT['init_iters']} + "
+                           f"{AMG_DEFAULT['setup_iters']} setup passes, SAP post-smoothing, coarse GMRES to "
+                           f"{AMG_DEFAULT['coarse_tol']}); setup time excluded, reported separately",
+                    dict(base, restart=16, maxit=500, mode="amg", amg=mg)))
     fb = op.field_bytes("f64", 1)
-    free, _ = torch.cuda.mem_get_info()
-    per = max(op.workspace_bytes(1, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=1,
-                                 schur=kw.get("schur", False), sap=kw.get("sap")) for _, _, kw in solvers) + 6 * fb
-    wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
-    log(f"[bench] fgmres: {nrhs_total} RHS in waves of {wave} (free {free / 2**30:.0f} GiB, "
-        f"{per / 2**30:.1f} GiB per RHS)")
-    wbytes = max(op.workspace_bytes(wave, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=wave,
-                                    schur=kw.get("schur", False), sap=kw.get("sap")) for _, _, kw in solvers)
-    work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.empty_cache()
+    # every solver in waves as large as its own workspace allows in the free HBM (lockstep right-hand sides share
+    # batched applications); the FP64 FGMRES(30) solutions (kept on the host) are the reference of the errors
     rec = {k: {"solver": d, "seconds": 0.0, "applies": [], "inner_applies": [], "true_residual": [], "err": [],
-               "phase_seconds": {"apply": 0.0, "precond": 0.0, "ortho": 0.0}} for k, d, _ in solvers}
-    for w0 in range(0, nrhs_total, wave):
-        nw = min(wave, nrhs_total - w0)
-        b = op.pack(synth.gaussian_spinor(dims, 3000 + w0, nrhs=nw, device="cuda"), "f64")
-        ref = None
-        for key, _, kw in solvers:
+               "wave": 0, "phase_seconds": {"apply": 0.0, "precond": 0.0, "ortho": 0.0}} for k, d, _ in solvers}
+    ref = {}
+    for key, _, kw in solvers:
+        free, _ = torch.cuda.mem_get_info()
+        per = op.workspace_bytes(1, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=1,
+                                 schur=kw.get("schur", False), sap=kw.get("sap"), amg=kw.get("amg")) + 3 * fb
+        wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
+        work = torch.empty(op.workspace_bytes(wave, kw["restart"], kw["mode"], kw.get("inner_restart", 30),
+                                              wave=wave, schur=kw.get("schur", False), sap=kw.get("sap"),
+                                              amg=kw.get("amg")), dtype=torch.uint8, device="cuda")
+        r = rec[key]
+        r["wave"] = wave
+        for w0 in range(0, nrhs_total, wave):
+            nw = min(wave, nrhs_total - w0)
+            b = op.pack(torch.cat([synth.gaussian_spinor(dims, 3000 + q, nrhs=1, device="cuda")
+                                   for q in range(w0, w0 + nw)]), "f64")
             torch.cuda.synchronize()
             t = time.perf_counter()
             x, st, _ = op.solve(b, nrhs=nw, work=work, wave=wave, **kw)
             torch.cuda.synchronize()
-            r = rec[key]
             r["seconds"] += time.perf_counter() - t
             for ph in r["phase_seconds"]:
-                r["phase_seconds"][ph] += st[0]["seconds_" + ph]
-            if ref is None:
-                ref = x
+                r["phase_seconds"][ph] += sum(st[k]["seconds_" + ph] for k in range(0, nw, wave))
             for k in range(nw):
-                u = ref[k * fb:(k + 1) * fb].view(torch.float64)
-                v = x[k * fb:(k + 1) * fb].view(torch.float64)
+                v = x[k * fb:(k + 1) * fb].view(torch.float64).cpu()
+                if key == "fp64":
+                    ref[w0 + k] = v
+                u = ref[w0 + k]
                 r["err"].append(float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(u)))
                 r["applies"].append(st[k]["applies"])
                 r["inner_applies"].append(st[k]["inner_applies"])
                 r["true_residual"].append(st[k]["true_residual"])
-            if x is not ref:
-                del x
-        log(f"[bench] fgmres after RHS {w0 + nw}: " + ", ".join(f"{k} {rec[k]['seconds']:.2f}s" for k in rec))
-        del b, ref
+            del x, b
+        del work
         torch.cuda.empty_cache()
-    out = {"nrhs": nrhs_total, "wave": wave, "tol": 1e-10,
+        log(f"[bench] fgmres {key}: {nrhs_total} RHS in waves of {wave}, {r['seconds']:.2f} s, "
+            f"applies {sum(r['applies'])}")
+    amg_stats = mg.stats()
+    mg.close()
+    torch.cuda.empty_cache()
+    out = {"nrhs": nrhs_total, "tol": 1e-10,
+           "amg_setup_seconds": amg_setup_s, "amg_coarse": {"dims": list(mg.coarse_dims), "unknowns_per_site":
+                                                             mg.unknowns, **amg_stats},
            "sweeps_one_rhs_seconds": {"fp64": {n: t for t, n, *_ in sweep64},
                                       "sap": {n: t for t, n, *_ in sweep_sap}}}
     for k, r in rec.items():
-        out[k] = {"solver": r["solver"], "seconds": r["seconds"], "phase_seconds": r["phase_seconds"],
-                  "applies": r["applies"], "true_residual_max": max(r["true_residual"]),
+        out[k] = {"solver": r["solver"], "seconds": r["seconds"], "wave": r["wave"],
+                  "phase_seconds": r["phase_seconds"], "applies": r["applies"], "true_residual_max": max(r["true_residual"]),
                   "converged": all(x < 1e-10 for x in r["true_residual"]),
                   "error_vs_fp64_max": max(r["err"])}
         if any(r["inner_applies"]):
@@ -480,6 +557,7 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
         add(pat, reps, reps * BYTES_SITE[p] * V, f"D apply {p}, 1 RHS")
         del x, y
     torch.cuda.synchronize()
+    log("[suite] single applies done")
     # one FP32 launch over batches {1, 4, 12, 24}: the link-stationary kernel
     _fixed(wd, 5, 128, 1, 1)
     sizes = [1, 4, 12, 24]
@@ -499,6 +577,7 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
     del outs, batches, nat
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    log("[suite] batched launch done")
     # even-odd reduced operator S on pairs of right-hand sides
     for p in ("f64", "f32", "f16s"):
         e, o = op.split(op.pack(psid, p), p, 2)
@@ -514,12 +593,33 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
             f"S (pair), even launch A_ee - H_eo, {p}")
         del e, o, out, tmp
     torch.cuda.synchronize()
+    log("[suite] even-odd done")
     # SAP, FP32 blocks of 4^4, one red-black cycle, 4 MR steps (two launches per cycle)
     bn = op.pack(psid[:1], "f64")
     for _ in range(3):
         op.sap(bn, block=(4, 4, 4, 4), cycles=1, mr_iters=4, prec="f32")
     add(r"sap_pass_kernel<1, true, true>", 6, 3 * SAP_BYTES_SITE_CYCLE * V, "SAP cycle FP32 4^4 blocks (2 passes)")
     torch.cuda.synchronize()
+    log("[suite] SAP done")
+    # two-level multigrid: restriction, prolongation (8 test vectors on 4^4 aggregates) and the coarse operator
+    from paper_2407_00041_amd import TwoLevel
+    N = AMG_DEFAULT["ntv"]
+    tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=N, device="cuda"), "f64")
+    mg = TwoLevel(op, tv, **dict(AMG_DEFAULT, init_iters=0, setup_iters=0))
+    del tv
+    c = mg.restrict(bn)
+    for _ in range(3):
+        mg.restrict(bn)
+        mg.prolong(c)
+        mg.coarse_apply(c)
+    torch.cuda.synchronize()
+    add(r"k_restrict", 4, 4 * (N + 1) * 192 * V, f"AMG restriction P^H f ({N} FP64 test vectors)")
+    add(r"k_prolong", 3, 3 * (N + 1) * 192 * V, f"AMG prolongation P c ({N} FP64 test vectors)")
+    add(r"k_coarse_apply", 3, 3 * mg.Vc * (5 * 4 * N * N + 4 * N) * 16,
+        "AMG coarse operator D_c (self + 4 forward blocks once, vectors in and out)")
+    mg.close()
+    del c
+    log("[suite] multigrid done")
     # one cycle of plain FP64 FGMRES(30) (the outer Gram-Schmidt kernels), and the mixed solver's inner cycles
     _fixed(wd, 3, 256, 2, 1)
     x, stt, _ = op.solve(bn, restart=30, tol=1e-14, maxit=31)
@@ -550,6 +650,7 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     del op
+    log("[suite] solver cycles done")
     # the link derivative at 24^3 x 48
     fd = (48, 24, 24, 24)
     Vf = int(np.prod(fd))
@@ -640,7 +741,7 @@ def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, co
         lines.append(f"| `{pat}` | {r['note']} | {r['seen']} (expected {r['dispatches']}) | {avg * 1e6:.1f} | "
                      f"{ab / 1e9:.4f} | {ag:.0f} | {ag / HBM_PEAK_GBS:.3f} | {rd / 1e9:.4f} | {wr / 1e9:.4f} | "
                      f"{cg:.0f} | {(rd + wr) / ab if ab else 0:.2f} |")
-    lines += ["", f"sources_sha256_16: {all_sources_hash()}", ""]
+    lines += ["", f"sources_sha256_16: {all_sources_hash()}", f"kernel_source_sha256_16: {kernel_hash()}", ""]
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
     log(f"[bench] wrote {out_md}")
@@ -677,6 +778,14 @@ def kernel_table(extra, V):
         row("sap_pass_kernel<1, true, true>", "SAP cycle, FP32 4^4 blocks, 4 MR steps (two launches)",
             extra["sap"]["ms_per_cycle"], extra["sap"]["alg_bytes_per_cycle"], "sap_pass_kernel<1, true, true>",
             extra["sap"]["flop_per_cycle"])
+    if "amg" in extra:
+        m = extra["amg"]
+        row("k_restrict", "AMG restriction P^H f, FP64, 8 test vectors", m["restrict_ms"], m["restrict_alg_bytes"],
+            "k_restrict")
+        row("k_prolong", "AMG prolongation P c, FP64, 8 test vectors", m["prolong_ms"], m["restrict_alg_bytes"],
+            "k_prolong")
+        row("k_coarse_apply", "AMG coarse operator D_c, FP64", m["coarse_apply_ms"], m["coarse_apply_alg_bytes"],
+            "k_coarse_apply")
     if "differentiation" in extra:
         d = extra["differentiation"]
         Vf = int(np.prod(d["dims"]))
@@ -733,37 +842,35 @@ def cpu_baseline_run(dims, U, psi, m0, csw, target_s=3.0):
             "cpu": cpu_info()}
 
 
-def oracle_fgmres_model(dims, U, m0, csw, steps, seed, full=False, restart=20):
-    """The oracle FGMRES (Algorithm 2, modified Gram-Schmidt) timed on the host.
+def oracle_fgmres_model(dims, site_rate, steps, restart=20, full_args=None, sample_sites=1 << 18):
+    """The oracle FGMRES (Algorithm 2, modified Gram-Schmidt) on the host, as a bounded sample.
 
-    Bounded sample (default): the oracle's own building blocks are timed at the
-    lattice size (two operator applications, and three modified Gram-Schmidt
-    inner iterations: an inner product and a vector update) and the solve is
-    extrapolated from the iteration structure the GPU solve of the same system
-    reported (applications, Arnoldi step index of every application).  With
-    full=True the oracle FGMRES runs to 1e-10 and is timed whole."""
+    The oracle's operator application is timed by cpu_baseline_run (sites per second, ``site_rate``); one
+    modified Gram-Schmidt inner iteration (an inner product and a vector update in NumPy) is timed on a vector of
+    ``sample_sites`` sites and scaled to the lattice; the solve is extrapolated from the iteration structure the
+    GPU solve of the same system reported (applications; step j of a restart cycle costs j + 1 inner iterations).
+    With full_args = (U, m0, csw, seed) the oracle FGMRES runs to 1e-10 and is timed whole instead."""
     import oracle
-    from paper_2407_00041_amd import synth
     V = int(np.prod(dims))
-    b = synth.gaussian_spinor(dims, seed)
-    C = oracle.clover_term(dims, U)
-    A = lambda v: oracle.dirac_apply(dims, U, v, m0, csw, clover=C)
-    if full:
+    if full_args is not None:
+        from paper_2407_00041_amd import synth
+        U, m0, csw, seed = full_args
+        b = synth.gaussian_spinor(dims, seed)
+        C = oracle.clover_term(dims, U)
         t = time.perf_counter()
-        _, info = oracle.fgmres(A, b, m=restart, tol=1e-10, maxit=10 * steps)
+        _, info = oracle.fgmres(lambda v: oracle.dirac_apply(dims, U, v, m0, csw, clover=C), b, m=restart,
+                                tol=1e-10, maxit=10 * steps)
         return {"seconds": time.perf_counter() - t, "applies": info["applies"], "extrapolated": False}
+    t_apply = V / site_rate
+    n = min(V, sample_sites)
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(12 * n) + 1j * rng.standard_normal(12 * n)
+    w = rng.standard_normal(12 * n) + 1j * rng.standard_normal(12 * n)
     t = time.perf_counter()
-    w = A(b)
-    w = A(w)
-    t_apply = (time.perf_counter() - t) / 2
-    v = b / np.linalg.norm(b)
-    t = time.perf_counter()
-    for _ in range(3):
-        h = np.vdot(v.ravel(), w.ravel())
+    for _ in range(5):
+        h = np.vdot(v, w)
         w = w - h * v
-    t_gs = (time.perf_counter() - t) / 3
-    # restart cycles of `restart` steps: one residual application per cycle, and step j of a cycle
-    # costs j + 1 Gram-Schmidt inner iterations
+    t_gs = (time.perf_counter() - t) / 5 * (V / n)
     cycles = -(-(steps - 1) // (restart + 1))   # each ends with the next cycle's (or the final) residual
     arnoldi = steps - cycles - 1
     gs = 0
@@ -774,8 +881,9 @@ def oracle_fgmres_model(dims, U, m0, csw, steps, seed, full=False, restart=20):
         left -= k
     est = steps * t_apply + gs * t_gs
     return {"seconds": est, "applies": steps, "extrapolated": True, "t_apply_s": t_apply, "t_gs_inner_s": t_gs,
-            "model": f"{steps} applications x {t_apply:.3f} s + {gs} Gram-Schmidt inner iterations x {t_gs:.3f} s "
-                     f"(restart {restart}, iteration counts of the GPU solve)"}
+            "model": f"{steps} applications x {t_apply:.2f} s (the timed oracle apply rate) + {gs} Gram-Schmidt "
+                     f"inner iterations x {t_gs:.3f} s (NumPy, timed on {n} sites and scaled), restart {restart}, "
+                     f"iteration counts of the GPU solve"}
 
 
 def main():
@@ -885,8 +993,17 @@ def main():
         extra["sap"] = sap_run(torch, op, psid, stream)
         log(f"[bench] SAP cycle (FP32, 4^4 blocks, 4 MR): {extra['sap']['ms_per_cycle']:.3f} ms, "
             f"{extra['sap']['alg_GBps']:.0f} GB/s, {extra['sap']['TFLOPs']:.1f} TFLOP/s")
+    mg = None
+    if not a.no_extra:
+        extra["amg"], mg = amg_run(torch, op, dims, stream)
+        log(f"[bench] AMG: setup {extra['amg']['setup_seconds']:.2f} s, restrict {extra['amg']['restrict_ms']:.3f} ms, "
+            f"prolong {extra['amg']['prolong_ms']:.3f} ms, coarse apply {extra['amg']['coarse_apply_ms']:.3f} ms, "
+            f"M {extra['amg']['precond_ms']:.1f} ms")
     if not a.no_extra and not a.no_fgmres and a.fgmres_rhs > 0:
-        extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs)
+        extra["fgmres"] = fgmres_run(torch, op, dims, a.fgmres_rhs, mg, extra["amg"]["setup_seconds"])
+    elif mg is not None:
+        mg.close()
+    mg = None
     if not a.no_extra:
         log("[bench] 32^4: FP64 apply and FGMRES(20)")
         extra["config_32"] = config32_run(torch, stream)
@@ -932,17 +1049,20 @@ def main():
         if not a.no_extra:
             # the oracle FGMRES beside the GPU solves: FGMRES(20) at 32^4, and one right-hand side of the
             # 48^3 x 96 FP64 FGMRES(30) run extrapolated to the 12 right-hand sides
+            site_rate = res["cpu_baseline"]["value"] * V
             c32 = extra.get("config_32", {}).get("fgmres20_fp64", {})
-            U32 = synth.smooth_links((32, 32, 32, 32), 1002, device="cuda").cpu().numpy() if c32 else None
             if c32:
-                o32 = oracle_fgmres_model((32, 32, 32, 32), U32, -0.3, 1.0, c32["applies"], 2000, full=a.cpu_full)
+                full = None
+                if a.cpu_full:
+                    U32 = synth.smooth_links((32, 32, 32, 32), 1002, device="cuda").cpu().numpy()
+                    full = (U32, -0.3, 1.0, 2000)
+                o32 = oracle_fgmres_model((32, 32, 32, 32), site_rate, c32["applies"], 20, full)
                 o32["gpu_seconds"] = c32["seconds"]
                 res["cpu_baseline"]["fgmres20_32^4"] = o32
                 log(f"[bench] oracle FGMRES(20) 32^4: {o32['seconds']:.1f} s (GPU {c32['seconds']:.2f} s)")
-            del U32
             f64 = extra.get("fgmres", {}).get("fp64")
             if f64:
-                o48 = oracle_fgmres_model(dims, U, a.m0, a.csw, int(f64["applies"][0]), 3000, restart=30)
+                o48 = oracle_fgmres_model(dims, site_rate, int(f64["applies"][0]), 30)
                 o48["rhs"] = 12
                 o48["seconds_12_rhs_extrapolated"] = 12 * o48["seconds"]
                 o48["gpu_seconds_12_rhs"] = f64["seconds"]

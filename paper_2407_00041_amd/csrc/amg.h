@@ -35,7 +35,7 @@ struct dirac_amg {
     // device buffers (owned; one allocation carved into pieces)
     void *mem = nullptr;
     double2 *test = nullptr;    // N native FP64 fields: the current test vectors
-    double2 *P = nullptr;       // [Vc][N][na][12]: column (a, s, k) on the components 6s..6s+5 of its sites
+    double2 *P = nullptr;       // [Vc][N][12][na]: column (a, s, k) on the components 6s..6s+5 of a's sites
     double2 *Dc = nullptr;      // [Vc][5][2N][2N]: self block, then the blocks to the +T, +Z, +Y, +X neighbours
     // preconditioner workspace (one right-hand side)
     double2 *cb = nullptr;      // coarse basis, coarse_restart + 1 vectors

@@ -15,9 +15,9 @@
 //     two-level inverse iteration v <- M v / |M v|, rebuilding P and D_c after
 //     every pass.
 //
-// Storage (FP64): P aggregate-major, [Vc][N][na][12] complex, so the reductions
-// of restriction and of the coarse-operator build read each column of an
-// aggregate as one contiguous run; D_c as [Vc][5][2N][2N] complex, the block of
+// Storage (FP64): P aggregate-major and component-major inside a column,
+// [Vc][N][12][na] complex, so consecutive lanes (consecutive local sites) read
+// consecutive entries and a chirality block of a column is one contiguous run; D_c as [Vc][5][2N][2N] complex, the block of
 // a coarse site with itself and with its +T, +Z, +Y, +X neighbours (row-major,
 // rows = output unknowns s*N + k).  The block to the -mu neighbour is not
 // stored: gamma_5-hermiticity of D and the chirality split of P give
@@ -90,8 +90,9 @@ __device__ __forceinline__ int site_index(const Geom &g, const int c[4]) {
     return ((c[0] * g.n[1] + c[1]) * g.n[2] + c[2]) * g.n[3] + c[3];
 }
 
-__device__ __forceinline__ size_t pidx(const AmgGeom &ag, int a, int k, int j) {
-    return ((size_t)(a * ag.N + k) * ag.na + j) * 12;
+// start of column k of aggregate a in P: entry (component e, local site j) at + e * na + j
+__device__ __forceinline__ size_t pcol(const AmgGeom &ag, int a, int k) {
+    return (size_t)(a * ag.N + k) * 12 * ag.na;
 }
 
 // deterministic work-group sum of M complex values (every thread gets the totals); lds holds [4][M]
@@ -138,11 +139,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_gather(double2 *fields, double2
     site_coords(g, s, c);
     agg_of(ag, c, a, j);
     double2 *f = fields + (size_t)k * 12 * g.V;
-    double2 *q = P + pidx(ag, a, k, j);
+    double2 *q = P + pcol(ag, a, k) + j;
 #pragma unroll
     for (int e = 0; e < 12; e++) {
-        if (dir == 0) q[e] = f[(size_t)e * g.V + s];
-        else f[(size_t)e * g.V + s] = q[e];
+        if (dir == 0) q[(size_t)e * ag.na] = f[(size_t)e * g.V + s];
+        else f[(size_t)e * g.V + s] = q[(size_t)e * ag.na];
     }
 }
 
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(kAmgThreads) void k_block_gs(double2 *P, AmgGeom ag
     __shared__ double2 h[kAmgMaxTv];
     const int a = blockIdx.x, sp = blockIdx.y;
     const int L = 6 * ag.na;
-    auto el = [&](int k, int e) -> double2 & { return P[pidx(ag, a, k, e / 6) + 6 * sp + e % 6]; };
+    // the chirality's 6 components of all na sites are one contiguous run of the column
+    auto el = [&](int k, int e) -> double2 & { return P[pcol(ag, a, k) + (size_t)6 * sp * ag.na + e]; };
     for (int k = 0; k < ag.N; k++) {
         double2 n0[1] = {make_double2(0.0, 0.0)};
         for (int e = threadIdx.x; e < L; e += kAmgThreads) {
@@ -217,10 +219,10 @@ __device__ __forceinline__ void column_at(const double2 *P, const AmgGeom &ag, i
 #pragma unroll
     for (int e = 0; e < 12; e++) p[e] = mk<double>(0.0, 0.0);
     if (a != src) return;
-    const double2 *q = P + pidx(ag, a, l, j) + 6 * sp;
+    const double2 *q = P + pcol(ag, a, l) + (size_t)6 * sp * ag.na + j;
 #pragma unroll
     for (int e = 0; e < 6; e++) {
-        const cx<double> v = mk<double>(q[e].x, q[e].y);
+        const cx<double> v = mk<double>(q[(size_t)e * ag.na].x, q[(size_t)e * ag.na].y);
         if (sp == 0) p[e] = v;
         else p[6 + e] = v;
     }
@@ -350,11 +352,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_coarse_build(const double2 *P, 
 #pragma unroll
                     for (int q = 0; q < kAmgChunk; q++) {
                         if (q >= nk) break;
-                        const double2 *pk = P + pidx(ag, a, k0 + q, j);
+                        const double2 *pk = P + pcol(ag, a, k0 + q) + j;
 #pragma unroll
                         for (int e = 0; e < 6; e++) {
-                            cj_acc(acc[2 * q], pk[e], make_double2(y[e].r, y[e].i));
-                            cj_acc(acc[2 * q + 1], pk[6 + e], make_double2(y[6 + e].r, y[6 + e].i));
+                            cj_acc(acc[2 * q], pk[(size_t)e * ag.na], make_double2(y[e].r, y[e].i));
+                            cj_acc(acc[2 * q + 1], pk[(size_t)(6 + e) * ag.na], make_double2(y[6 + e].r, y[6 + e].i));
                         }
                     }
                 }
@@ -390,11 +392,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_restrict(const double2 *P, cons
                 int cc[4];
                 coords_of(ag, a, j, cc);
                 const int s = site_index(g, cc);
-                const double2 *pk = P + pidx(ag, a, k, j);
+                const double2 *pk = P + pcol(ag, a, k) + j;
 #pragma unroll
                 for (int e = 0; e < 6; e++) {
-                    cj_acc(acc0, pk[e], f[(size_t)e * g.V + s]);
-                    cj_acc(acc1, pk[6 + e], f[(size_t)(6 + e) * g.V + s]);
+                    cj_acc(acc0, pk[(size_t)e * ag.na], f[(size_t)e * g.V + s]);
+                    cj_acc(acc1, pk[(size_t)(6 + e) * ag.na], f[(size_t)(6 + e) * g.V + s]);
                 }
             }
 #pragma unroll
@@ -426,11 +428,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_prolong(const double2 *P, const
     for (int e = 0; e < 12; e++) o[e] = make_double2(0.0, 0.0);
     const double2 *ca = c + (size_t)a * 2 * ag.N;
     for (int k = 0; k < ag.N; k++) {
-        const double2 *pk = P + pidx(ag, a, k, j);
+        const double2 *pk = P + pcol(ag, a, k) + j;
         const double2 c0 = ca[k], c1 = ca[ag.N + k];
 #pragma unroll
         for (int e = 0; e < 6; e++) {
-            const double2 p0 = pk[e], p1 = pk[6 + e];
+            const double2 p0 = pk[(size_t)e * ag.na], p1 = pk[(size_t)(6 + e) * ag.na];
             o[e].x += p0.x * c0.x - p0.y * c0.y;
             o[e].y += p0.x * c0.y + p0.y * c0.x;
             o[6 + e].x += p1.x * c1.x - p1.y * c1.y;
