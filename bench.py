@@ -242,6 +242,12 @@ SAP_DEFAULT = {"block": (4, 4, 4, 4), "cycles": 1, "mr_iters": 4, "prec": "f32"}
 # vectors, SAP smoother as above, coarse GMRES(30) to 5e-2
 AMG_DEFAULT = {"agg": (4, 4, 4, 4), "ntv": 8, "init_iters": 3, "setup_iters": 1, "smoother": SAP_DEFAULT,
                "coarse_restart": 30, "coarse_maxit": 300, "coarse_tol": 0.05}
+# alternatives tried on one right-hand side in the solver comparison: P in FP32, two smoother cycles, and more
+# test vectors with a second setup pass
+AMG_SWEEP = [("p32", dict(AMG_DEFAULT, prec="f32")),
+             ("p32_c2", dict(AMG_DEFAULT, prec="f32", smoother=dict(SAP_DEFAULT, cycles=2))),
+             ("p32_n12_s2_c2", dict(AMG_DEFAULT, prec="f32", ntv=12, setup_iters=2,
+                                    smoother=dict(SAP_DEFAULT, cycles=2)))]
 
 
 def solver_sweep(op, bn, configs):
@@ -339,21 +345,45 @@ def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
         ("even_odd_mixed", "the mixed solver on S (FP16S S in the inner GMRES)",
          dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], schur=True, **inner)),
     ]
-    # two-level multigrid: one setup serves every right-hand side (its time is reported on its own)
-    if mg is None:
-        from paper_2407_00041_amd import TwoLevel
+    # two-level multigrid: one setup serves every right-hand side (its time is reported on its own); a few
+    # multigrid configurations are tried on one right-hand side and the fastest solves all twelve
+    from paper_2407_00041_amd import TwoLevel
+
+    def make_mg(cfg):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=AMG_DEFAULT["ntv"], device="cuda"), "f64")
-        mg = TwoLevel(op, tv, **AMG_DEFAULT)
+        tv = op.pack(synth.gaussian_spinor(dims, 4000, nrhs=cfg["ntv"], device="cuda"), "f64")
+        m = TwoLevel(op, tv, **cfg)
         del tv
         torch.cuda.synchronize()
-        amg_setup_s = time.perf_counter() - t
+        return m, time.perf_counter() - t
+
+    if mg is None:
+        mg, amg_setup_s = make_mg(AMG_DEFAULT)
+    b1 = op.pack(synth.gaussian_spinor(dims, 3000, nrhs=1, device="cuda"), "f64")
+    sweep_amg = []
+    best_amg = None
+    for k, (name, cfg) in enumerate([("default", AMG_DEFAULT)] + AMG_SWEEP):
+        m, ts = (mg, amg_setup_s) if k == 0 else make_mg(cfg)
+        (t1, _, _, ap, _), = solver_sweep(op, b1, [(name, dict(base, restart=16, maxit=500, mode="amg", amg=m))])
+        sweep_amg.append((t1, name, cfg, ap, ts, None))
+        torch.cuda.empty_cache()
+        if best_amg is None or t1 < best_amg[0]:
+            if best_amg is not None:
+                best_amg[5].close()
+            best_amg = (t1, name, cfg, ap, ts, m)
+        else:
+            m.close()
+    del b1
+    _, amg_name, amg_cfg, _, amg_setup_s, mg = best_amg
+    log("[bench] amg sweep " + ", ".join(f"{n} {t:.3f}s/{a} (setup {ts:.2f}s)" for t, n, _, a, ts, _ in sweep_amg))
     log(f"[bench] AMG setup {amg_setup_s:.2f} s (coarse lattice {mg.coarse_dims}, {mg.unknowns} unknowns per site)")
-    solvers.append(("amg", f"FP64 FGMRES(16), preconditioner two-level multigrid ({AMG_DEFAULT['agg']} aggregates, "
-                           f"{AMG_DEFAULT['ntv']} test vectors, {AMG_DEFAULT['init_iters']} + "
-                           f"{AMG_DEFAULT['setup_iters']} setup passes, SAP post-smoothing, coarse GMRES to "
-                           f"{AMG_DEFAULT['coarse_tol']}); setup time excluded, reported separately",
+    sm = amg_cfg["smoother"]
+    solvers.append(("amg", f"FP64 FGMRES(16), preconditioner two-level multigrid ({amg_cfg['agg']} aggregates, "
+                           f"{amg_cfg['ntv']} test vectors, {amg_cfg['init_iters']} + {amg_cfg['setup_iters']} setup "
+                           f"passes, SAP post-smoothing with {sm['cycles']} cycle(s) of {sm['mr_iters']} MR steps, "
+                           f"coarse GMRES to {amg_cfg['coarse_tol']}, P stored in {amg_cfg.get('prec', 'f64')}); "
+                           f"setup time excluded, reported separately",
                     dict(base, restart=16, maxit=500, mode="amg", amg=mg)))
     fb = op.field_bytes("f64", 1)
     torch.cuda.empty_cache()
@@ -404,7 +434,10 @@ def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
            "amg_setup_seconds": amg_setup_s, "amg_coarse": {"dims": list(mg.coarse_dims), "unknowns_per_site":
                                                              mg.unknowns, **amg_stats},
            "sweeps_one_rhs_seconds": {"fp64": {n: t for t, n, *_ in sweep64},
-                                      "sap": {n: t for t, n, *_ in sweep_sap}}}
+                                      "sap": {n: t for t, n, *_ in sweep_sap},
+                                      "amg": {n: {"solve": t, "applies": a, "setup": ts}
+                                              for t, n, _, a, ts, _ in sweep_amg}},
+           "amg_config": amg_name}
     for k, r in rec.items():
         out[k] = {"solver": r["solver"], "seconds": r["seconds"], "wave": r["wave"],
                   "phase_seconds": r["phase_seconds"], "applies": r["applies"], "true_residual_max": max(r["true_residual"]),
@@ -673,6 +706,8 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
     add(r"vectorized_elementwise_kernel<4, at::native::BUnaryFunctor<float", 5, 5 * 2 * (1 << 30),
         "copy probe (torch.mul), 1 GiB in + 1 GiB out")
     wd.tune_set("explicit", 0)
+    # the sources this run was built from (the summary records these, not the sources present when it is written)
+    man["_sources"] = {"all": all_sources_hash(), "kernel": kernel_hash()}
     with open(manifest_path, "w") as f:
         json.dump(man, f, indent=1)
     log(f"[bench] kernel suite done; manifest {manifest_path}")
@@ -697,6 +732,7 @@ def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, co
     dispatch count, average duration, algorithmic GB/s, and the counter bytes
     (FETCH_SIZE scaled by the copy probe's calibration, WRITE_SIZE likewise)."""
     man = json.load(open(manifest_path))
+    src = man.pop("_sources", {"all": all_sources_hash(), "kernel": kernel_hash()})
     kt = _read_csv(_find(trace_dir, "kernel_trace.csv"))
 
     def counters(d, name):
@@ -741,7 +777,7 @@ def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, co
         lines.append(f"| `{pat}` | {r['note']} | {r['seen']} (expected {r['dispatches']}) | {avg * 1e6:.1f} | "
                      f"{ab / 1e9:.4f} | {ag:.0f} | {ag / HBM_PEAK_GBS:.3f} | {rd / 1e9:.4f} | {wr / 1e9:.4f} | "
                      f"{cg:.0f} | {(rd + wr) / ab if ab else 0:.2f} |")
-    lines += ["", f"sources_sha256_16: {all_sources_hash()}", f"kernel_source_sha256_16: {kernel_hash()}", ""]
+    lines += ["", f"sources_sha256_16: {src['all']}", f"kernel_source_sha256_16: {src['kernel']}", ""]
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
     log(f"[bench] wrote {out_md}")

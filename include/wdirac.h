@@ -333,7 +333,8 @@ int dirac_sap(const dirac_op *op, double *x, const double *b, int nrhs, const sa
  *     caller's test vectors, build P and D_c; then setup_iters passes of
  *     v_k <- M v_k / |M v_k| with the current two-level method, each
  *     followed by a rebuild.
- * Everything runs in FP64 except the smoother (its own precision).
+ * Everything runs in FP64 except the smoother (its own precision) and,
+ * with prec = WDIRAC_F32, the storage of P.
  */
 typedef struct {
     int agg[4];            /* aggregate extents {aT, aZ, aY, aX}              */
@@ -345,6 +346,10 @@ typedef struct {
     int coarse_restart;    /* GMRES restart on D_c, 1..1000                   */
     long long coarse_maxit;/* D_c applications per coarse solve (>= 1)        */
     double coarse_tol;     /* relative residual of a coarse solve, (0, 1)     */
+    int prec;              /* storage of P: WDIRAC_F64 or WDIRAC_F32 (FP32    */
+                           /* rounds the orthonormal columns; restriction,    */
+                           /* prolongation and the coarse build still         */
+                           /* accumulate in FP64)                             */
 } amg_params;
 
 typedef struct dirac_amg dirac_amg;

@@ -300,17 +300,18 @@ class TwoLevel:
     construction from the caller's initial test vectors (device, native FP64,
     ntv fields), then restriction, prolongation, the coarse operator, the
     coarse solve and the preconditioner M.  ``smoother`` holds sap_params
-    keywords."""
+    keywords; ``prec`` is the storage of P ("f64" or "f32")."""
 
     def __init__(self, op: DiracOp, testvecs: torch.Tensor, agg=(4, 4, 4, 4), ntv: int = 8, init_iters: int = 3,
                  setup_iters: int = 1, smoother=None, coarse_restart: int = 30, coarse_maxit: int = 1000,
-                 coarse_tol: float = 0.05, stream=None):
+                 coarse_tol: float = 0.05, prec="f64", stream=None):
         self.lib = _lib.load()
         self.op = op
         self.N = int(ntv)
         sp = DiracOp.sap_params(**(smoother or {}))
         self.params = _lib.AmgParams((ctypes.c_int * 4)(*[int(a) for a in agg]), self.N, int(init_iters),
-                                     int(setup_iters), sp, int(coarse_restart), int(coarse_maxit), float(coarse_tol))
+                                     int(setup_iters), sp, int(coarse_restart), int(coarse_maxit), float(coarse_tol),
+                                     _prec(prec))
         h = ctypes.c_void_p()
         check(self.lib.dirac_amg_create(ctypes.byref(h), op.handle, ctypes.byref(self.params), _ptr(testvecs),
                                         _stream(stream)), "dirac_amg_create")

@@ -32,7 +32,8 @@ class SapParams(ctypes.Structure):
 
 class AmgParams(ctypes.Structure):
     _fields_ = [("agg", _I * 4), ("ntv", _I), ("init_iters", _I), ("setup_iters", _I), ("smoother", SapParams),
-                ("coarse_restart", _I), ("coarse_maxit", ctypes.c_longlong), ("coarse_tol", ctypes.c_double)]
+                ("coarse_restart", _I), ("coarse_maxit", ctypes.c_longlong), ("coarse_tol", ctypes.c_double),
+                ("prec", _I)]
 
 
 class FgmresParams(ctypes.Structure):

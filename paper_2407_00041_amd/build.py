@@ -39,16 +39,17 @@ def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
 
 
 def build(jobs: int | None = None, verbose: bool = False, out: str = OUT, build_dir: str = BUILD,
-          extra=()) -> str:
-    """Compile and link; ``extra`` adds hipcc flags (e.g. -D overrides of the
-    kernels' compile-time launch parameters) and ``out`` names the library."""
+          extra=(), link_extra=()) -> str:
+    """Compile and link; ``extra`` adds hipcc compile flags (e.g. -D overrides
+    of the kernels' compile-time launch parameters), ``link_extra`` link
+    flags, and ``out`` names the library."""
     os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir, tuple(extra)), srcs))
     tmp = out + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

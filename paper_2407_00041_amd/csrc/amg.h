@@ -35,7 +35,8 @@ struct dirac_amg {
     // device buffers (owned; one allocation carved into pieces)
     void *mem = nullptr;
     double2 *test = nullptr;    // N native FP64 fields: the current test vectors
-    double2 *P = nullptr;       // [Vc][N][12][na]: column (a, s, k) on the components 6s..6s+5 of a's sites
+    void *P = nullptr;          // [Vc][N][12][na] double2 or float2 (p.prec): column (a, s, k) on the
+                                // components 6s..6s+5 of a's sites
     double2 *Dc = nullptr;      // [Vc][5][2N][2N]: self block, then the blocks to the +T, +Z, +Y, +X neighbours
     // preconditioner workspace (one right-hand side)
     double2 *cb = nullptr;      // coarse basis, coarse_restart + 1 vectors

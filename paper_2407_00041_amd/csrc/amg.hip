@@ -15,7 +15,7 @@
 //     two-level inverse iteration v <- M v / |M v|, rebuilding P and D_c after
 //     every pass.
 //
-// Storage (FP64): P aggregate-major and component-major inside a column,
+// Storage: P (FP64, or FP32 with amg_params.prec) aggregate-major and component-major inside a column,
 // [Vc][N][12][na] complex, so consecutive lanes (consecutive local sites) read
 // consecutive entries and a chirality block of a column is one contiguous run; D_c as [Vc][5][2N][2N] complex, the block of
 // a coarse site with itself and with its +T, +Z, +Y, +X neighbours (row-major,
@@ -28,6 +28,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <vector>
 
 #include "amg.h"
@@ -127,11 +128,21 @@ __device__ __forceinline__ void cj_acc(double2 &acc, double2 a, double2 b) {
     acc.y += a.x * b.y - a.y * b.x;
 }
 
+// entries of P in storage S (double2: FP64, float2: FP32, round to nearest), arithmetic always in FP64
+__device__ __forceinline__ double2 pld(const double2 *p) { return *p; }
+__device__ __forceinline__ double2 pld(const float2 *p) {
+    const float2 v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void pst(double2 *p, double2 v) { *p = v; }
+__device__ __forceinline__ void pst(float2 *p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
 // ---------------------------------------------------------------------------
 // kernels
 
 // dir 0: P[a][k][j] = test_k(site);  dir 1: out_k(site) = P[a][k][j]   (native FP64 fields)
-__global__ __launch_bounds__(kAmgThreads) void k_gather(double2 *fields, double2 *P, Geom g, AmgGeom ag, int dir) {
+template <typename S>
+__global__ __launch_bounds__(kAmgThreads) void k_gather(double2 *fields, S *P, Geom g, AmgGeom ag, int dir) {
     const int s = blockIdx.x * kAmgThreads + threadIdx.x;
     if (s >= g.V) return;
     const int k = blockIdx.y;
@@ -139,23 +150,25 @@ __global__ __launch_bounds__(kAmgThreads) void k_gather(double2 *fields, double2
     site_coords(g, s, c);
     agg_of(ag, c, a, j);
     double2 *f = fields + (size_t)k * 12 * g.V;
-    double2 *q = P + pcol(ag, a, k) + j;
+    S *q = P + pcol(ag, a, k) + j;
 #pragma unroll
     for (int e = 0; e < 12; e++) {
-        if (dir == 0) q[(size_t)e * ag.na] = f[(size_t)e * g.V + s];
-        else f[(size_t)e * g.V + s] = q[(size_t)e * ag.na];
+        if (dir == 0) pst(q + (size_t)e * ag.na, f[(size_t)e * g.V + s]);
+        else f[(size_t)e * g.V + s] = pld(q + (size_t)e * ag.na);
     }
 }
 
 // Gram-Schmidt (classical, two passes) of the N columns of one (aggregate, chirality) in order; flag |= 1 when a
 // column is dependent on the previous ones (remaining norm <= 1e-12 of its original norm)
-__global__ __launch_bounds__(kAmgThreads) void k_block_gs(double2 *P, AmgGeom ag, int *flag) {
+template <typename S>
+__global__ __launch_bounds__(kAmgThreads) void k_block_gs(S *P, AmgGeom ag, int *flag) {
     __shared__ double2 red[4 * kAmgChunk];
     __shared__ double2 h[kAmgMaxTv];
     const int a = blockIdx.x, sp = blockIdx.y;
     const int L = 6 * ag.na;
     // the chirality's 6 components of all na sites are one contiguous run of the column
-    auto el = [&](int k, int e) -> double2 & { return P[pcol(ag, a, k) + (size_t)6 * sp * ag.na + e]; };
+    auto at = [&](int k, int e) { return P + pcol(ag, a, k) + (size_t)6 * sp * ag.na + e; };
+    auto el = [&](int k, int e) { return pld(at(k, e)); };
     for (int k = 0; k < ag.N; k++) {
         double2 n0[1] = {make_double2(0.0, 0.0)};
         for (int e = threadIdx.x; e < L; e += kAmgThreads) {
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(kAmgThreads) void k_block_gs(double2 *P, AmgGeom ag
                     w.x -= c.x * v.x - c.y * v.y;
                     w.y -= c.x * v.y + c.y * v.x;
                 }
-                el(k, e) = w;
+                pst(at(k, e), w);
             }
             __syncthreads();
         }
@@ -204,25 +217,27 @@ __global__ __launch_bounds__(kAmgThreads) void k_block_gs(double2 *P, AmgGeom ag
         if (dep && threadIdx.x == 0) atomicOr(flag, 1);
         const double inv = dep ? 0.0 : 1.0 / sqrt(nk[0].x);
         for (int e = threadIdx.x; e < L; e += kAmgThreads) {
-            double2 w = el(k, e);
-            el(k, e) = make_double2(w.x * inv, w.y * inv);
+            const double2 w = el(k, e);
+            pst(at(k, e), make_double2(w.x * inv, w.y * inv));
         }
         __syncthreads();
     }
 }
 
 // column (sp, l) of aggregate `src` at the site with coordinates c (zero off its chirality), into p[12]
-__device__ __forceinline__ void column_at(const double2 *P, const AmgGeom &ag, int src, int l, int sp,
+template <typename S>
+__device__ __forceinline__ void column_at(const S *P, const AmgGeom &ag, int src, int l, int sp,
                                           const int c[4], cx<double> p[12]) {
     int a, j;
     agg_of(ag, c, a, j);
 #pragma unroll
     for (int e = 0; e < 12; e++) p[e] = mk<double>(0.0, 0.0);
     if (a != src) return;
-    const double2 *q = P + pcol(ag, a, l) + (size_t)6 * sp * ag.na + j;
+    const S *q = P + pcol(ag, a, l) + (size_t)6 * sp * ag.na + j;
 #pragma unroll
     for (int e = 0; e < 6; e++) {
-        const cx<double> v = mk<double>(q[(size_t)e * ag.na].x, q[(size_t)e * ag.na].y);
+        const double2 u = pld(q + (size_t)e * ag.na);
+        const cx<double> v = mk<double>(u.x, u.y);
         if (sp == 0) p[e] = v;
         else p[6 + e] = v;
     }
@@ -279,7 +294,8 @@ __device__ __forceinline__ void site_term(const OpData &d, int V, int s, const c
 // and target sites lie in a (site-local term and the hops inside a, including those that wrap around a
 // direction with one aggregate); block 1 + mu the forward hops from a's sites on its +mu face into a + mu
 // (zero when one aggregate spans mu).
-__global__ __launch_bounds__(kAmgThreads) void k_coarse_build(const double2 *P, double2 *Dc, OpData d, Geom g,
+template <typename S>
+__global__ __launch_bounds__(kAmgThreads) void k_coarse_build(const S *P, double2 *Dc, OpData d, Geom g,
                                                               AmgGeom ag, int apbc) {
     __shared__ double2 red[4 * 2 * kAmgChunk];
     const int a = blockIdx.x;
@@ -352,11 +368,12 @@ __global__ __launch_bounds__(kAmgThreads) void k_coarse_build(const double2 *P, 
 #pragma unroll
                     for (int q = 0; q < kAmgChunk; q++) {
                         if (q >= nk) break;
-                        const double2 *pk = P + pcol(ag, a, k0 + q) + j;
+                        const S *pk = P + pcol(ag, a, k0 + q) + j;
 #pragma unroll
                         for (int e = 0; e < 6; e++) {
-                            cj_acc(acc[2 * q], pk[(size_t)e * ag.na], make_double2(y[e].r, y[e].i));
-                            cj_acc(acc[2 * q + 1], pk[(size_t)(6 + e) * ag.na], make_double2(y[6 + e].r, y[6 + e].i));
+                            cj_acc(acc[2 * q], pld(pk + (size_t)e * ag.na), make_double2(y[e].r, y[e].i));
+                            cj_acc(acc[2 * q + 1], pld(pk + (size_t)(6 + e) * ag.na),
+                                   make_double2(y[6 + e].r, y[6 + e].i));
                         }
                     }
                 }
@@ -376,9 +393,10 @@ __global__ __launch_bounds__(kAmgThreads) void k_coarse_build(const double2 *P, 
 
 // c[a][s][k] = scale * sum over a's sites and s's components of conj(P) f; one work-group per (a, rhs).  The
 // work-group's eight 32-lane groups take one test vector each (passes of eight), every lane a strided subset of
-// the aggregate's sites (consecutive lanes read consecutive 192-byte columns of P); each group reduces over its
-// lanes in a fixed order.
-__global__ __launch_bounds__(kAmgThreads) void k_restrict(const double2 *P, const double2 *f, double2 *c, Geom g,
+// the aggregate's sites (consecutive lanes read consecutive entries of P's component-major column); each group
+// reduces over its lanes in a fixed order.
+template <typename S>
+__global__ __launch_bounds__(kAmgThreads) void k_restrict(const S *P, const double2 *f, double2 *c, Geom g,
                                                           AmgGeom ag, double scale) {
     const int a = blockIdx.x;
     const int kq = threadIdx.x >> 5, lane = threadIdx.x & 31;
@@ -392,11 +410,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_restrict(const double2 *P, cons
                 int cc[4];
                 coords_of(ag, a, j, cc);
                 const int s = site_index(g, cc);
-                const double2 *pk = P + pcol(ag, a, k) + j;
+                const S *pk = P + pcol(ag, a, k) + j;
 #pragma unroll
                 for (int e = 0; e < 6; e++) {
-                    cj_acc(acc0, pk[(size_t)e * ag.na], f[(size_t)e * g.V + s]);
-                    cj_acc(acc1, pk[(size_t)(6 + e) * ag.na], f[(size_t)(6 + e) * g.V + s]);
+                    cj_acc(acc0, pld(pk + (size_t)e * ag.na), f[(size_t)e * g.V + s]);
+                    cj_acc(acc1, pld(pk + (size_t)(6 + e) * ag.na), f[(size_t)(6 + e) * g.V + s]);
                 }
             }
 #pragma unroll
@@ -414,7 +432,8 @@ __global__ __launch_bounds__(kAmgThreads) void k_restrict(const double2 *P, cons
 }
 
 // f(x) = sum_k P_k(x) c[a(x)][s][k] on the components of s; one thread per site, blockIdx.y = rhs
-__global__ __launch_bounds__(kAmgThreads) void k_prolong(const double2 *P, const double2 *c, double2 *f, Geom g,
+template <typename S>
+__global__ __launch_bounds__(kAmgThreads) void k_prolong(const S *P, const double2 *c, double2 *f, Geom g,
                                                          AmgGeom ag) {
     const int s = blockIdx.x * kAmgThreads + threadIdx.x;
     if (s >= g.V) return;
@@ -428,11 +447,11 @@ __global__ __launch_bounds__(kAmgThreads) void k_prolong(const double2 *P, const
     for (int e = 0; e < 12; e++) o[e] = make_double2(0.0, 0.0);
     const double2 *ca = c + (size_t)a * 2 * ag.N;
     for (int k = 0; k < ag.N; k++) {
-        const double2 *pk = P + pcol(ag, a, k) + j;
+        const S *pk = P + pcol(ag, a, k) + j;
         const double2 c0 = ca[k], c1 = ca[ag.N + k];
 #pragma unroll
         for (int e = 0; e < 6; e++) {
-            const double2 p0 = pk[(size_t)e * ag.na], p1 = pk[(size_t)(6 + e) * ag.na];
+            const double2 p0 = pld(pk + (size_t)e * ag.na), p1 = pld(pk + (size_t)(6 + e) * ag.na);
             o[e].x += p0.x * c0.x - p0.y * c0.y;
             o[e].y += p0.x * c0.y + p0.y * c0.x;
             o[6 + e].x += p1.x * c1.x - p1.y * c1.y;
@@ -525,6 +544,8 @@ int check_params(const dirac_op *op, const amg_params *p, AmgGeom &ag, SapGeom &
     if (p->coarse_restart < 1 || p->coarse_restart > 1000) return fail(WDIRAC_EINVAL, "coarse_restart in [1, 1000]");
     if (p->coarse_maxit < 1) return fail(WDIRAC_EINVAL, "coarse_maxit must be >= 1");
     if (!(p->coarse_tol > 0.0) || !(p->coarse_tol < 1.0)) return fail(WDIRAC_EINVAL, "coarse_tol must be in (0, 1)");
+    if (p->prec != WDIRAC_F64 && p->prec != WDIRAC_F32)
+        return fail(WDIRAC_EINVAL, "AMG prec (storage of P) must be WDIRAC_F64 or WDIRAC_F32");
     long long na = 1, vc = 1;
     for (int mu = 0; mu < 4; mu++) {
         const int A = p->agg[mu], L = op->g.n[mu];
@@ -685,15 +706,32 @@ int coarse_gmres(const dirac_amg *A, double2 *x, const double2 *b, long long *it
     return WDIRAC_OK;
 }
 
+bool p32(const dirac_amg *A) { return A->p.prec == WDIRAC_F32; }
+const float2 *P32(const dirac_amg *A) { return static_cast<const float2 *>(A->P); }
+const double2 *P64(const dirac_amg *A) { return static_cast<const double2 *>(A->P); }
+
 hipError_t restrict_launch(const dirac_amg *A, double2 *c, const double2 *f, int nrhs, double scale_, hipStream_t st) {
-    hipLaunchKernelGGL(k_restrict, dim3(A->ag.Vc, nrhs), dim3(kAmgThreads), 0, st, A->P, f, c, A->op->g, A->ag,
-                       scale_);
+    const dim3 grid(A->ag.Vc, nrhs), blk(kAmgThreads);
+    if (p32(A)) hipLaunchKernelGGL(k_restrict<float2>, grid, blk, 0, st, P32(A), f, c, A->op->g, A->ag, scale_);
+    else hipLaunchKernelGGL(k_restrict<double2>, grid, blk, 0, st, P64(A), f, c, A->op->g, A->ag, scale_);
     return hipGetLastError();
 }
 
 hipError_t prolong_launch(const dirac_amg *A, double2 *f, const double2 *c, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_prolong, dim3((A->op->g.V + kAmgThreads - 1) / kAmgThreads, nrhs), dim3(kAmgThreads), 0, st,
-                       A->P, c, f, A->op->g, A->ag);
+    const dim3 grid((A->op->g.V + kAmgThreads - 1) / kAmgThreads, nrhs), blk(kAmgThreads);
+    if (p32(A)) hipLaunchKernelGGL(k_prolong<float2>, grid, blk, 0, st, P32(A), c, f, A->op->g, A->ag);
+    else hipLaunchKernelGGL(k_prolong<double2>, grid, blk, 0, st, P64(A), c, f, A->op->g, A->ag);
+    return hipGetLastError();
+}
+
+// native FP64 fields <-> P (dir 0: fields into P, dir 1: P into fields)
+hipError_t gather_launch(const dirac_amg *A, double2 *fields, int dir, hipStream_t st) {
+    const Geom &g = A->op->g;
+    const dim3 grid((g.V + kAmgThreads - 1) / kAmgThreads, A->ag.N), blk(kAmgThreads);
+    if (p32(A))
+        hipLaunchKernelGGL(k_gather<float2>, grid, blk, 0, st, fields, static_cast<float2 *>(A->P), g, A->ag, dir);
+    else
+        hipLaunchKernelGGL(k_gather<double2>, grid, blk, 0, st, fields, static_cast<double2 *>(A->P), g, A->ag, dir);
     return hipGetLastError();
 }
 
@@ -701,18 +739,25 @@ hipError_t prolong_launch(const dirac_amg *A, double2 *f, const double2 *c, int 
 int build(dirac_amg *A, hipStream_t st) {
     const Geom &g = A->op->g;
     AMG_TRY(hipMemsetAsync(A->flag, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_gather, dim3((g.V + kAmgThreads - 1) / kAmgThreads, A->ag.N), dim3(kAmgThreads), 0, st,
-                       A->test, A->P, g, A->ag, 0);
-    AMG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_block_gs, dim3(A->ag.Vc, 2), dim3(kAmgThreads), 0, st, A->P, A->ag, A->flag);
+    AMG_TRY(gather_launch(A, A->test, 0, st));
+    if (p32(A))
+        hipLaunchKernelGGL(k_block_gs<float2>, dim3(A->ag.Vc, 2), dim3(kAmgThreads), 0, st,
+                           static_cast<float2 *>(A->P), A->ag, A->flag);
+    else
+        hipLaunchKernelGGL(k_block_gs<double2>, dim3(A->ag.Vc, 2), dim3(kAmgThreads), 0, st,
+                           static_cast<double2 *>(A->P), A->ag, A->flag);
     AMG_TRY(hipGetLastError());
     int flag = 0;
     AMG_TRY(hipMemcpyAsync(&flag, A->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     AMG_TRY(hipStreamSynchronize(st));
     if (flag) return fail(WDIRAC_EINVAL, "test vectors are linearly dependent on some aggregate");
     const int apbc = (A->op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0;
-    hipLaunchKernelGGL(k_coarse_build, dim3(A->ag.Vc), dim3(kAmgThreads), 0, st, A->P, A->Dc, A->op->data(WDIRAC_F64),
-                       g, A->ag, apbc);
+    if (p32(A))
+        hipLaunchKernelGGL(k_coarse_build<float2>, dim3(A->ag.Vc), dim3(kAmgThreads), 0, st, P32(A), A->Dc,
+                           A->op->data(WDIRAC_F64), g, A->ag, apbc);
+    else
+        hipLaunchKernelGGL(k_coarse_build<double2>, dim3(A->ag.Vc), dim3(kAmgThreads), 0, st, P64(A), A->Dc,
+                           A->op->data(WDIRAC_F64), g, A->ag, apbc);
     AMG_TRY(hipGetLastError());
     return WDIRAC_OK;
 }
@@ -738,6 +783,9 @@ int setup(dirac_amg *A, hipStream_t st) {
         }
     int rc = build(A, st);
     if (rc) return rc;
+    if (log_level() >= 2)
+        std::fprintf(stderr, "[wdirac] amg setup: %d smoother passes over %d test vectors, P and D_c built\n",
+                     A->p.init_iters, A->ag.N);
     for (int it = 0; it < A->p.setup_iters; it++) {
         // every test vector through the current two-level method, then one rebuild
         for (int k = 0; k < A->ag.N; k++) {
@@ -749,6 +797,9 @@ int setup(dirac_amg *A, hipStream_t st) {
         }
         rc = build(A, st);
         if (rc) return rc;
+        if (log_level() >= 2)
+            std::fprintf(stderr, "[wdirac] amg setup: two-level pass %d done (%lld coarse solves, %lld D_c applies)\n",
+                         it + 1, A->coarse_solves, A->coarse_iters);
     }
     return WDIRAC_OK;
 }
@@ -805,12 +856,13 @@ int dirac_amg_create(dirac_amg **out, const dirac_op *op, const amg_params *p, c
     const Geom &g = op->g;
     const size_t field = a256((size_t)12 * g.V * sizeof(double2));
     const size_t cvec = a256((size_t)coarse_len(ag) * sizeof(double2));
-    const size_t nP = a256((size_t)ag.N * field);
+    const size_t nT = a256((size_t)ag.N * field);
+    const size_t nP = a256((size_t)ag.N * 12 * g.V * (p->prec == WDIRAC_F32 ? sizeof(float2) : sizeof(double2)));
     const size_t nDc = a256((size_t)ag.Vc * 5 * 4 * ag.N * ag.N * sizeof(double2));
     const size_t nsap = a256(sap_workspace(op, &p->smoother, 1));
     const size_t nscal = a256((p->coarse_restart + 4) * sizeof(double2));
     const size_t npart = a256(partial_entries_amg() * sizeof(double2));
-    const size_t total = nP /*test*/ + nP /*P*/ + nDc + (size_t)(p->coarse_restart + 1) * cvec + 2 * cvec +
+    const size_t total = nT /*test*/ + nP /*P*/ + nDc + (size_t)(p->coarse_restart + 1) * cvec + 2 * cvec +
                          3 * field + nsap + nscal + npart + 256;
     auto *A = new dirac_amg;
     A->op = op;
@@ -829,8 +881,8 @@ int dirac_amg_create(dirac_amg **out, const dirac_op *op, const amg_params *p, c
         q += n;
         return r;
     };
-    A->test = reinterpret_cast<double2 *>(take(nP));
-    A->P = reinterpret_cast<double2 *>(take(nP));
+    A->test = reinterpret_cast<double2 *>(take(nT));
+    A->P = take(nP);
     A->Dc = reinterpret_cast<double2 *>(take(nDc));
     A->cb = reinterpret_cast<double2 *>(take((size_t)(p->coarse_restart + 1) * cvec));
     A->crhs = reinterpret_cast<double2 *>(take(cvec));
@@ -960,9 +1012,7 @@ int dirac_amg_export(const dirac_amg *amg, int what, double *out, void *stream) 
     if (what == WDIRAC_AMG_TEST_VECTORS) {
         e = hipMemcpyAsync(out, amg->test, fb * amg->ag.N, hipMemcpyDeviceToDevice, st);
     } else if (what == WDIRAC_AMG_INTERPOLATION) {
-        hipLaunchKernelGGL(k_gather, dim3((g.V + kAmgThreads - 1) / kAmgThreads, amg->ag.N), dim3(kAmgThreads), 0,
-                           st, reinterpret_cast<double2 *>(out), amg->P, g, amg->ag, 1);
-        e = hipGetLastError();
+        e = gather_launch(amg, reinterpret_cast<double2 *>(out), 1, st);
     } else if (what == WDIRAC_AMG_COARSE_OPERATOR) {
         e = hipMemcpyAsync(out, amg->Dc, (size_t)amg->ag.Vc * 5 * 4 * amg->ag.N * amg->ag.N * sizeof(double2),
                            hipMemcpyDeviceToDevice, st);

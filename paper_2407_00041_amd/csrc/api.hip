@@ -1,4 +1,6 @@
 // C ABI of the library: operator handle, applies, layout conversion.
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -24,8 +26,19 @@ constexpr double kCloverTol = 1e-10;  // largest |C_00 + C_11| / max(1, |C|) acc
 
 void set_error(const std::string &msg) { g_err = msg; }
 
+// WDIRAC_LOG: 0 (default) silent, 1 every failing call's status and message on stderr, 2 also solver and setup
+// progress
+int log_level() {
+    static const int level = [] {
+        const char *e = std::getenv("WDIRAC_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return level;
+}
+
 int fail(int code, const std::string &msg) {
     g_err = msg;
+    if (log_level() >= 1) std::fprintf(stderr, "[wdirac] status %d: %s\n", code, msg.c_str());
     return code;
 }
 

@@ -16,6 +16,8 @@ namespace wd {
 // error state (thread-local message, status codes of the C ABI)
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
+// verbosity from the WDIRAC_LOG environment variable (read once): 0 silent, 1 errors, 2 progress
+int log_level();
 #define WD_HIP(call)                                                                   \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \

@@ -40,6 +40,7 @@
 // low-precision solves.
 
 #include <algorithm>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -755,10 +756,13 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                 continue;
             }
             r.restarts++;
+            if (log_level() >= 2)
+                std::fprintf(stderr, "[wdirac] fgmres rhs %d: restart %lld after %lld applies, relres %.3e\n",
+                             (int)(&r - R.data()), r.restarts, r.applies, r.relres);
             r.cw.assign(m + 1, 0.0);
             r.sz.assign(m, 1.0);
             r.cw[0] = beta;  // V[0] = r = beta v_0
-            if (!mixed && !sapm) r.sz[0] = beta;
+            if (!mixed && !sapm && !amgm) r.sz[0] = beta;  // M = I: Z aliases V
             r.outer.reset(m, beta);
             r.phase = Phase::Arnoldi;
         }
@@ -800,7 +804,7 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
                     WD_TRY((scale<double2, double2>(r.V[jn], r.V[jn], nullptr, false, 1.0 / cn, c.N, c.st)));
                     r.cw[jn] = 1.0;
                 }
-                if (!mixed && !sapm) r.sz[jn] = r.cw[jn];  // Z aliases V
+                if (!mixed && !sapm && !amgm) r.sz[jn] = r.cw[jn];  // Z aliases V
                 continue;
             }
             std::vector<zc> yz = r.outer.solve();

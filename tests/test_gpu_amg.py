@@ -25,7 +25,7 @@ def rel(a, b):
 
 
 def make(dims, agg, N, seed, ap=False, compress=False, init=0, setup=0, ctol=1e-12, sap_block=(2, 2, 2, 2),
-         sap_prec="f64", m0=-0.3, csw=1.0):
+         sap_prec="f64", m0=-0.3, csw=1.0, prec="f64"):
     U = synth.smooth_links(dims, seed).numpy()
     T = synth.gaussian_spinor(dims, seed + 1, nrhs=N)
     op = DiracOp(dims, U, m0, csw, precisions=("f64", "f32"), antiperiodic_t=ap, compress_links=compress,
@@ -33,7 +33,7 @@ def make(dims, agg, N, seed, ap=False, compress=False, init=0, setup=0, ctol=1e-
     tv = op.pack(to_dev(T), "f64")
     mg = TwoLevel(op, tv, agg=agg, ntv=N, init_iters=init, setup_iters=setup,
                   smoother=dict(block=sap_block, cycles=1, mr_iters=4, prec=sap_prec), coarse_restart=30,
-                  coarse_maxit=20000, coarse_tol=ctol)
+                  coarse_maxit=20000, coarse_tol=ctol, prec=prec)
     return U, T, op, mg
 
 
@@ -80,6 +80,29 @@ def test_interpolation_and_coarse_operator_match_oracle(dims, agg, N, ap, compre
                 assert rel(blocks[a, 1 + mu], Dc[a * n2:(a + 1) * n2, b * n2:(b + 1) * n2]) < 1e-12
             elif nc[mu] == 1:
                 assert not blocks[a, 1 + mu].any()
+    mg.close()
+    op.close()
+
+
+def test_fp32_interpolation_matches_oracle():
+    """P stored in FP32 (amg_params.prec): P, restriction, the coarse operator and M agree with the oracle's FP64
+    ones to FP32 rounding, and FGMRES with M still reaches 1e-10 (the preconditioner's precision does not limit the
+    outer FP64 solve)."""
+    need_gpu()
+    dims, agg, N = (8, 4, 4, 4), (2, 2, 2, 2), 6
+    U, T, op, mg = make(dims, agg, N, 75, prec="f32")
+    tl = oamg.TwoLevel(dims, U, -0.3, 1.0, agg, T, sap_block=(2, 2, 2, 2), sap_cycles=1, sap_mr=4)
+    assert rel(op.unpack(mg.export("interpolation"), "f64", N).cpu().numpy(), tl.q) < 1e-6
+    f = synth.gaussian_spinor(dims, 76)
+    assert rel(mg.restrict(op.pack(to_dev(f), "f64")).cpu().numpy()[0], tl.restrict(f)) < 1e-6
+    cr = synth.gaussian_spinor((1, 1, 1, tl.Vc * 2 * N), 77).reshape(-1)[:tl.Vc * 2 * N].reshape(tl.Vc, 2, N)
+    assert rel(mg.coarse_apply(to_dev(cr[None])).cpu().numpy()[0], tl.coarse_apply(cr)) < 1e-6
+    z = op.unpack(mg.precond(op.pack(to_dev(f), "f64")), "f64").cpu().numpy()[0]
+    assert rel(z, tl.precond(f)) < 1e-5
+    x, st, rc = op.solve(op.pack(to_dev(f), "f64"), restart=16, tol=1e-10, maxit=400, mode="amg", amg=mg)
+    assert rc == 0 and st[0]["converged"]
+    xg = op.unpack(x, "f64").cpu().numpy()[0]
+    assert rel(oracle.dirac_apply(dims, U, xg, -0.3, 1.0), f) <= 1.01e-10
     mg.close()
     op.close()
 
@@ -160,7 +183,7 @@ def test_amg_argument_errors():
     tv = op.pack(to_dev(T), "f64")
     sm = dict(block=(2, 2, 2, 2), prec="f64")
     for kw in (dict(agg=(3, 2, 2, 2)), dict(ntv=33), dict(agg=(1, 1, 1, 1), ntv=7), dict(coarse_tol=0.0),
-               dict(coarse_restart=0)):
+               dict(coarse_restart=0), dict(prec="f16s")):
         args = dict(agg=(2, 2, 2, 2), ntv=4, smoother=sm)
         args.update(kw)
         with pytest.raises(WdiracError) as e:
