@@ -571,6 +571,8 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
                     compress_clover=True, even_odd=True)
     man = {}
 
+    # a pattern's dispatches are its first `dispatches` matches in launch order (its last ones with
+    # select = "last"): later solver sections launch the same kernels with other sizes
     def add(pattern, n, nbytes, note):
         e = man.setdefault(pattern, {"dispatches": 0, "alg_bytes": 0.0, "note": note})
         e["dispatches"] += n
@@ -703,8 +705,10 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
     for _ in range(5):
         torch.mul(src, 2.0, out=dst)
     torch.cuda.synchronize()
-    add(r"vectorized_elementwise_kernel<4, at::native::BUnaryFunctor<float", 5, 5 * 2 * (1 << 30),
+    add(r"vectorized_elementwise_kernel<4, at::native::[AB]UnaryFunctor<float, float, float, "
+        r"at::native::binary_internal::MulFunctor<float", 5, 5 * 2 * (1 << 30),
         "copy probe (torch.mul), 1 GiB in + 1 GiB out")
+    man[list(man)[-1]]["select"] = "last"
     wd.tune_set("explicit", 0)
     # the sources this run was built from (the summary records these, not the sources present when it is written)
     man["_sources"] = {"all": all_sources_hash(), "kernel": kernel_hash()}
@@ -733,10 +737,10 @@ def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, co
     (FETCH_SIZE scaled by the copy probe's calibration, WRITE_SIZE likewise)."""
     man = json.load(open(manifest_path))
     src = man.pop("_sources", {"all": all_sources_hash(), "kernel": kernel_hash()})
-    kt = _read_csv(_find(trace_dir, "kernel_trace.csv"))
+    kt = sorted(_read_csv(_find(trace_dir, "kernel_trace.csv")), key=lambda r: int(r["Dispatch_Id"]))
 
     def counters(d, name):
-        rows = _read_csv(_find(d, "counter_collection.csv"))
+        rows = sorted(_read_csv(_find(d, "counter_collection.csv")), key=lambda r: int(r["Dispatch_Id"]))
         out = []
         for r in rows:
             if r.get("Counter_Name", "") == name:
@@ -746,15 +750,21 @@ def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, co
     fetch = counters(fetch_dir, "FETCH_SIZE")
     write = counters(write_dir, "WRITE_SIZE")
     res = {}
+
+    def pick(items, e):
+        n = e["dispatches"]
+        return items[-n:] if e.get("select") == "last" else items[:n]
+
     for pat, e in man.items():
         rx = re.compile(pat)
-        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in kt if rx.search(r["Kernel_Name"])]
-        fk = [v for k, v in fetch if rx.search(k)]
-        wk = [v for k, v in write if rx.search(k)]
+        durs = pick([(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in kt
+                     if rx.search(r["Kernel_Name"])], e)
+        fk = pick([v for k, v in fetch if rx.search(k)], e)
+        wk = pick([v for k, v in write if rx.search(k)], e)
         res[pat] = {"note": e["note"], "dispatches": e["dispatches"], "seen": len(durs),
                     "seconds": sum(durs), "alg_bytes": e["alg_bytes"],
                     "fetch_kib": sum(fk), "write_kib": sum(wk), "counted": (len(fk), len(wk))}
-    probe = next(p for p in res if "BUnaryFunctor" in p)
+    probe = next(p for p in res if "MulFunctor<float" in p)
     cal_f = res[probe]["alg_bytes"] / 2 / max(res[probe]["fetch_kib"] * 1024, 1)
     cal_w = res[probe]["alg_bytes"] / 2 / max(res[probe]["write_kib"] * 1024, 1)
     lines = ["# Product kernels at the benchmark sizes: time, algorithmic and counted HBM traffic", "",
@@ -832,7 +842,8 @@ def kernel_table(extra, V):
 
 def cpu_info():
     """CPU model and identification numbers from /proc/cpuinfo, and the CPU set this process may use."""
-    info = {"logical_cpus_in_affinity": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    info = {"logical_cpus_in_affinity": len(os.sched_getaffinity(0)), "logical_cpus_at_start": len(START_CPUS),
+            "os_cpu_count": os.cpu_count()}
     try:
         for line in open("/proc/cpuinfo"):
             k, _, v = line.partition(":")
@@ -844,8 +855,18 @@ def cpu_info():
     return info
 
 
+# the CPU set the process started with (the GPU runtime may narrow the main thread's mask once it initialises)
+START_CPUS = os.sched_getaffinity(0)
+
+
 def _oracle_threads():
+    """Restore the process's starting CPU set on this thread (OpenMP threads inherit it) and use one oracle thread
+    per CPU in it."""
     import oracle
+    try:
+        os.sched_setaffinity(0, START_CPUS)
+    except OSError:
+        pass
     n = len(os.sched_getaffinity(0))
     oracle.set_threads(n)
     return oracle.num_threads()
