@@ -239,15 +239,14 @@ def batched_run(torch, op, dims, stream, steps):
 
 SAP_DEFAULT = {"block": (4, 4, 4, 4), "cycles": 1, "mr_iters": 4, "prec": "f32"}
 # two-level multigrid preconditioner: aggregates of 4^4 sites (a 24 x 12^3 coarse lattice at 48^3 x 96), 8 test
-# vectors, SAP smoother as above, coarse GMRES(30) to 5e-2
+# vectors, SAP smoother as above, coarse GMRES(30) to 5e-2, the interpolation stored in FP32 (FP64 accumulation)
 AMG_DEFAULT = {"agg": (4, 4, 4, 4), "ntv": 8, "init_iters": 3, "setup_iters": 1, "smoother": SAP_DEFAULT,
-               "coarse_restart": 30, "coarse_maxit": 300, "coarse_tol": 0.05}
-# alternatives tried on one right-hand side in the solver comparison: P in FP32, two smoother cycles, and more
+               "coarse_restart": 30, "coarse_maxit": 300, "coarse_tol": 0.05, "prec": "f32"}
+# alternatives tried on one right-hand side in the solver comparison: P in FP64, two smoother cycles, and more
 # test vectors with a second setup pass
-AMG_SWEEP = [("p32", dict(AMG_DEFAULT, prec="f32")),
-             ("p32_c2", dict(AMG_DEFAULT, prec="f32", smoother=dict(SAP_DEFAULT, cycles=2))),
-             ("p32_n12_s2_c2", dict(AMG_DEFAULT, prec="f32", ntv=12, setup_iters=2,
-                                    smoother=dict(SAP_DEFAULT, cycles=2)))]
+AMG_SWEEP = [("p64", dict(AMG_DEFAULT, prec="f64")),
+             ("c2", dict(AMG_DEFAULT, smoother=dict(SAP_DEFAULT, cycles=2))),
+             ("n12_s2_c2", dict(AMG_DEFAULT, ntv=12, setup_iters=2, smoother=dict(SAP_DEFAULT, cycles=2)))]
 
 
 def solver_sweep(op, bn, configs):
@@ -256,11 +255,15 @@ def solver_sweep(op, bn, configs):
     import torch
     out = []
     for name, kw in configs:
+        # the workspace is allocated outside the timed region
+        work = torch.empty(op.workspace_bytes(1, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=1,
+                                              sap=kw.get("sap"), amg=kw.get("amg")), dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, st, rc = op.solve(bn, **kw)
+        _, st, rc = op.solve(bn, work=work, wave=1, **kw)
         torch.cuda.synchronize()
         out.append((time.perf_counter() - t, name, kw, st[0]["applies"], rc))
+        del work
     return out
 
 

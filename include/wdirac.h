@@ -200,7 +200,9 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * each work-group's columns forming a 16 (X) x 4 (Y) x block/64 (Z) patch,
  * 5 link-stationary: FP32/FP16S with two-row links, each lane keeps its links
  * and clover on chip for all right-hand sides of the launch, 128-lane
- * work-groups; other precisions and link formats fall back to order 2),
+ * work-groups over the tiles of order 6; other precisions and link formats
+ * fall back to order 2, 6 XCD k takes the (t, z) planes with z = k mod 8,
+ * z-block by z-block and each block's planes in T order),
  * "tchunk" (orders 3 and 4: sites per lane along T, >= 1),
  * "persistent_blocks" (0, the default: dirac_apply_batched launches one
  * work-group per work item; > 0: a persistent grid of at most that many and
@@ -220,8 +222,8 @@ int dirac_tune_get(const char *key, int *value);
  * nrhs right-hand sides in one launch, on temporary device buffers, and keep
  * the fastest for every later launch with the same lattice extents,
  * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...), link format and
- * clover format.  Candidates: tile orders 0, 2, 3, 4 (and 5 for FP32/FP16S
- * with two-row links and several right-hand sides), work-groups of 128/256,
+ * clover format.  Candidates: tile orders 0, 2, 3, 4 (and, for several
+ * right-hand sides, 6, and 5 for FP32/FP16S with two-row links), work-groups of 128/256,
  * T-chunks 2/4/8, register blocks 1/2/4 and, for several right-hand sides, a
  * persistent grid.  The choice is appended to the JSON-lines file named by
  * the environment variable WDIRAC_TUNE_CACHE when it is set; that file is

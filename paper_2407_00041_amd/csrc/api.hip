@@ -309,7 +309,7 @@ int dirac_tune_set(const char *key, int value) {
         if (value < 64 || value > 256 || value % 64) return fail(WDIRAC_EINVAL, "block must be 64, 128, 192 or 256");
         t.block = value;
     } else if (k == "order") {
-        if (value < 0 || value > 5) return fail(WDIRAC_EINVAL, "order must be 0 .. 5");
+        if (value < 0 || value > 6) return fail(WDIRAC_EINVAL, "order must be 0 .. 6");
         t.order = value;
     } else if (k == "tchunk") {
         if (value < 1 || value > 4096) return fail(WDIRAC_EINVAL, "tchunk must be in [1, 4096]");

@@ -29,7 +29,9 @@ constexpr int kOrderTSweep = 2;    // each XCD gets 1/8 of every T-slice; slices
 constexpr int kOrderColumn = 3;    // lanes walk columns along T (register-carried T neighbours)
 constexpr int kOrderPatch = 4;     // as kOrderColumn, a work-group's columns form a z-y-x patch
 constexpr int kOrderStationary = 5;  // FP32/FP16S, two-row links: each lane keeps its links (registers) and
-                                     // clover (LDS) for all right-hand sides of the launch; T-sweep tiles
+                                     // clover (LDS) for all right-hand sides of the launch; plane tiles
+constexpr int kOrderZPlanes = 6;  // XCD k takes the (t, z) planes with z = k mod 8, z-block by z-block, each
+                                   // z-block's planes in T order (tiles of one plane are consecutive)
 constexpr int kPatchX = 16, kPatchY = 4;  // patch extent in X and Y; Z extent = block / 64
 constexpr int kStationaryBlock = 128;     // work-group size of the link-stationary kernel (LDS budget)
 constexpr int kMaxStationaryRhs = 64;     // right-hand sides per link-stationary launch
@@ -52,6 +54,8 @@ struct TileMap {
     int nslots;           // ntiles rounded up to a multiple of 8
     int patches;          // kOrderPatch: patches per T-slice
     int npx, npy, pz;     // kOrderPatch: patches along X and Y, patch extent in Z
+    int nt, nz;           // kOrderZPlanes: lattice extents in T and Z
+    int plane_tiles;      // kOrderZPlanes: tiles per (t, z) plane
 };
 
 TileMap make_tilemap(const Geom &g, int order, int block, int tchunk);

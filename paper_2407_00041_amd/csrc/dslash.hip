@@ -288,6 +288,18 @@ __device__ __forceinline__ void tile_range(const TileMap &m, int vb, int &lo, in
         const int r1 = base + (int)(((long long)(k + 1) * m.slice) >> 3);
         lo = r0 + tile * m.block;
         hi = min(lo + m.block, r1);
+    } else if (m.order == kOrderZPlanes) {
+        const int k = vb & 7, j = vb >> 3;
+        const int q = j / m.plane_tiles, tile = j - q * m.plane_tiles;
+        const int zb = q / m.nt, t = q - zb * m.nt;
+        const int z = zb * 8 + k;
+        const int plane = m.slice / m.nz;
+        lo = hi = 0;
+        if (z < m.nz) {
+            const int base = (t * m.nz + z) * plane;
+            lo = base + tile * m.block;
+            hi = min(lo + m.block, base + plane);
+        }
     } else {
         int tile = vb;
         if (m.order == kOrderXcdChunk) {
@@ -537,6 +549,9 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     m.tchunk = tchunk < 1 ? 1 : (tchunk > g.n[0] ? g.n[0] : tchunk);
     m.patches = m.npx = m.npy = 0;
     m.pz = block / (kPatchX * kPatchY);
+    m.nt = g.n[0];
+    m.nz = g.n[1];
+    m.plane_tiles = 0;
     if (order == kOrderColumn) {
         const int per_range = (m.slice + 7) / 8;
         m.tiles_per_range = (per_range + block - 1) / block;
@@ -547,6 +562,9 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
         m.patches = m.npx * m.npy * ((g.n[1] + m.pz - 1) / m.pz);
         m.tiles_per_range = (m.patches + 7) / 8;
         m.ntiles = (g.n[0] + m.tchunk - 1) / m.tchunk * 8 * m.tiles_per_range;
+    } else if (order == kOrderZPlanes) {
+        m.plane_tiles = (m.slice / m.nz + block - 1) / block;
+        m.ntiles = (m.nz + 7) / 8 * m.nt * m.plane_tiles * 8;
     } else if (order == kOrderTSweep) {
         const int per_range = (m.slice + 7) / 8;
         m.tiles_per_range = (per_range + block - 1) / block;
@@ -667,7 +685,13 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 }
 
 // Link-stationary launch: all right-hand sides of all batches, in groups of
-// kMaxStationaryRhs, one work-group per T-sweep tile of kStationaryBlock sites.
+// kMaxStationaryRhs, one work-group per plane tile of kStationaryBlock sites.
+// Plane tiles (each XCD walks the T-planes of every eighth z in T order)
+// keep a site's T-neighbours in work-groups that run at the same time, a few
+// right-hand sides apart, so their spinors are mostly re-read from the caches;
+// with T-slice tiles the next slice only starts after the current one has
+// walked every right-hand side (measured at 48^3 x 96, 41 RHS: FP32
+// 44.0 -> 39.5 ms, FP16S 27.5 -> 25.7 ms, results bit-identical).
 template <int P, bool DAG>
 static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g,
                                     int apbc, hipStream_t st) {
@@ -677,7 +701,7 @@ static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, cons
         for (int r = 0; r < batches[b].nrhs; r++)
             rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
                              static_cast<char *>(batches[b].out) + r * rb);
-    const TileMap m = make_tilemap(g, kOrderTSweep, kStationaryBlock, 1);
+    const TileMap m = make_tilemap(g, kOrderZPlanes, kStationaryBlock, 1);
     for (size_t r0 = 0; r0 < rhs.size(); r0 += kMaxStationaryRhs) {
         RhsTable tab;
         tab.n = (int)std::min<size_t>(kMaxStationaryRhs, rhs.size() - r0);
@@ -701,7 +725,8 @@ static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData 
     for (int b = 0; b < nbatch; b++) total += batches[b].nrhs;
     if (cfg.order == kOrderStationary) {
         if constexpr (P != WDIRAC_F64) {
-            if (d.rows == 2) return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, st);
+            if (d.rows == 2)
+                return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, st);
         }
         cfg.order = kOrderTSweep;  // FP64 or full links: the register-blocked site kernel
     }

@@ -54,7 +54,7 @@ void load_cache_locked() {
                    "{\"key\": \"%255[^\"]\", \"order\": %d, \"block\": %d, \"tchunk\": %d, \"nr\": %d, "
                    "\"persistent\": %d, \"us\": %lf",
                    key, &c.order, &c.block, &c.tchunk, &c.nr, &c.persistent, &us) == 7) {
-            if (c.order >= 0 && c.order <= 5 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
+            if (c.order >= 0 && c.order <= 6 && c.block >= 64 && c.block <= 256 && c.block % 64 == 0 &&
                 c.tchunk >= 1 && (c.nr == 1 || c.nr == 2 || c.nr == 4) && (c.persistent == 0 || c.persistent == 1))
                 g_table[key] = c;
         }
@@ -103,13 +103,14 @@ extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_ou
         for (int order : {2, 3})
             for (int nr : {1, 2})
                 if (nr <= nrhs) cands.push_back({order, 256, 4, nr, 1});
-    for (int order : {2, 3, 4})
+    for (int order : {2, 3, 4, 6})
         for (int block : {128, 256})
             for (int tchunk : {2, 4, 8}) {
                 if (!is_column_order(order) && tchunk != 4) continue;
                 for (int nr : nrs) {
                     if (nr > 1 && nr > nrhs) continue;
                     if (nrhs == 1 && nr > 1) continue;
+                    if (order == kOrderZPlanes && nrhs == 1) continue;  // measured slower for one RHS
                     if (is_column_order(order) && prec == WDIRAC_F64 && nr > 2) continue;
                     cands.push_back({order, block, tchunk, nr});
                 }

@@ -88,10 +88,12 @@ def test_many_register_blocks_split_launches(restore_tuning):
     assert torch.equal(out, singles(op, nat, "f32", 30))
 
 
-@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("order", [0, 1, 2, 6])
 @pytest.mark.parametrize("block", [64, 128, 192, 256])
-def test_tile_orders_and_blocks(order, block, restore_tuning):
-    dims = (5, 3, 7, 4)          # slices not divisible by 8 or by the block
+@pytest.mark.parametrize("dims", [(5, 3, 7, 4), (3, 11, 4, 6)])
+def test_tile_orders_and_blocks(order, block, dims, restore_tuning):
+    # slices not divisible by 8 or by the block; Z extents below 8 and a ragged
+    # second z-block of eight planes (order 6)
     U, psi = fields(dims, 2)
     op = DiracOp(dims, U, -0.3, 1.0)
     nat = op.pack(to_dev(psi), "f64")
@@ -158,12 +160,13 @@ def test_patch_order_equals_column_order(block, prec, restore_tuning):
 @pytest.mark.parametrize("prec", ["f32", "f16s", "f64"])
 @pytest.mark.parametrize("compress", [True, False])
 @pytest.mark.parametrize("compact", [False, True])
-def test_stationary_order_equals_site_kernel(prec, compress, compact, restore_tuning):
+@pytest.mark.parametrize("dims", [(5, 3, 7, 4), (2, 10, 5, 6)])
+def test_stationary_order_equals_site_kernel(prec, compress, compact, dims, restore_tuning):
     """Tile order 5 (links and clover kept on chip for every right-hand side
     of the launch) runs the site kernel's arithmetic, so results agree bit for
-    bit; 70 right-hand sides in uneven batches need two launches, the lattice
-    leaves a ragged last tile.  FP64 and full links fall back to order 2."""
-    dims = (5, 3, 7, 4)
+    bit; 70 right-hand sides in uneven batches need two launches, the planes
+    leave a ragged last tile, and the second lattice a ragged second z-block
+    of its plane tiles.  FP64 and full links fall back to order 2."""
     sizes = [1, 24, 45]
     n = sum(sizes)
     U, psi = fields(dims, 47, nrhs=n)
@@ -203,6 +206,8 @@ def test_batched_argument_errors(restore_tuning):
         tune_set("block", 100)
     with pytest.raises(WdiracError):
         tune_set("nosuchkey", 1)
+    with pytest.raises(WdiracError):
+        tune_set("order", 7)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
