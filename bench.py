@@ -230,6 +230,8 @@ def batched_run(torch, op, dims, stream, steps):
     tuned = {"fixed": True} if TUNE_FIXED else op.autotune("f32", n)
     ms = time_launches(torch, lambda: op.apply_batched(batches, "f32", stream=stream), steps, 3, stream)
     res = {"batches": sizes, "prec": "f32", "ms_per_launch": ms, "rhs_applies_per_s": n * 1000.0 / ms,
+           "note": "ms_per_launch is one dirac_apply_batched call (the link-stationary kernel may split it into "
+                   "launches of launch.tchunk right-hand sides)",
            "alg_GBps": (LINK_BYTES["f32"] + CLOVER_BYTES["f32"] + 192 * n) * op.V / (ms * 1e-3) / 1e9,
            "launch": tuned}
     del outs, batches, nat
@@ -267,6 +269,12 @@ def solver_sweep(op, bn, configs):
     return out
 
 
+def amg_pass_bytes(ntv, prec):
+    """Algorithmic bytes per fine site of one restriction or prolongation: the ntv interpolation columns (12
+    complex entries per site, FP64 or FP32) and the FP64 fine field."""
+    return ntv * (192 if prec == "f64" else 96) + 192
+
+
 def amg_run(torch, op, dims, stream, steps=10):
     """The two-level multigrid of the benchmark: setup time (from seeded Gaussian test vectors), then its kernels
     (restriction, prolongation, coarse operator) and one application of M timed on one right-hand side.  Returns
@@ -294,7 +302,7 @@ def amg_run(torch, op, dims, stream, steps=10):
     torch.cuda.synchronize()
     ms_m = (time.perf_counter() - t) / 3 * 1e3
     s1 = mg.stats()
-    rp = (N + 1) * 192 * V
+    rp = amg_pass_bytes(N, AMG_DEFAULT.get("prec", "f64")) * V
     rc = mg.Vc * (5 * 4 * N * N + 4 * N) * 16
     res = {"params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in AMG_DEFAULT.items() if k != "smoother"},
            "smoother": {k: (list(v) if isinstance(v, tuple) else v) for k, v in AMG_DEFAULT["smoother"].items()},
@@ -596,8 +604,9 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
         del x, y
     torch.cuda.synchronize()
     log("[suite] single applies done")
-    # one FP32 launch over batches {1, 4, 12, 24}: the link-stationary kernel
-    _fixed(wd, 5, 128, 1, 1)
+    # one FP32 apply over batches {1, 4, 12, 24}: the link-stationary kernel in launches of 6 right-hand sides
+    group = 6
+    _fixed(wd, 5, 128, group, 1)
     sizes = [1, 4, 12, 24]
     n = sum(sizes)
     nat = op.pack(synth.gaussian_spinor(dims, 2100, nrhs=n, device="cuda"), "f32")
@@ -610,8 +619,10 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
         r0 += k
     for _ in range(2):
         op.apply_batched(batches, "f32", stream=st)
-    add(r"dslash_stationary_kernel<1, false>", 2, 2 * (LINK_BYTES["f32"] + CLOVER_BYTES["f32"] + 192 * n) * V,
-        "batched FP32 apply, 41 RHS in batches {1,4,12,24}")
+    nl = -(-n // group)
+    add(r"dslash_stationary_kernel<1, false>", 2 * nl,
+        2 * (nl * (LINK_BYTES["f32"] + CLOVER_BYTES["f32"]) + 192 * n) * V,
+        f"batched FP32 apply, 41 RHS in batches {{1,4,12,24}}, launches of {group} RHS")
     del outs, batches, nat
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -651,8 +662,9 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
         mg.prolong(c)
         mg.coarse_apply(c)
     torch.cuda.synchronize()
-    add(r"k_restrict", 4, 4 * (N + 1) * 192 * V, f"AMG restriction P^H f ({N} FP64 test vectors)")
-    add(r"k_prolong", 3, 3 * (N + 1) * 192 * V, f"AMG prolongation P c ({N} FP64 test vectors)")
+    pp = AMG_DEFAULT.get("prec", "f64")
+    add(r"k_restrict", 4, 4 * amg_pass_bytes(N, pp) * V, f"AMG restriction P^H f ({N} test vectors, P in {pp})")
+    add(r"k_prolong", 3, 3 * amg_pass_bytes(N, pp) * V, f"AMG prolongation P c ({N} test vectors, P in {pp})")
     add(r"k_coarse_apply", 3, 3 * mg.Vc * (5 * 4 * N * N + 4 * N) * 16,
         "AMG coarse operator D_c (self + 4 forward blocks once, vectors in and out)")
     mg.close()
@@ -829,9 +841,10 @@ def kernel_table(extra, V):
             extra["sap"]["flop_per_cycle"])
     if "amg" in extra:
         m = extra["amg"]
-        row("k_restrict", "AMG restriction P^H f, FP64, 8 test vectors", m["restrict_ms"], m["restrict_alg_bytes"],
-            "k_restrict")
-        row("k_prolong", "AMG prolongation P c, FP64, 8 test vectors", m["prolong_ms"], m["restrict_alg_bytes"],
+        pp = m["params"].get("prec", "f64")
+        row("k_restrict", f"AMG restriction P^H f, P in {pp}, 8 test vectors", m["restrict_ms"],
+            m["restrict_alg_bytes"], "k_restrict")
+        row("k_prolong", f"AMG prolongation P c, P in {pp}, 8 test vectors", m["prolong_ms"], m["restrict_alg_bytes"],
             "k_prolong")
         row("k_coarse_apply", "AMG coarse operator D_c, FP64", m["coarse_apply_ms"], m["coarse_apply_alg_bytes"],
             "k_coarse_apply")

@@ -203,7 +203,9 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * work-groups over the tiles of order 6; other precisions and link formats
  * fall back to order 2, 6 XCD k takes the (t, z) planes with z = k mod 8,
  * z-block by z-block and each block's planes in T order),
- * "tchunk" (orders 3 and 4: sites per lane along T, >= 1),
+ * "tchunk" (orders 3 and 4: sites per lane along T, >= 1; order 5:
+ * right-hand sides per launch, the launch split into groups of that many,
+ * 1 or >= 64 for all in one launch),
  * "persistent_blocks" (0, the default: dirac_apply_batched launches one
  * work-group per work item; > 0: a persistent grid of at most that many and
  * at most the co-resident work-groups, each walking the item list),
@@ -223,7 +225,8 @@ int dirac_tune_get(const char *key, int *value);
  * the fastest for every later launch with the same lattice extents,
  * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...), link format and
  * clover format.  Candidates: tile orders 0, 2, 3, 4 (and, for several
- * right-hand sides, 6, and 5 for FP32/FP16S with two-row links), work-groups of 128/256,
+ * right-hand sides, 6, and 5 for FP32/FP16S with two-row links, in one
+ * launch or groups of 4, 6, 8 or 12 right-hand sides), work-groups of 128/256,
  * T-chunks 2/4/8, register blocks 1/2/4 and, for several right-hand sides, a
  * persistent grid.  The choice is appended to the JSON-lines file named by
  * the environment variable WDIRAC_TUNE_CACHE when it is set; that file is

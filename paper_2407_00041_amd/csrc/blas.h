@@ -31,18 +31,15 @@ constexpr int kMdotChunks = kRedBlocks;
 __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restrict__ partial, int ngroups, int stride,
                                                         double2 *__restrict__ out);
 
-// out[i] = <v_i, w> = v_i^H w for i < nv (passes of kMdot vectors),
-// out[nv].x = |w|^2; partial needs kRedBlocks * (kMdot + 1) entries.  S = double2 (FP64 storage).
-template <typename S>
-hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
-                hipStream_t st);
-// the same in one launch per kGS vectors (w read about once from HBM, see
-// k_mdot_all); partial as documented at kMdotChunks
+// out[i] = <v_i, w> = v_i^H w for i < nv, out[nv].x = |w|^2, in one launch per
+// kGS vectors (w read about once from HBM, see k_mdot_all); partial as
+// documented at kMdotChunks.  S = double2 (FP64 storage).
 template <typename S>
 hipError_t mdot_all(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
                     hipStream_t st);
 // w -= sum_i coef[i] cscale[i] v_i (coef on the device, cscale on the host or
-// null for 1); norm_out[0].x = |w_new|^2 when norm_out != null
+// null for 1); norm_out[0].x = |w_new|^2 when norm_out != null.  partial needs
+// kRedBlocks + kGS entries (norm partials, then the scaled coefficients of a pass)
 template <typename S>
 hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, const double *cscale, void *w, long long N,
                       double2 *partial, double2 *norm_out, hipStream_t st);

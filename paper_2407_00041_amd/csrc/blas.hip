@@ -48,33 +48,29 @@ __device__ __forceinline__ void block_reduce(double2 (&v)[NV], double2 *lds) {
     }
 }
 
-// partial[blk][i] = sum conj(v_i) w over the group's elements (i < nv),
-// partial[blk][kMdot] = sum |w|^2 (real part)
-template <typename S>
-__global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__restrict__ w,
-                                                       double2 *__restrict__ partial, long long N) {
-    __shared__ double2 lds[(kMdot + 1) * kRedThreads];
-    double2 acc[kMdot + 1];
-#pragma unroll
-    for (int i = 0; i <= kMdot; i++) acc[i] = make_double2(0, 0);
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+// Inner products of w with up to kGS basis vectors in ONE launch.  The grid
+// is (vector group of kMdot, element chunk) work-groups, dealt so that the
+// groups of one chunk are consecutive work-groups of the same XCD (the
+// hardware hands work-groups to the 8 XCDs round-robin): after the first
+// group, a chunk of w comes from that XCD's L2, so w crosses HBM about once
+// whatever the number of vectors.  partial[(chunk * ngroups + group) *
+// (kMdot + 1) + i] = sum conj(v_{kMdot group + i}) w over the chunk; column
+// kMdot of group 0 holds sum |w|^2.
+template <typename S, int NV>
+__device__ __forceinline__ void mdot_chunk(const VecList &vl, int i0, const S *__restrict__ w, long long e0,
+                                           long long stride, long long N, double2 (&acc)[kMdot + 1]) {
+    for (long long e = e0; e < N; e += stride) {
         const double2 we = Elem<S>::ld(w, e);
+        double2 vv[NV > 0 ? NV : 1];
+#pragma unroll
+        for (int i = 0; i < NV; i++) vv[i] = Elem<S>::ld(static_cast<const S *>(vl.v[i0 + i]), e);
         acc[kMdot].x += we.x * we.x + we.y * we.y;
 #pragma unroll
-        for (int i = 0; i < kMdot; i++) {
-            if (i < vl.n) {
-                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
-                const double2 p = cj_mul(vi, we);
-                acc[i].x += p.x;
-                acc[i].y += p.y;
-            }
+        for (int i = 0; i < NV; i++) {
+            const double2 p = cj_mul(vv[i], we);
+            acc[i].x += p.x;
+            acc[i].y += p.y;
         }
-    }
-    block_reduce<kMdot + 1>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i <= kMdot; i++) partial[(size_t)blockIdx.x * (kMdot + 1) + i] = acc[i];
     }
 }
 
@@ -85,32 +81,24 @@ __global__ __launch_bounds__(kRedThreads) void k_mdot(VecList vl, const S *__res
 // group, a chunk of w comes from that XCD's L2, so w crosses HBM about once
 // whatever the number of vectors.  partial[(chunk * ngroups + group) *
 // (kMdot + 1) + i] = sum conj(v_{kMdot group + i}) w over the chunk; column
-// kMdot of group 0 holds sum |w|^2.
-template <typename S>
+// kMdot holds sum |w|^2 (read from group 0).  Every group but the last has
+// kMdot vectors, the last NL (a template parameter, so that each element's
+// loads of all vectors are issued together, without a branch between them).
+template <typename S, int NL>
 __global__ __launch_bounds__(kRedThreads) void k_mdot_all(VecList vl, const S *__restrict__ w,
                                                            double2 *__restrict__ partial, long long N, int ngroups,
                                                            int nchunks) {
     __shared__ double2 lds[(kMdot + 1) * kRedThreads];
     const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
     const int group = q % ngroups, chunk = (q / ngroups) * 8 + xcd;
-    const int i0 = group * kMdot;
     double2 acc[kMdot + 1];
 #pragma unroll
     for (int i = 0; i <= kMdot; i++) acc[i] = make_double2(0, 0);
-    const long long stride = (long long)nchunks * blockDim.x;
-    for (long long e = (long long)chunk * blockDim.x + threadIdx.x; e < N; e += stride) {
-        const double2 we = Elem<S>::ld(w, e);
-        if (group == 0) acc[kMdot].x += we.x * we.x + we.y * we.y;
-#pragma unroll
-        for (int i = 0; i < kMdot; i++) {
-            if (i0 + i < vl.n) {
-                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i0 + i]), e);
-                const double2 p = cj_mul(vi, we);
-                acc[i].x += p.x;
-                acc[i].y += p.y;
-            }
-        }
-    }
+    const long long stride = (long long)nchunks * blockDim.x, e0 = (long long)chunk * blockDim.x + threadIdx.x;
+    if (group < ngroups - 1)
+        mdot_chunk<S, kMdot>(vl, group * kMdot, w, e0, stride, N, acc);
+    else
+        mdot_chunk<S, NL>(vl, group * kMdot, w, e0, stride, N, acc);
     block_reduce<kMdot + 1>(acc, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -150,29 +138,32 @@ __global__ __launch_bounds__(kRedThreads) void k_colsum(const double2 *__restric
     if (threadIdx.x == 0) out[blockIdx.x] = a[0];
 }
 
-// w -= sum_i coef[i] v_i (i < nv); partial[blk] = sum |w_new|^2 if partial
-template <typename S>
-__global__ __launch_bounds__(kRedThreads) void k_axpy_multi(VecList vl, const double2 *__restrict__ coef,
-                                                             ScaleList sl, S *__restrict__ w,
-                                                             double2 *__restrict__ partial, long long N) {
+// cs[i] = coef[i] * sl.s[i], i < n (one work-group of kGS lanes)
+__global__ void k_scale_coef(const double2 *__restrict__ coef, ScaleList sl, int n, double2 *__restrict__ cs) {
+    const int i = threadIdx.x;
+    if (i < n) cs[i] = make_double2(coef[i].x * sl.s[i], coef[i].y * sl.s[i]);
+}
+
+// w -= sum_i cs[i] v_i over NV vectors (a template parameter: the loads of all NV vectors of an element are issued
+// together; the coefficients are read with uniform addresses, so they stay in scalar registers);
+// partial[blk] = sum |w_new|^2 if partial
+template <typename S, int NV>
+__global__ __launch_bounds__(kRedThreads) void k_axpy_multi(VecList vl, const double2 *__restrict__ cs,
+                                                             S *__restrict__ w, double2 *__restrict__ partial,
+                                                             long long N) {
     __shared__ double2 lds[kRedThreads];
-    double2 c[kGS];
-#pragma unroll
-    for (int i = 0; i < kGS; i++) {
-        const double2 ci = i < vl.n ? coef[i] : make_double2(0, 0);
-        c[i] = make_double2(ci.x * sl.s[i], ci.y * sl.s[i]);
-    }
     double2 nrm[1] = {make_double2(0, 0)};
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
         double2 we = Elem<S>::ld(w, e);
+        double2 vv[NV];
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
-            if (i < vl.n) {
-                const double2 vi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
-                we.x -= c[i].x * vi.x - c[i].y * vi.y;
-                we.y -= c[i].x * vi.y + c[i].y * vi.x;
-            }
+        for (int i = 0; i < NV; i++) vv[i] = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const double2 c = cs[i];
+            we.x -= c.x * vv[i].x - c.y * vv[i].y;
+            we.y -= c.x * vv[i].y + c.y * vv[i].x;
         }
         Elem<S>::st(w, e, we);
         nrm[0].x += we.x * we.x + we.y * we.y;
@@ -213,21 +204,21 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(const double2 *__restr
     if (threadIdx.x == 0) partial[blockIdx.x] = nrm[0];
 }
 
-// x += sum_i c_i z_i (x FP64, z of storage S; coefficients passed by value)
-template <typename S>
+// x += sum_i c_i z_i over NV vectors (x FP64, z of storage S; coefficients passed by value)
+template <typename S, int NV>
 __global__ __launch_bounds__(kRedThreads) void k_update(VecList vl, CoefList cl, double2 *__restrict__ x,
                                                          long long N) {
     const double2 *c = cl.c;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
         double2 xe = x[e];
+        double2 zz[NV];
 #pragma unroll
-        for (int i = 0; i < kGS; i++) {
-            if (i < vl.n) {
-                const double2 zi = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
-                xe.x += c[i].x * zi.x - c[i].y * zi.y;
-                xe.y += c[i].x * zi.y + c[i].y * zi.x;
-            }
+        for (int i = 0; i < NV; i++) zz[i] = Elem<S>::ld(static_cast<const S *>(vl.v[i]), e);
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            xe.x += c[i].x * zz[i].x - c[i].y * zz[i].y;
+            xe.y += c[i].x * zz[i].y + c[i].y * zz[i].x;
         }
         x[e] = xe;
     }
@@ -236,30 +227,15 @@ __global__ __launch_bounds__(kRedThreads) void k_update(VecList vl, CoefList cl,
 // ---------------------------------------------------------------------------
 // launchers
 
+// one case per vector count of a pass, 1 .. kGS
+#define WD_NV_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+static_assert(kGS == 32, "WD_NV_CASES lists 1 .. kGS");
+
 static int red_grid(long long N) {
     long long g = (N + kRedThreads - 1) / kRedThreads;
     return (int)(g < kRedBlocks ? g : kRedBlocks);
-}
-
-template <typename S>
-hipError_t mdot(const void *const *v, int nv, const void *w, long long N, double2 *partial, double2 *out,
-                hipStream_t st) {
-    // out[0..nv) = <v_i, w>, out[nv] = |w|^2 (real part), in passes of kMdot vectors
-    const int G = red_grid(N);
-    for (int i0 = 0; i0 < nv || i0 == 0; i0 += kMdot) {
-        VecList vl;
-        vl.n = nv - i0 < kMdot ? nv - i0 : kMdot;
-        if (vl.n < 0) vl.n = 0;
-        for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
-        hipLaunchKernelGGL(k_mdot<S>, dim3(G), dim3(kRedThreads), 0, st, vl, static_cast<const S *>(w), partial, N);
-        if (vl.n > 0)
-            hipLaunchKernelGGL(k_colsum, dim3(vl.n), dim3(kRedThreads), 0, st, partial, G, kMdot + 1, out + i0);
-        if (i0 + kMdot >= nv) {
-            hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial + kMdot, G, kMdot + 1, out + nv);
-            break;
-        }
-    }
-    return hipGetLastError();
 }
 
 template <typename S>
@@ -272,8 +248,17 @@ hipError_t mdot_all(const void *const *v, int nv, const void *w, long long N, do
         if (vl.n < 0) vl.n = 0;
         for (int i = 0; i < kGS; i++) vl.v[i] = i < vl.n ? v[i0 + i] : w;
         const int ngroups = vl.n > 0 ? (vl.n + kMdot - 1) / kMdot : 1;
-        hipLaunchKernelGGL(k_mdot_all<S>, dim3(nchunks * ngroups), dim3(kRedThreads), 0, st, vl,
-                           static_cast<const S *>(w), partial, N, ngroups, nchunks);
+        const int nl = vl.n - (ngroups - 1) * kMdot;  // vectors of the last group (0 with none: |w|^2 only)
+        const dim3 grid(nchunks * ngroups), blk(kRedThreads);
+        const S *ws = static_cast<const S *>(w);
+        switch (nl) {
+#define WD_MDOT_CASE(n) \
+    case n: hipLaunchKernelGGL((k_mdot_all<S, n>), grid, blk, 0, st, vl, ws, partial, N, ngroups, nchunks); break;
+            WD_MDOT_CASE(0) WD_MDOT_CASE(1) WD_MDOT_CASE(2) WD_MDOT_CASE(3) WD_MDOT_CASE(4)
+            WD_MDOT_CASE(5) WD_MDOT_CASE(6) WD_MDOT_CASE(7) WD_MDOT_CASE(8)
+#undef WD_MDOT_CASE
+        default: return hipErrorInvalidValue;
+        }
         const bool last = i0 + kGS >= nv;
         // outputs of this launch: its vl.n products, plus |w|^2 after the last one
         hipLaunchKernelGGL(k_colsum_groups, dim3(vl.n + (last ? 1 : 0)), dim3(kRedThreads), 0, st, partial, nchunks,
@@ -296,8 +281,18 @@ hipError_t axpy_multi(const void *const *v, int nv, const double2 *coef, const d
             sl.s[i] = (i < vl.n && cscale) ? cscale[i0 + i] : 1.0;
         }
         const bool last = i0 + kGS >= nv;
-        hipLaunchKernelGGL(k_axpy_multi<S>, dim3(G), dim3(kRedThreads), 0, st, vl, coef + i0, sl, static_cast<S *>(w),
-                           (last && norm_out) ? partial : (double2 *)nullptr, N);
+        double2 *pt = (last && norm_out) ? partial : (double2 *)nullptr;
+        S *ws = static_cast<S *>(w);
+        // scaled coefficients after the first kRedBlocks entries of partial (the norm partials of this pass)
+        double2 *cs = partial + kRedBlocks;
+        hipLaunchKernelGGL(k_scale_coef, dim3(1), dim3(kGS), 0, st, coef + i0, sl, vl.n, cs);
+        switch (vl.n) {
+#define WD_AXPY_CASE(n) \
+    case n: hipLaunchKernelGGL((k_axpy_multi<S, n>), dim3(G), dim3(kRedThreads), 0, st, vl, cs, ws, pt, N); break;
+            WD_NV_CASES(WD_AXPY_CASE)
+#undef WD_AXPY_CASE
+        default: return hipErrorInvalidValue;
+        }
         if (last && norm_out)
             hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kRedThreads), 0, st, partial, G, 1, norm_out);
     }
@@ -330,12 +325,17 @@ hipError_t update(const void *const *z, int nz, const double2 *coef, double2 *x,
             vl.v[i] = i < vl.n ? z[i0 + i] : x;
             cl.c[i] = i < vl.n ? coef[i0 + i] : make_double2(0, 0);
         }
-        hipLaunchKernelGGL(k_update<S>, dim3(red_grid(N)), dim3(kRedThreads), 0, st, vl, cl, x, N);
+        switch (vl.n) {
+#define WD_UPDATE_CASE(n) \
+    case n: hipLaunchKernelGGL((k_update<S, n>), dim3(red_grid(N)), dim3(kRedThreads), 0, st, vl, cl, x, N); break;
+            WD_NV_CASES(WD_UPDATE_CASE)
+#undef WD_UPDATE_CASE
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
 
-template hipError_t mdot<double2>(const void *const *, int, const void *, long long, double2 *, double2 *, hipStream_t);
 template hipError_t mdot_all<double2>(const void *const *, int, const void *, long long, double2 *, double2 *,
                                       hipStream_t);
 template hipError_t axpy_multi<double2>(const void *const *, int, const double2 *, const double *, void *, long long,

@@ -685,7 +685,12 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 }
 
 // Link-stationary launch: all right-hand sides of all batches, in groups of
-// kMaxStationaryRhs, one work-group per plane tile of kStationaryBlock sites.
+// `group` (2 .. kMaxStationaryRhs - 1; else kMaxStationaryRhs) per launch,
+// one work-group per plane tile of kStationaryBlock sites.  Smaller groups
+// re-read the links and clover once per group but shorten the time between
+// the uses of a neighbour spinor by work-groups of neighbouring planes
+// (measured, FP32, 41 RHS at 48^3 x 96: groups of 6 36.4 ms, all in one
+// launch 39.7 ms; FP16S is fastest in one launch).
 // Plane tiles (each XCD walks the T-planes of every eighth z in T order)
 // keep a site's T-neighbours in work-groups that run at the same time, a few
 // right-hand sides apart, so their spinors are mostly re-read from the caches;
@@ -694,7 +699,7 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 // 44.0 -> 39.5 ms, FP16S 27.5 -> 25.7 ms, results bit-identical).
 template <int P, bool DAG>
 static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g,
-                                    int apbc, hipStream_t st) {
+                                    int apbc, int group, hipStream_t st) {
     const size_t rb = field_rhs_bytes(P, g.V);
     std::vector<std::pair<const void *, void *>> rhs;
     for (int b = 0; b < nbatch; b++)
@@ -702,9 +707,10 @@ static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, cons
             rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
                              static_cast<char *>(batches[b].out) + r * rb);
     const TileMap m = make_tilemap(g, kOrderZPlanes, kStationaryBlock, 1);
-    for (size_t r0 = 0; r0 < rhs.size(); r0 += kMaxStationaryRhs) {
+    const size_t grp = (group >= 2 && group < kMaxStationaryRhs) ? (size_t)group : (size_t)kMaxStationaryRhs;
+    for (size_t r0 = 0; r0 < rhs.size(); r0 += grp) {
         RhsTable tab;
-        tab.n = (int)std::min<size_t>(kMaxStationaryRhs, rhs.size() - r0);
+        tab.n = (int)std::min(grp, rhs.size() - r0);
         for (int i = 0; i < kMaxStationaryRhs; i++) {
             const size_t k = r0 + std::min(i, tab.n - 1);
             tab.in[i] = rhs[k].first;
@@ -726,7 +732,7 @@ static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData 
     if (cfg.order == kOrderStationary) {
         if constexpr (P != WDIRAC_F64) {
             if (d.rows == 2)
-                return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, st);
+                return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, cfg.tchunk, st);
         }
         cfg.order = kOrderTSweep;  // FP64 or full links: the register-blocked site kernel
     }

@@ -65,10 +65,11 @@ def test_full_size_fp64_fgmres30(schur):
 
 
 def test_full_size_41_rhs_batched_launch(restore_tuning):
-    """48^3 x 96, FP32, two-row links, compact clover: the benchmark's one launch
+    """48^3 x 96, FP32, two-row links, compact clover: the benchmark's one call
     over uneven batches {1, 4, 12, 24} (41 right-hand sides), in the
-    link-stationary configuration its autotuner selects; 300 sampled sites of
-    every right-hand side against the oracle."""
+    configuration its autotuner selects and in the link-stationary kernel with
+    launches of 6 right-hand sides; 300 sampled sites of every right-hand side
+    against the oracle."""
     m0, csw = -0.35, 1.0
     U = _links(DIMS48, 1003)
     op = DiracOp(DIMS48, U, m0, csw, precisions=("f64", "f32"), compress_links=True, compress_clover=True)
@@ -85,22 +86,27 @@ def test_full_size_41_rhs_batched_launch(restore_tuning):
     del psid
     torch.cuda.empty_cache()
     rb = op.field_bytes("f32", 1)
-    for k, v in (("order", 5), ("block", 128), ("tchunk", 1), ("nr_f32", 1)):
-        tune_set(k, v)
-    outs, batches, r0 = [], [], 0
-    for s in sizes:
-        o = op.empty("f32", s)
-        outs.append(o)
-        batches.append((o, nat[r0 * rb:(r0 + s) * rb], s))
-        r0 += s
-    op.apply_batched(batches, "f32")
-    r0 = 0
-    for o, s in zip(outs, sizes):
-        got = op.unpack(o, "f32", s).reshape(s, V, 12)[:, st].cpu().numpy()
-        for k in range(s):
-            assert rel_l2(got[k], want[r0 + k]) < TOL["f32"], (s, k)
-        r0 += s
-    del outs, batches, nat, op
+    tune_set("explicit", 0)
+    cfg = op.autotune("f32", n)
+    for explicit in (False, True):
+        if explicit:
+            for k, v in (("order", 5), ("block", 128), ("tchunk", 6), ("nr_f32", 1)):
+                tune_set(k, v)
+        outs, batches, r0 = [], [], 0
+        for s in sizes:
+            o = op.empty("f32", s)
+            outs.append(o)
+            batches.append((o, nat[r0 * rb:(r0 + s) * rb], s))
+            r0 += s
+        op.apply_batched(batches, "f32")
+        r0 = 0
+        for o, s in zip(outs, sizes):
+            got = op.unpack(o, "f32", s).reshape(s, V, 12)[:, st].cpu().numpy()
+            for k in range(s):
+                assert rel_l2(got[k], want[r0 + k]) < TOL["f32"], (explicit, cfg, s, k)
+            r0 += s
+        del outs, batches
+    del nat, op
     torch.cuda.empty_cache()
 
 
