@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--summarize", nargs=5, metavar=("MANIFEST", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "OUT_MD"),
                     help="join a kernel-suite manifest with rocprofv3 output into a summary and exit (no GPU)")
     ap.add_argument("--summary-command", default="", help="command text recorded in the summary")
+    ap.add_argument("--summarize-headline", nargs=3, metavar=("TRACE_DIR", "BENCH_LOG", "OUT_MD"),
+                    help="summarize a rocprofv3 kernel trace of the default FP64 bench run (the last steps + warmup "
+                         "dispatches of its stencil kernel) against the bench's own timing, and exit (no GPU)")
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the oracle FGMRES solves to convergence instead of a bounded sample")
     return ap.parse_args()
@@ -746,6 +749,41 @@ def _find(d, suffix):
     return hits[0]
 
 
+def summarize_headline(trace_dir, bench_log, out_md, command):
+    """The timed FP64 stencil launches of one bench run under rocprofv3 --kernel-trace: the bench times
+    `warmup + steps` launches of its autotuned kernel last (autotuning launches of the same kernel come
+    earlier), so the last that many dispatches of that kernel are the timed ones."""
+    text = open(bench_log).read()
+    j = json.loads(next(ln for ln in reversed(text.splitlines()) if ln.startswith("{")))
+    kern, n = j["roofline"]["kernel"], j["steps"] + j["warmup"]
+    ev = next(ln for ln in text.splitlines() if ln.startswith("[bench] FP64:"))
+    kt = sorted(_read_csv(_find(trace_dir, "kernel_trace.csv")), key=lambda r: int(r["Dispatch_Id"]))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in kt
+            if r["Kernel_Name"].startswith("void " + kern + "(") or r["Kernel_Name"].startswith(kern + "(")]
+    seen, durs = len(durs), durs[-n:]
+    avg = sum(durs) / len(durs)
+    alg = j["roofline"]["alg_bytes_per_launch"]
+    stats = _read_csv(_find(trace_dir, "kernel_stats.csv"))
+    lines = [f"# FP64 Wilson-clover stencil, 48^3 x 96, one RHS: kernel trace of the bench command", "",
+             "Command (repo root, MI355X):", "", "```", command, "```", "",
+             f"Kernel `{kern}` (launch {json.dumps(j['extra']['f64']['launch'])}).",
+             f"Bench's own HIP-event timing in the same run: `{ev.strip()}`.", "",
+             f"Timed dispatches (the last {n} of {seen}; earlier ones are the autotuner's candidates): average "
+             f"{avg:.1f} us (min {min(durs):.1f}, max {max(durs):.1f}). Algorithmic bytes per launch "
+             f"{j['roofline']['alg_bytes_per_site']} B/site x {j['config']['sites']} sites = {alg / 1e9:.2f} GB -> "
+             f"{alg / (avg * 1e-6) / 1e9:.0f} GB/s = {alg / (avg * 1e-6) / 1e9 / HBM_PEAK_GBS:.3f} of 8 TB/s.", "",
+             "Top kernels of the whole run (input generation, operator setup and autotuning included):", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]:
+        name = r["Name"] if len(r["Name"]) < 110 else r["Name"][:60] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    lines += ["", f"kernel_source_sha256_16: {kernel_hash()}", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    log(f"[bench] wrote {out_md}")
+
+
 def summarize_profile(manifest_path, trace_dir, fetch_dir, write_dir, out_md, command):
     """Join the suite's manifest with rocprofv3 output: per kernel pattern the
     dispatch count, average duration, algorithmic GB/s, and the counter bytes
@@ -965,6 +1003,9 @@ def main():
     os.environ.setdefault("OMP_PROC_BIND", "close")
     a = parse()
     TUNE_FIXED = bool(a.fixed_launch)
+    if a.summarize_headline:
+        summarize_headline(*a.summarize_headline, command=a.summary_command)
+        return
     if a.summarize:
         summarize_profile(*a.summarize, command=a.summary_command)
         return
