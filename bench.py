@@ -61,6 +61,8 @@ KERNEL_SOURCES = ["paper_2407_00041_amd/csrc/dslash.hip", "paper_2407_00041_amd/
 TRAFFIC_PROFILE = "profiles/dslash_f64_48x96_hbm_traffic.md"
 # mixed solver: FP64 outer FGMRES, inner GMRES on the reduced-precision operator
 MIXED = {"mode": "mixed_f16s", "restart": 8, "inner_restart": 10, "inner_tol": 0.1}
+# (outer restart, inner restart, inner tolerance) of the mixed solver tried on one right-hand side, on D and on S
+MIXED_SWEEP = [(8, 10, 0.1), (8, 10, 0.05), (8, 16, 0.05), (16, 10, 0.05), (8, 6, 0.2)]
 TUNE_FIXED = False
 
 
@@ -262,7 +264,8 @@ def solver_sweep(op, bn, configs):
     for name, kw in configs:
         # the workspace is allocated outside the timed region
         work = torch.empty(op.workspace_bytes(1, kw["restart"], kw["mode"], kw.get("inner_restart", 30), wave=1,
-                                              sap=kw.get("sap"), amg=kw.get("amg")), dtype=torch.uint8, device="cuda")
+                                              schur=kw.get("schur", False), sap=kw.get("sap"), amg=kw.get("amg")),
+                           dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, st, rc = op.solve(bn, work=work, wave=1, **kw)
@@ -320,14 +323,14 @@ def amg_run(torch, op, dims, stream, steps=10):
 def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
     """12 right-hand sides to 1e-10, in waves sized to the free HBM, by every
     solver: plain FP64 FGMRES(30) (the reference), plain FP64 at the restart a
-    one-RHS sweep picks, the mixed FP64/FP16S solver at its tuned restart 8 and
-    at restart 30, FGMRES with the SAP preconditioner, FP64 and mixed on the
-    even-odd reduced system, and FGMRES with the two-level multigrid (one
-    setup for all right-hand sides).  Times are summed over the waves; errors
+    one-RHS sweep picks, the mixed FP64/FP16S solver at the (outer restart,
+    inner restart, inner tolerance) a one-RHS sweep picks and at outer restart
+    30, FGMRES with the SAP preconditioner, FP64 and mixed on the even-odd
+    reduced system (the mixed one swept on S), and FGMRES with the two-level
+    multigrid (one setup for all right-hand sides).  Times are summed over the waves; errors
     are against the FP64 FGMRES(30) solution."""
     from paper_2407_00041_amd import synth
     base = dict(tol=1e-10)
-    inner = dict(inner_restart=MIXED["inner_restart"], inner_tol=MIXED["inner_tol"], inner_maxit=MIXED["inner_restart"])
     b1 = op.pack(synth.gaussian_spinor(dims, 3000, nrhs=1, device="cuda"), "f64")
     for n in (1, 2, 3):       # batched applies of the solvers' waves
         if not TUNE_FIXED:
@@ -340,24 +343,35 @@ def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
                                                                 sap=dict(SAP_DEFAULT, cycles=c, mr_iters=k)))
                                       for m in (10, 16) for c, k in ((1, 4), (2, 4), (1, 6))])
     best_sap = min(sweep_sap)
+    sweep_mixed = {}
+    for schur in (False, True):
+        sweep_mixed[schur] = solver_sweep(
+            op, b1, [(f"r{o} i{ir} t{t}", dict(base, restart=o, maxit=500, mode=MIXED["mode"], schur=schur,
+                                               inner_restart=ir, inner_tol=t, inner_maxit=ir))
+                     for o, ir, t in MIXED_SWEEP])
+    best_mixed = {k: min(v) for k, v in sweep_mixed.items()}
     log("[bench] fp64 restart sweep " + ", ".join(f"{n} {t:.2f}s/{a}" for t, n, _, a, _ in sweep64))
     log("[bench] sap sweep " + ", ".join(f"{n} {t:.3f}s/{a}" for t, n, _, a, _ in sweep_sap))
+    for schur in (False, True):
+        log(f"[bench] mixed sweep{' on S' if schur else ''} " +
+            ", ".join(f"{n} {t:.3f}s/{a}" for t, n, _, a, _ in sweep_mixed[schur]))
     del b1
+
+    def mixed_desc(kw, what):
+        return (f"FP64 FGMRES({kw['restart']}){what}, preconditioner inner GMRES({kw['inner_restart']}) on the FP16S "
+                f"operator (relative tol {kw['inner_tol']}), the fastest of a one-RHS sweep")
     solvers = [
         ("fp64", "FGMRES(30), FP64", dict(base, restart=30, maxit=5000, mode="f64")),
         ("fp64_best_restart", f"FGMRES({best64[2]['restart']}), FP64 (fastest restart of 10/16/20/30/50 on one RHS)",
          best64[2]),
-        ("mixed", f"FP64 FGMRES({MIXED['restart']}), preconditioner inner GMRES({MIXED['inner_restart']}) on the "
-                  f"FP16S operator (relative tol {MIXED['inner_tol']})",
-         dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], **inner)),
-        ("mixed_restart30", "the mixed solver with outer FGMRES(30)",
-         dict(base, restart=30, maxit=500, mode=MIXED["mode"], **inner)),
+        ("mixed", mixed_desc(best_mixed[False][2], ""), best_mixed[False][2]),
+        ("mixed_restart30", "the mixed solver with outer FGMRES(30)", dict(best_mixed[False][2], restart=30)),
         ("sap", f"FP64 FGMRES({best_sap[2]['restart']}), preconditioner SAP (FP32, 4^4 blocks, red-black, "
                 f"{best_sap[2]['sap']['cycles']} cycle(s), {best_sap[2]['sap']['mr_iters']} MR steps)", best_sap[2]),
         ("even_odd_fp64", "FGMRES(30), FP64, on S = A_ee - H_eo A_oo^-1 H_oe",
          dict(base, restart=30, maxit=5000, mode="f64", schur=True)),
-        ("even_odd_mixed", "the mixed solver on S (FP16S S in the inner GMRES)",
-         dict(base, restart=MIXED["restart"], maxit=500, mode=MIXED["mode"], schur=True, **inner)),
+        ("even_odd_mixed", mixed_desc(best_mixed[True][2], " on S (FP16S S in the inner GMRES)"),
+         best_mixed[True][2]),
     ]
     # two-level multigrid: one setup serves every right-hand side (its time is reported on its own); a few
     # multigrid configurations are tried on one right-hand side and the fastest solves all twelve
@@ -449,6 +463,8 @@ def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
                                                              mg.unknowns, **amg_stats},
            "sweeps_one_rhs_seconds": {"fp64": {n: t for t, n, *_ in sweep64},
                                       "sap": {n: t for t, n, *_ in sweep_sap},
+                                      "mixed": {n: t for t, n, *_ in sweep_mixed[False]},
+                                      "mixed_on_S": {n: t for t, n, *_ in sweep_mixed[True]},
                                       "amg": {n: {"solve": t, "applies": a, "setup": ts}
                                               for t, n, _, a, ts, _ in sweep_amg}},
            "amg_config": amg_name}
