@@ -32,6 +32,8 @@ constexpr int kOrderStationary = 5;  // FP32/FP16S, two-row links: each lane kee
                                      // clover (LDS) for all right-hand sides of the launch; plane tiles
 constexpr int kOrderZPlanes = 6;  // XCD k takes the (t, z) planes with z = k mod 8, z-block by z-block, each
                                    // z-block's planes in T order (tiles of one plane are consecutive)
+constexpr int kOrderZGroups = 7;  // link-stationary kernel only: as kOrderZPlanes over pairs of consecutive
+                                  // z-planes, a work-group's two waves take the same 64 (y, x) sites of each
 constexpr int kPatchX = 16, kPatchY = 4;  // patch extent in X and Y; Z extent = block / 64
 constexpr int kStationaryBlock = 128;     // work-group size of the link-stationary kernel (LDS budget)
 constexpr int kMaxStationaryRhs = 64;     // right-hand sides per link-stationary launch
@@ -54,7 +56,8 @@ struct TileMap {
     int nslots;           // ntiles rounded up to a multiple of 8
     int patches;          // kOrderPatch: patches per T-slice
     int npx, npy, pz;     // kOrderPatch: patches along X and Y, patch extent in Z
-    int nt, nz;           // kOrderZPlanes: lattice extents in T and Z
+    int nt, nz;           // kOrderZPlanes / kOrderZGroups: lattice extents in T and Z
+    int zw;               // kOrderZGroups: z-planes per work-group (block / 64)
     int plane_tiles;      // kOrderZPlanes: tiles per (t, z) plane
 };
 

@@ -313,6 +313,20 @@ __device__ __forceinline__ void tile_range(const TileMap &m, int vb, int &lo, in
     }
 }
 
+// site of lane l of tile slot vb in kOrderZGroups (-1: no site): XCD k takes the groups of zw consecutive z-planes
+// (zw p, ..., zw p + zw - 1) with p = k mod 8, group-block by group-block, each block's T-planes in order; a tile
+// is 64 consecutive (y, x) sites, wave w of the work-group in plane zw p + w
+__device__ __forceinline__ int zgroup_site(const TileMap &m, int vb, int l) {
+    const int k = vb & 7, j = vb >> 3;
+    const int q = j / m.plane_tiles, tile = j - q * m.plane_tiles;
+    const int zb = q / m.nt, t = q - zb * m.nt;
+    const int z = m.zw * (zb * 8 + k) + (l >> 6);
+    const int plane = m.slice / m.nz;
+    const int xy = tile * 64 + (l & 63);
+    if (z >= m.nz || xy >= plane) return -1;
+    return (t * m.nz + z) * plane + xy;
+}
+
 // Minimum waves per SIMD the register allocation must allow, per precision
 // and register block (the compiler otherwise trades occupancy for early
 // load hoisting).  Values from launch sweeps at 48^3 x 96.
@@ -428,10 +442,16 @@ void dslash_stationary_kernel(RhsTable tab, OpData d, Geom g, TileMap m, int apb
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     __shared__ float4 lds[18][kStationaryBlock];
-    int lo, hi;
-    tile_range(m, blockIdx.x, lo, hi);
-    const int s = lo + (int)threadIdx.x;
-    if (s >= hi) return;
+    int s;
+    if (m.order == kOrderZGroups) {
+        s = zgroup_site(m, blockIdx.x, threadIdx.x);
+        if (s < 0) return;
+    } else {
+        int lo, hi;
+        tile_range(m, blockIdx.x, lo, hi);
+        s = lo + (int)threadIdx.x;
+        if (s >= hi) return;
+    }
     const int V = g.V;
     const int tid = threadIdx.x;
     const bool compact = d.clover_compact != 0;
@@ -551,6 +571,7 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     m.pz = block / (kPatchX * kPatchY);
     m.nt = g.n[0];
     m.nz = g.n[1];
+    m.zw = 1;
     m.plane_tiles = 0;
     if (order == kOrderColumn) {
         const int per_range = (m.slice + 7) / 8;
@@ -562,6 +583,10 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
         m.patches = m.npx * m.npy * ((g.n[1] + m.pz - 1) / m.pz);
         m.tiles_per_range = (m.patches + 7) / 8;
         m.ntiles = (g.n[0] + m.tchunk - 1) / m.tchunk * 8 * m.tiles_per_range;
+    } else if (order == kOrderZGroups) {
+        m.zw = block / 64;
+        m.plane_tiles = (m.slice / m.nz + 63) / 64;
+        m.ntiles = ((m.nz + m.zw - 1) / m.zw + 7) / 8 * m.nt * m.plane_tiles * 8;
     } else if (order == kOrderZPlanes) {
         m.plane_tiles = (m.slice / m.nz + block - 1) / block;
         m.ntiles = (m.nz + 7) / 8 * m.nt * m.plane_tiles * 8;
@@ -690,7 +715,12 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 // re-read the links and clover once per group but shorten the time between
 // the uses of a neighbour spinor by work-groups of neighbouring planes
 // (measured, FP32, 41 RHS at 48^3 x 96: groups of 6 36.4 ms, all in one
-// launch 39.7 ms; FP16S is fastest in one launch).
+// launch 39.7 ms; FP16S is fastest in one launch).  With zw >= 2 the two
+// waves of a work-group take the same 64 (y, x) sites of two consecutive
+// z-planes, so one of a site's two z-neighbours is read inside the
+// work-group; over plane tiles both are planes of other XCDs (FP32, groups
+// of 12: 33.7 ms; four z-planes in 256-lane work-groups measured slower,
+// 41 ms).
 // Plane tiles (each XCD walks the T-planes of every eighth z in T order)
 // keep a site's T-neighbours in work-groups that run at the same time, a few
 // right-hand sides apart, so their spinors are mostly re-read from the caches;
@@ -699,14 +729,15 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 // 44.0 -> 39.5 ms, FP16S 27.5 -> 25.7 ms, results bit-identical).
 template <int P, bool DAG>
 static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g,
-                                    int apbc, int group, hipStream_t st) {
+                                    int apbc, int group, int zw, hipStream_t st) {
     const size_t rb = field_rhs_bytes(P, g.V);
     std::vector<std::pair<const void *, void *>> rhs;
     for (int b = 0; b < nbatch; b++)
         for (int r = 0; r < batches[b].nrhs; r++)
             rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
                              static_cast<char *>(batches[b].out) + r * rb);
-    const TileMap m = make_tilemap(g, kOrderZPlanes, kStationaryBlock, 1);
+    static_assert(kStationaryBlock == 128, "z-pair tiles are two waves");
+    const TileMap m = make_tilemap(g, zw >= 2 ? kOrderZGroups : kOrderZPlanes, kStationaryBlock, 1);
     const size_t grp = (group >= 2 && group < kMaxStationaryRhs) ? (size_t)group : (size_t)kMaxStationaryRhs;
     for (size_t r0 = 0; r0 < rhs.size(); r0 += grp) {
         RhsTable tab;
@@ -732,7 +763,7 @@ static hipError_t launch_p(const dirac_batch *batches, int nbatch, const OpData 
     if (cfg.order == kOrderStationary) {
         if constexpr (P != WDIRAC_F64) {
             if (d.rows == 2)
-                return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, cfg.tchunk, st);
+                return launch_stationary<P, DAG>(batches, nbatch, d, g, apbc, cfg.tchunk, cfg.nr, st);
         }
         cfg.order = kOrderTSweep;  // FP64 or full links: the register-blocked site kernel
     }

@@ -162,13 +162,15 @@ def test_patch_order_equals_column_order(block, prec, restore_tuning):
 @pytest.mark.parametrize("compact", [False, True])
 @pytest.mark.parametrize("dims", [(5, 3, 7, 4), (2, 10, 5, 6)])
 @pytest.mark.parametrize("group", [1, 7])
-def test_stationary_order_equals_site_kernel(prec, compress, compact, dims, group, restore_tuning):
+@pytest.mark.parametrize("zw", [1, 2])
+def test_stationary_order_equals_site_kernel(prec, compress, compact, dims, group, zw, restore_tuning):
     """Tile order 5 (links and clover kept on chip for every right-hand side
     of the launch) runs the site kernel's arithmetic, so results agree bit for
     bit; 70 right-hand sides in uneven batches need two launches (ten in
-    groups of 7, the tchunk knob), the planes leave a ragged last tile, and
-    the second lattice a ragged second z-block of its plane tiles.  FP64 and
-    full links fall back to order 2."""
+    groups of 7, the tchunk knob), over plane tiles or z-pair tiles (the nr
+    knob); the planes leave a ragged last tile, the lattices ragged z-blocks
+    and z-pairs (Z extents 3 and 10).
+    FP64 and full links fall back to order 2."""
     sizes = [1, 24, 45]
     n = sum(sizes)
     U, psi = fields(dims, 47, nrhs=n)
@@ -179,10 +181,12 @@ def test_stationary_order_equals_site_kernel(prec, compress, compact, dims, grou
     tune_set("block", 128)
     for dag in (False, True):
         tune_set("order", 2)
+        tune_set("nr_" + prec, 1)
         ref = op.empty(prec, n).zero_()
         op.apply_native(ref, nat, n, prec, dag)
         tune_set("order", 5)
         tune_set("tchunk", group)
+        tune_set("nr_" + prec, zw)
         out = op.empty(prec, n).zero_()
         batches, r0 = [], 0
         for k in sizes:
