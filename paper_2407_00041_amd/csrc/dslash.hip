@@ -711,22 +711,21 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 
 // Link-stationary launch: all right-hand sides of all batches, in groups of
 // `group` (2 .. kMaxStationaryRhs - 1; else kMaxStationaryRhs) per launch,
-// one work-group per plane tile of kStationaryBlock sites.  Smaller groups
-// re-read the links and clover once per group but shorten the time between
-// the uses of a neighbour spinor by work-groups of neighbouring planes
-// (measured, FP32, 41 RHS at 48^3 x 96: groups of 6 36.4 ms, all in one
-// launch 39.7 ms; FP16S is fastest in one launch).  With zw >= 2 the two
-// waves of a work-group take the same 64 (y, x) sites of two consecutive
-// z-planes, so one of a site's two z-neighbours is read inside the
-// work-group; over plane tiles both are planes of other XCDs (FP32, groups
-// of 12: 33.7 ms; four z-planes in 256-lane work-groups measured slower,
-// 41 ms).
-// Plane tiles (each XCD walks the T-planes of every eighth z in T order)
-// keep a site's T-neighbours in work-groups that run at the same time, a few
-// right-hand sides apart, so their spinors are mostly re-read from the caches;
-// with T-slice tiles the next slice only starts after the current one has
-// walked every right-hand side (measured at 48^3 x 96, 41 RHS: FP32
-// 44.0 -> 39.5 ms, FP16S 27.5 -> 25.7 ms, results bit-identical).
+// one work-group of kStationaryBlock lanes per tile.  Measurements below are
+// FP32 and FP16S, 41 RHS at 48^3 x 96, all results bit-identical.
+// - Plane tiles (zw = 1: 128 consecutive sites of one (t, z) plane; each XCD
+//   walks the T-planes of every eighth z in T order) keep a site's
+//   T-neighbours in work-groups that run at the same time, a few right-hand
+//   sides apart; with T-slice tiles the next slice only started after the
+//   current one had walked every right-hand side (FP32 44.0 -> 39.5 ms, FP16S
+//   27.5 -> 25.7 ms).  Both z-neighbours are planes of other XCDs.
+// - Z-pair tiles (zw >= 2: the two waves take the same 64 (y, x) sites of
+//   planes z and z + 1) read one of the two z-neighbours inside the
+//   work-group (FP32 groups of 12: 33.7 ms; four z-planes in 256-lane
+//   work-groups were slower, 41 ms).
+// - Smaller groups re-read the links and clover once per launch but shorten
+//   the time between the uses of a neighbour spinor (FP32 plane tiles: groups
+//   of 6 36.4 ms, all in one launch 39.7 ms; FP16S is fastest in one launch).
 template <int P, bool DAG>
 static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, const OpData &d, const Geom &g,
                                     int apbc, int group, int zw, hipStream_t st) {

@@ -3,8 +3,9 @@
 // For one operator, precision and number of right-hand sides the tuner times
 // a small set of candidate configurations (tile order including the lattice
 // order without XCD remapping, work-group size, T-chunk of the column sweep,
-// register block, persistent grid) with HIP events on temporary
-// buffers and keeps the fastest.  Choices are stored per (lattice extents,
+// register block, persistent grid; for the link-stationary kernel the
+// right-hand sides per launch and the plane or z-pair tile shape) with HIP
+// events on temporary buffers and keeps the fastest.  Choices are stored per (lattice extents,
 // precision, right-hand-side bucket, link format, clover format) and used by
 // every later launch with that key; they can be appended to a JSON-lines cache file
 // (environment variable WDIRAC_TUNE_CACHE) and are read back from it the first
