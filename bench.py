@@ -623,10 +623,10 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
         del x, y
     torch.cuda.synchronize()
     log("[suite] single applies done")
-    # one FP32 apply over batches {1, 4, 12, 24}: the link-stationary kernel over z-pair tiles in launches of 12
-    # right-hand sides
-    group = 12
-    _fixed(wd, 5, 128, group, 2)
+    # one FP32 apply over batches {1, 4, 12, 24}: the link-stationary kernel over z-pair tiles walked in (y, x)
+    # blocks, in launches of 16 right-hand sides
+    group = 16
+    _fixed(wd, 5, 128, group, 4)
     sizes = [1, 4, 12, 24]
     n = sum(sizes)
     nat = op.pack(synth.gaussian_spinor(dims, 2100, nrhs=n, device="cuda"), "f32")
@@ -642,7 +642,7 @@ def kernel_suite(torch, manifest_path, dims=(96, 48, 48, 48)):
     nl = -(-n // group)
     add(r"dslash_stationary_kernel<1, false>", 2 * nl,
         2 * (nl * (LINK_BYTES["f32"] + CLOVER_BYTES["f32"]) + 192 * n) * V,
-        f"batched FP32 apply, 41 RHS in batches {{1,4,12,24}}, z-pair tiles, launches of {group} RHS")
+        f"batched FP32 apply, 41 RHS in batches {{1,4,12,24}}, z-pair tiles in (y, x) blocks, launches of {group} RHS")
     _fixed(wd, 5, 128, 1, 1)     # the later sections' launches as before
     del outs, batches, nat
     torch.cuda.synchronize()

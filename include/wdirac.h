@@ -210,9 +210,10 @@ int dirac_apply_batched(const dirac_op *op, const dirac_batch *batches, int nbat
  * work-group per work item; > 0: a persistent grid of at most that many and
  * at most the co-resident work-groups, each walking the item list),
  * "nr_f64", "nr_f32", "nr_f16s" (right-hand sides per register block: 1, 2
- * or 4; for order 5 the work-group shape instead: 1 for tiles of 128
- * consecutive sites of one (t, z) plane, 2 or 4 for the same 64 (y, x) sites
- * of two consecutive z-planes, one wave each).  Setting any of these launch knobs makes them override autotuned
+ * or 4; for order 5 the tile shape instead: 1 for tiles of 128 consecutive
+ * sites of one (t, z) plane, 2 for the same 64 (y, x) sites of two
+ * consecutive z-planes, one wave each, 4 for those walked along T in (y, x)
+ * blocks of about eight x-rows).  Setting any of these launch knobs makes them override autotuned
  * choices; "explicit" = 0 returns to the autotuned ones (1 forces the knobs).
  * Not synchronised with launches in flight; set before applying.
  * Errors: EINVAL (unknown key or value out of range).
@@ -228,8 +229,8 @@ int dirac_tune_get(const char *key, int *value);
  * precision, right-hand-side bucket (1, 2, 3-4, 5-8, ...), link format and
  * clover format.  Candidates: tile orders 0, 2, 3, 4 (and, for several
  * right-hand sides, 6, and 5 for FP32/FP16S with two-row links, in one
- * launch or groups of 4, 6, 8 or 12 right-hand sides, over plane or z-pair
- * tiles), work-groups of 128/256,
+ * launch or groups of 4, 6, 8, 12 or 16 right-hand sides, over plane or
+ * z-pair tiles), work-groups of 128/256,
  * T-chunks 2/4/8, register blocks 1/2/4 and, for several right-hand sides, a
  * persistent grid.  The choice is appended to the JSON-lines file named by
  * the environment variable WDIRAC_TUNE_CACHE when it is set; that file is

@@ -33,7 +33,8 @@ constexpr int kOrderStationary = 5;  // FP32/FP16S, two-row links: each lane kee
 constexpr int kOrderZPlanes = 6;  // XCD k takes the (t, z) planes with z = k mod 8, z-block by z-block, each
                                    // z-block's planes in T order (tiles of one plane are consecutive)
 constexpr int kOrderZGroups = 7;  // link-stationary kernel only: as kOrderZPlanes over pairs of consecutive
-                                  // z-planes, a work-group's two waves take the same 64 (y, x) sites of each
+                                  // z-planes, a work-group's two waves take the same 64 (y, x) sites of each;
+                                  // optionally walked along T in (y, x) blocks of xyb tiles
 constexpr int kPatchX = 16, kPatchY = 4;  // patch extent in X and Y; Z extent = block / 64
 constexpr int kStationaryBlock = 128;     // work-group size of the link-stationary kernel (LDS budget)
 constexpr int kMaxStationaryRhs = 64;     // right-hand sides per link-stationary launch
@@ -58,6 +59,7 @@ struct TileMap {
     int npx, npy, pz;     // kOrderPatch: patches along X and Y, patch extent in Z
     int nt, nz;           // kOrderZPlanes / kOrderZGroups: lattice extents in T and Z
     int zw;               // kOrderZGroups: z-planes per work-group (block / 64)
+    int xyb;              // kOrderZGroups: tiles per (y, x) block; the T-planes of a block run before the next block
     int plane_tiles;      // kOrderZPlanes: tiles per (t, z) plane
 };
 

@@ -318,12 +318,15 @@ __device__ __forceinline__ void tile_range(const TileMap &m, int vb, int &lo, in
 // is 64 consecutive (y, x) sites, wave w of the work-group in plane zw p + w
 __device__ __forceinline__ int zgroup_site(const TileMap &m, int vb, int l) {
     const int k = vb & 7, j = vb >> 3;
-    const int q = j / m.plane_tiles, tile = j - q * m.plane_tiles;
-    const int zb = q / m.nt, t = q - zb * m.nt;
+    const int nxyb = (m.plane_tiles + m.xyb - 1) / m.xyb;
+    const int tl = j % m.xyb, q = j / m.xyb;
+    const int t = q % m.nt, r = q / m.nt;
+    const int xyb = r % nxyb, zb = r / nxyb;
+    const int tile = xyb * m.xyb + tl;
     const int z = m.zw * (zb * 8 + k) + (l >> 6);
     const int plane = m.slice / m.nz;
     const int xy = tile * 64 + (l & 63);
-    if (z >= m.nz || xy >= plane) return -1;
+    if (z >= m.nz || tile >= m.plane_tiles || xy >= plane) return -1;
     return (t * m.nz + z) * plane + xy;
 }
 
@@ -572,6 +575,7 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     m.nt = g.n[0];
     m.nz = g.n[1];
     m.zw = 1;
+    m.xyb = 1;
     m.plane_tiles = 0;
     if (order == kOrderColumn) {
         const int per_range = (m.slice + 7) / 8;
@@ -586,7 +590,9 @@ TileMap make_tilemap(const Geom &g, int order, int block, int tchunk) {
     } else if (order == kOrderZGroups) {
         m.zw = block / 64;
         m.plane_tiles = (m.slice / m.nz + 63) / 64;
-        m.ntiles = ((m.nz + m.zw - 1) / m.zw + 7) / 8 * m.nt * m.plane_tiles * 8;
+        m.xyb = (tchunk >= 1 && tchunk < m.plane_tiles) ? tchunk : m.plane_tiles;
+        const int nxyb = (m.plane_tiles + m.xyb - 1) / m.xyb;
+        m.ntiles = ((m.nz + m.zw - 1) / m.zw + 7) / 8 * nxyb * m.nt * m.xyb * 8;
     } else if (order == kOrderZPlanes) {
         m.plane_tiles = (m.slice / m.nz + block - 1) / block;
         m.ntiles = (m.nz + 7) / 8 * m.nt * m.plane_tiles * 8;
@@ -722,7 +728,11 @@ static hipError_t launch_nr(const dirac_batch *batches, int nbatch, const OpData
 // - Z-pair tiles (zw >= 2: the two waves take the same 64 (y, x) sites of
 //   planes z and z + 1) read one of the two z-neighbours inside the
 //   work-group (FP32 groups of 12: 33.7 ms; four z-planes in 256-lane
-//   work-groups were slower, 41 ms).
+//   work-groups were slower, 41 ms).  With zw = 4 an XCD walks its z-pairs
+//   along T in blocks of about eight x-rows before the next block, so a
+//   T-neighbour's tile ran only a few work-groups earlier (FP32 groups of
+//   16: 30.3 ms; FP16S in one launch 24.3 ms; blocks of whole rows measured
+//   faster than ragged ones).
 // - Smaller groups re-read the links and clover once per launch but shorten
 //   the time between the uses of a neighbour spinor (FP32 plane tiles: groups
 //   of 6 36.4 ms, all in one launch 39.7 ms; FP16S is fastest in one launch).
@@ -736,7 +746,9 @@ static hipError_t launch_stationary(const dirac_batch *batches, int nbatch, cons
             rhs.emplace_back(static_cast<const char *>(batches[b].in) + r * rb,
                              static_cast<char *>(batches[b].out) + r * rb);
     static_assert(kStationaryBlock == 128, "z-pair tiles are two waves");
-    const TileMap m = make_tilemap(g, zw >= 2 ? kOrderZGroups : kOrderZPlanes, kStationaryBlock, 1);
+    // zw = 4: z-pair tiles walked along T in (y, x) blocks of about eight x-rows (0: whole planes)
+    const int xyb = zw == 4 ? (8 * g.n[3] + 63) / 64 : 0;
+    const TileMap m = make_tilemap(g, zw >= 2 ? kOrderZGroups : kOrderZPlanes, kStationaryBlock, xyb);
     const size_t grp = (group >= 2 && group < kMaxStationaryRhs) ? (size_t)group : (size_t)kMaxStationaryRhs;
     for (size_t r0 = 0; r0 < rhs.size(); r0 += grp) {
         RhsTable tab;

@@ -98,8 +98,8 @@ extern "C" int dirac_autotune(const dirac_op *op, int prec, int nrhs, int cfg_ou
     std::vector<LaunchCfg> cands;
     const int nrs[3] = {1, 2, 4};
     if (prec != WDIRAC_F64 && op->link_rows == 2 && nrhs > 1)  // all right-hand sides per launch, or groups;
-        for (int zw : {1, 2})                                      // plane tiles or z-pair tiles
-            for (int group : {1, 4, 6, 8, 12})
+        for (int zw : {1, 2, 4})                 // plane tiles, z-pair tiles, z-pair tiles in (y, x) blocks
+            for (int group : {1, 4, 6, 8, 12, 16})
                 if (group == 1 || group < nrhs) cands.push_back({kOrderStationary, kStationaryBlock, group, zw});
     for (int nr : nrs)  // lattice order without the XCD-aware remapping
         if (nr == 1 || nr <= nrhs) cands.push_back({kOrderLinear, 256, 4, nr});

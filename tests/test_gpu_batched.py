@@ -160,17 +160,18 @@ def test_patch_order_equals_column_order(block, prec, restore_tuning):
 @pytest.mark.parametrize("prec", ["f32", "f16s", "f64"])
 @pytest.mark.parametrize("compress", [True, False])
 @pytest.mark.parametrize("compact", [False, True])
-@pytest.mark.parametrize("dims", [(5, 3, 7, 4), (2, 10, 5, 6)])
+@pytest.mark.parametrize("dims", [(5, 3, 7, 4), (2, 10, 5, 6), (2, 5, 12, 16)])
 @pytest.mark.parametrize("group", [1, 7])
-@pytest.mark.parametrize("zw", [1, 2])
+@pytest.mark.parametrize("zw", [1, 2, 4])
 def test_stationary_order_equals_site_kernel(prec, compress, compact, dims, group, zw, restore_tuning):
     """Tile order 5 (links and clover kept on chip for every right-hand side
     of the launch) runs the site kernel's arithmetic, so results agree bit for
     bit; 70 right-hand sides in uneven batches need two launches (ten in
-    groups of 7, the tchunk knob), over plane tiles or z-pair tiles (the nr
-    knob); the planes leave a ragged last tile, the lattices ragged z-blocks
-    and z-pairs (Z extents 3 and 10).
-    FP64 and full links fall back to order 2."""
+    groups of 7, the tchunk knob), over plane tiles, z-pair tiles and z-pair
+    tiles walked in (y, x) blocks (the nr knob); the planes leave a ragged
+    last tile, the lattices ragged z-blocks and z-pairs (Z extents 3, 10 and
+    5), and the third lattice three 64-site tiles per plane in (y, x) blocks
+    of two.  FP64 and full links fall back to order 2."""
     sizes = [1, 24, 45]
     n = sum(sizes)
     U, psi = fields(dims, 47, nrhs=n)

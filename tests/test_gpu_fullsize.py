@@ -68,8 +68,8 @@ def test_full_size_41_rhs_batched_launch(restore_tuning):
     """48^3 x 96, FP32, two-row links, compact clover: the benchmark's one call
     over uneven batches {1, 4, 12, 24} (41 right-hand sides), in the
     configuration its autotuner selects and in the link-stationary kernel with
-    launches of 6 right-hand sides over plane tiles and z-pair tiles; 300
-    sampled sites of every right-hand side against the oracle."""
+    launches of 6 right-hand sides over plane tiles and both z-pair walks;
+    300 sampled sites of every right-hand side against the oracle."""
     m0, csw = -0.35, 1.0
     U = _links(DIMS48, 1003)
     op = DiracOp(DIMS48, U, m0, csw, precisions=("f64", "f32"), compress_links=True, compress_clover=True)
@@ -88,7 +88,7 @@ def test_full_size_41_rhs_batched_launch(restore_tuning):
     rb = op.field_bytes("f32", 1)
     tune_set("explicit", 0)
     cfg = op.autotune("f32", n)
-    for explicit in (None, 1, 2):
+    for explicit in (None, 1, 2, 4):
         if explicit:
             for k, v in (("order", 5), ("block", 128), ("tchunk", 6), ("nr_f32", explicit)):
                 tune_set(k, v)
