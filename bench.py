@@ -332,7 +332,7 @@ def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
     from paper_2407_00041_amd import synth
     base = dict(tol=1e-10)
     b1 = op.pack(synth.gaussian_spinor(dims, 3000, nrhs=1, device="cuda"), "f64")
-    for n in (1, 2, 3):       # batched applies of the solvers' waves
+    for n in (1, 2, 3, 6):    # batched applies of the solvers' waves (tuning buckets 1, 2, 3-4, 5-8)
         if not TUNE_FIXED:
             op.autotune("f64", n)
             op.autotune("f16s", n)
