@@ -71,6 +71,10 @@ __device__ __forceinline__ void hop_boundary(cx<T> (&acc)[NR][12], int level = 1
 // once for all of them.
 constexpr int kParMax = 16;
 constexpr int kParNr = 2;  // right-hand sides per lane
+// FP16S with at least four right-hand sides in a launch: four per lane (147-151 VGPRs, 3 waves/SIMD instead of
+// 4), so a lane's links and A or A^-1 serve four of them (measured at 48^3 x 96: S 0.84 -> 0.77 ms per RHS on
+// 4 RHS).  With two or three the idle slots would cost the occupancy for nothing (0.82 -> 0.89 ms per launch on 2).
+constexpr int kParNrF16 = 4;
 #ifndef WD_PARITY_COLUMN
 #define WD_PARITY_COLUMN 1
 #endif
@@ -387,16 +391,16 @@ hipError_t launch_mode(const dirac_op *op, int parity, const ParityItem *items, 
             tab.self[q] = items[a + q].self;
             tab.hop[q] = items[a + q].hop;
         }
-        // one instantiation (pairs) for every count, a lone last right-hand side included: a single-RHS
-        // instantiation rounds differently, and results must not depend on how right-hand sides are grouped
-        const dim3 grid(op->g.n[0] * 8 * tpr, (tab.n + kParNr - 1) / kParNr);
+        // pairs (or fours, see kParNrF16) for every count, a lone last right-hand side included: a single-RHS
+        // instantiation may round differently, and results must not depend on how right-hand sides are grouped
+        // (the per-RHS arithmetic of the pair and four instantiations is the same code, unrolled)
         if constexpr (HOP && (P != WDIRAC_F16S || WD_PARITY_COLUMN_F16)) {
             if (kParColumnWalk) {
                 // the column walk: T-chunks of CH slices, each XCD 1/8 of the columns
                 constexpr int CH = P == WDIRAC_F16S ? 2 : kParChunk;
                 const int C = op->g.stride[0];
                 const int tpc = ((C + 7) / 8 + 255) / 256;
-                const dim3 gc((op->g.n[0] + CH - 1) / CH * 8 * tpc, grid.y);
+                const dim3 gc((op->g.n[0] + CH - 1) / CH * 8 * tpc, (tab.n + kParNr - 1) / kParNr);
                 if (rows2)
                     hipLaunchKernelGGL((parity_column_kernel<P, DAG, SELF, HOP, INV, 2, kParNr, CH>), gc, dim3(256),
                                        0, st, tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpc);
@@ -408,6 +412,21 @@ hipError_t launch_mode(const dirac_op *op, int parity, const ParityItem *items, 
                 continue;
             }
         }
+        if constexpr (P == WDIRAC_F16S) {
+            if (tab.n >= kParNrF16) {
+                const dim3 g4(op->g.n[0] * 8 * tpr, (tab.n + kParNrF16 - 1) / kParNrF16);
+                if (rows2)
+                    hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2, kParNrF16>), g4, dim3(256), 0, st,
+                                       tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpr);
+                else
+                    hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 3, kParNrF16>), g4, dim3(256), 0, st,
+                                       tab, op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpr);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                continue;
+            }
+        }
+        const dim3 grid(op->g.n[0] * 8 * tpr, (tab.n + kParNr - 1) / kParNr);
         if (rows2)
             hipLaunchKernelGGL((parity_kernel<P, DAG, SELF, HOP, INV, 2, kParNr>), grid, dim3(256), 0, st, tab,
                                op->data(P), op->cinv(P), op->g, parity, apbc, (T)fh, tpr);
