@@ -131,55 +131,75 @@ __device__ __forceinline__ C ld(const double2 *f, int V, int k, int s) {
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: M_mu,nu(s) for one plane, summed over right-hand sides
-template <int MU, int NU>
-__device__ __forceinline__ void insert_plane(double2 *__restrict__ out, const double2 *__restrict__ eta,
-                                             const double2 *__restrict__ x, int nrhs, int V, int s, int plane) {
+// pass 1: M_mu,nu(s) for the six planes, summed over right-hand sides.  A lane
+// loads one chiral block of its site's eta and x (6 components each) at a time
+// and folds that block's part of every plane's K into the plane's 9 reals of
+// M = K - K^H (linear in K), so the spinors are read once, not once per plane,
+// and only one block of them is live.
+//
+// m[9] = (Im M_00, Im M_11, Im M_22, M_01, M_02, M_12) as (i, i, i, re, im, re, im, re, im)
+template <int MU, int NU, int BLK>
+__device__ __forceinline__ void insert_plane_acc(double (&m)[9], const C (&e)[6], const C (&xv)[6]) {
     // K = sum_blk sum_be x_{blk,be} (x) conj(zeta_{blk,be}) with zeta = P_blk^H eta_blk for the chiral blocks
     // P_0 = B_mu B_nu^H and P_1 = B_mu^H B_nu of gamma_mu gamma_nu, i.e. zeta_0 = B_nu (B_mu^H eta_0) and
     // zeta_1 = B_nu^H (B_mu eta_1).
-    M3 K;
+    C z[2][3];
 #pragma unroll
-    for (int e = 0; e < 9; e++) K.a[e] = cz();
-    const size_t rs = (size_t)12 * V;
-    for (int r = 0; r < nrhs; r++) {
-        const double2 *er = eta + r * rs, *xr = x + r * rs;
-#pragma unroll
-        for (int blk = 0; blk < 2; blk++) {
-            C z[2][3], xv[2][3];
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                const C e0 = ld(er, V, 6 * blk + a, s), e1 = ld(er, V, 6 * blk + 3 + a, s);
-                C t0, t1;
-                if (blk == 0) {
-                    bhmul<MU>(e0, e1, t0, t1);
-                    bmul<NU>(t0, t1, z[0][a], z[1][a]);
-                } else {
-                    bmul<MU>(e0, e1, t0, t1);
-                    bhmul<NU>(t0, t1, z[0][a], z[1][a]);
-                }
-                xv[0][a] = ld(xr, V, 6 * blk + a, s);
-                xv[1][a] = ld(xr, V, 6 * blk + 3 + a, s);
-            }
-#pragma unroll
-            for (int be = 0; be < 2; be++)
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int a = 0; a < 3; a++) K.a[3 * b + a] = cjfma(K.a[3 * b + a], z[be][a], xv[be][b]);
+    for (int a = 0; a < 3; a++) {
+        C t0, t1;
+        if constexpr (BLK == 0) {
+            bhmul<MU>(e[a], e[3 + a], t0, t1);
+            bmul<NU>(t0, t1, z[0][a], z[1][a]);
+        } else {
+            bmul<MU>(e[a], e[3 + a], t0, t1);
+            bhmul<NU>(t0, t1, z[0][a], z[1][a]);
         }
     }
+    M3 K;
+#pragma unroll
+    for (int q = 0; q < 9; q++) K.a[q] = cz();
+#pragma unroll
+    for (int be = 0; be < 2; be++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) K.a[3 * b + a] = cjfma(K.a[3 * b + a], z[be][a], xv[3 * be + b]);
     // M = K - K^H: imaginary diagonal and upper triangle
+    m[0] += 2.0 * K.a[0].i;
+    m[1] += 2.0 * K.a[4].i;
+    m[2] += 2.0 * K.a[8].i;
+    m[3] += K.a[1].r - K.a[3].r;
+    m[4] += K.a[1].i + K.a[3].i;
+    m[5] += K.a[2].r - K.a[6].r;
+    m[6] += K.a[2].i + K.a[6].i;
+    m[7] += K.a[5].r - K.a[7].r;
+    m[8] += K.a[5].i + K.a[7].i;
+}
+
+template <int BLK>
+__device__ __forceinline__ void insert_block(double (&m)[kPlanes][9], const double2 *__restrict__ eta,
+                                             const double2 *__restrict__ x, int V, int s) {
+    C e[6], xv[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        e[k] = ld(eta, V, 6 * BLK + k, s);
+        xv[k] = ld(x, V, 6 * BLK + k, s);
+    }
+    insert_plane_acc<0, 1, BLK>(m[0], e, xv);
+    insert_plane_acc<0, 2, BLK>(m[1], e, xv);
+    insert_plane_acc<0, 3, BLK>(m[2], e, xv);
+    insert_plane_acc<1, 2, BLK>(m[3], e, xv);
+    insert_plane_acc<1, 3, BLK>(m[4], e, xv);
+    insert_plane_acc<2, 3, BLK>(m[5], e, xv);
+}
+
+__device__ __forceinline__ void store_insert(double2 *__restrict__ out, int V, int plane, int s, const double (&m)[9]) {
     double2 *o = out + (size_t)plane * kInsertVec * V + s;
-    const double m00 = 2.0 * K.a[0].i, m11 = 2.0 * K.a[4].i, m22 = 2.0 * K.a[8].i;
-    const C m01 = {K.a[1].r - K.a[3].r, K.a[1].i + K.a[3].i};
-    const C m02 = {K.a[2].r - K.a[6].r, K.a[2].i + K.a[6].i};
-    const C m12 = {K.a[5].r - K.a[7].r, K.a[5].i + K.a[7].i};
-    o[0] = make_double2(m00, m11);
-    o[(size_t)V] = make_double2(m22, m01.r);
-    o[(size_t)2 * V] = make_double2(m01.i, m02.r);
-    o[(size_t)3 * V] = make_double2(m02.i, m12.r);
-    o[(size_t)4 * V] = make_double2(m12.i, 0.0);
+    o[0] = make_double2(m[0], m[1]);
+    o[(size_t)V] = make_double2(m[2], m[3]);
+    o[(size_t)2 * V] = make_double2(m[4], m[5]);
+    o[(size_t)3 * V] = make_double2(m[6], m[7]);
+    o[(size_t)4 * V] = make_double2(m[8], 0.0);
 }
 
 __device__ __forceinline__ M3 load_insert(const double2 *__restrict__ M, int V, int plane, int s) {
@@ -334,24 +354,40 @@ __global__ __launch_bounds__(256) void force_insert_kernel(double2 *__restrict__
                                                            const double2 *__restrict__ x, int nrhs, int V) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
-    insert_plane<0, 1>(out, eta, x, nrhs, V, s, 0);
-    insert_plane<0, 2>(out, eta, x, nrhs, V, s, 1);
-    insert_plane<0, 3>(out, eta, x, nrhs, V, s, 2);
-    insert_plane<1, 2>(out, eta, x, nrhs, V, s, 3);
-    insert_plane<1, 3>(out, eta, x, nrhs, V, s, 4);
-    insert_plane<2, 3>(out, eta, x, nrhs, V, s, 5);
+    double m[kPlanes][9];
+#pragma unroll
+    for (int q = 0; q < kPlanes; q++)
+#pragma unroll
+        for (int k = 0; k < 9; k++) m[q][k] = 0.0;
+    const size_t rs = (size_t)12 * V;
+    for (int r = 0; r < nrhs; r++) {
+        insert_block<0>(m, eta + r * rs, x + r * rs, V, s);
+        insert_block<1>(m, eta + r * rs, x + r * rs, V, s);
+    }
+#pragma unroll
+    for (int q = 0; q < kPlanes; q++) store_insert(out, V, q, s, m[q]);
 }
 
 __global__ __launch_bounds__(256, 2) void force_link_kernel(double2 *__restrict__ out, const double2 *__restrict__ U,
                                                          const double2 *__restrict__ Mins,
                                                          const double2 *__restrict__ eta,
                                                          const double2 *__restrict__ x, int nrhs, Geom g, int apbc,
-                                                         int with_clover, double csw, int raw) {
+                                                         int with_clover, double csw, int raw, int eighth) {
     __shared__ double2 stage[kLinkSites * kLdsPitch];
     const int lane = threadIdx.x & 63, rho = threadIdx.x >> 6;
-    const int base = blockIdx.x * kLinkSites;
+    // XCD-aware tiles (work-groups go round-robin to the 8 XCDs): XCD k takes the k-th eighth of every T-slice
+    // (eighth = sites, a multiple of kLinkSites), and all XCDs advance through the slices together, so a tile's
+    // X, Y and most Z neighbours are its own XCD's recent tiles (its L2) and its T neighbours were read by the
+    // same XCD one slice earlier or are read one slice later
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int tpe = eighth / kLinkSites;
+    const int t = j / tpe;
+    const int slice = g.stride[0];
+    const int lo = xcd * eighth + (j - t * tpe) * kLinkSites;  // the tile's first site within its T-slice
+    const int hi = min((xcd + 1) * eighth, slice);             // end of this XCD's eighth
+    const int base = t * slice + lo;
     const int y = base + lane;
-    if (y < g.V) {
+    if (lo + lane < hi) {
         Site p;
         int r = y;
         p.c[3] = r % g.n[3]; r /= g.n[3];
@@ -384,7 +420,7 @@ __global__ __launch_bounds__(256, 2) void force_link_kernel(double2 *__restrict_
         }
     }
     __syncthreads();
-    const int nsite = min(kLinkSites, g.V - base);
+    const int nsite = min(kLinkSites, hi - lo);  // <= 0 for the empty tiles past a short slice's end
     double2 *dst = out + (size_t)base * 36;
     for (int t = threadIdx.x; t < nsite * 36; t += blockDim.x) dst[t] = stage[(t / 36) * kLdsPitch + t % 36];
 }
@@ -418,10 +454,12 @@ extern "C" int dirac_force(const dirac_op *op, double *dU, const double *eta, co
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("force insert launch: ") + hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(force_link_kernel, dim3((V + kLinkSites - 1) / kLinkSites), dim3(4 * kLinkSites), 0, st,
+    const int slice = op->g.stride[0];
+    const int eighth = ((slice + 7) / 8 + kLinkSites - 1) / kLinkSites * kLinkSites;
+    hipLaunchKernelGGL(force_link_kernel, dim3(op->g.n[0] * 8 * (eighth / kLinkSites)), dim3(4 * kLinkSites), 0, st,
                        reinterpret_cast<double2 *>(dU), reinterpret_cast<const double2 *>(op->links_canon),
                        (const double2 *)M, e2, x2, nrhs, op->g, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0,
-                       with_clover, op->csw, raw ? 1 : 0);
+                       with_clover, op->csw, raw ? 1 : 0, eighth);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(WDIRAC_EHIP, std::string("force launch: ") + hipGetErrorString(e));
     return WDIRAC_OK;

@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("dims,csw,ap,kind", [((4, 4, 4, 4), 1.0, False, "smooth"),
                                               ((2, 2, 2, 2), 1.0, True, "haar"),
                                               ((3, 4, 2, 4), 0.0, True, "haar"),
-                                              ((4, 2, 6, 2), 1.3, False, "haar")])
+                                              ((4, 2, 6, 2), 1.3, False, "haar"),
+                                              # 720 sites per T-slice: six 128-site eighths, the last one ragged
+                                              # (80 sites), two XCDs without a tile in each slice
+                                              ((3, 6, 10, 12), 1.0, True, "haar")])
 def test_force_matches_oracle_every_link(dims, csw, ap, kind):
     need_gpu()
     V = synth.volume(dims)
