@@ -19,6 +19,8 @@ hipError_t su3_deviation(const double *links_can_dev, int V, double *out, hipStr
 hipError_t clover_structure_deviation(const double *clover_can_dev, int V, double *out, hipStream_t st);
 hipError_t clover_inverse_to_native(dirac_op *op, const double *inv_can_dev, hipStream_t st);
 hipError_t nonfinite_any(const double *dev, size_t n, bool *out, hipStream_t st);
+hipError_t force_links_layout(double *dst, const double *canon, int V, hipStream_t st);
+size_t force_links_bytes(int V);
 
 static thread_local std::string g_err;
 constexpr double kSu3Tol = 1e-12;  // largest |U U^H - 1|, |det U - 1| accepted for two-row storage
@@ -97,7 +99,7 @@ size_t dirac_field_bytes(const dirac_op *op, int prec, int nrhs) {
 int dirac_destroy(dirac_op *op) {
     if (!op) return WDIRAC_OK;
     void *bufs[] = {op->links64, op->clover64, op->links32, op->clover32, op->links16, op->clover16,
-                    op->links_canon, op->cinv64, op->cinv32, op->cinv16};
+                    op->links_force, op->cinv64, op->cinv32, op->cinv16};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     delete op;
@@ -160,8 +162,10 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
             if ((flags & WDIRAC_WITH_F32) && !alloc((void **)&op->cinv32, Vt * 72 * 4)) break;
             if ((flags & WDIRAC_WITH_F16) && !alloc((void **)&op->cinv16, Vt * 72 * 2)) break;
         }
-        if (!alloc((void **)&op->links_canon, nl) || !alloc((void **)&cc, nc)) break;
-        lc = op->links_canon;
+        // the canonical links (lc) serve the set-up kernels only; the force keeps its own component-major copy
+        if (!alloc((void **)&op->links_force, force_links_bytes((int)V)) || !alloc((void **)&lc, nl) ||
+            !alloc((void **)&cc, nc))
+            break;
         if (hipMemcpy(lc, links, nl, hipMemcpyHostToDevice) != hipSuccess) {
             rc = fail(WDIRAC_EHIP, "copy of links to the device failed");
             break;
@@ -225,7 +229,8 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
                 break;
             }
         }
-        if (operator_to_native(op, lc, cc, st) != hipSuccess) {
+        if (operator_to_native(op, lc, cc, st) != hipSuccess ||
+            force_links_layout(op->links_force, lc, (int)V, st) != hipSuccess) {
             rc = fail(WDIRAC_EHIP, "layout conversion launch failed");
             break;
         }
@@ -250,6 +255,7 @@ int dirac_create(dirac_op **out, const int dims[4], const double *links, const d
             break;
         }
     } while (false);
+    if (lc) (void)hipFree(lc);
     if (cc) (void)hipFree(cc);
     if (ic) (void)hipFree(ic);
     if (bad) (void)hipFree(bad);

@@ -133,7 +133,7 @@ struct dirac_op {
     void *links64 = nullptr, *clover64 = nullptr;
     void *links32 = nullptr, *clover32 = nullptr;
     void *links16 = nullptr, *clover16 = nullptr;
-    double *links_canon = nullptr;  // canonical FP64 links (force kernels)
+    double *links_force = nullptr;  // FP64 links of the force kernel, site tiles [V/64][4][9][64] complex
     // inverse site-local term A(x)^{-1} (even-odd flag only): packed clover layout
     void *cinv64 = nullptr, *cinv32 = nullptr, *cinv16 = nullptr;
     int link_rows = 3;

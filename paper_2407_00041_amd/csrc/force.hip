@@ -32,10 +32,11 @@
 //
 // Two passes: force_insert_kernel forms M_mu,nu(x) for the six planes once
 // per site (anti-Hermitian, 9 reals each), force_link_kernel then gathers
-// them with the links around each plaquette.  One work-group covers 64 sites;
-// its wave w computes the links of direction w, so every branch on the
-// direction is wave-uniform, and the work-group's 64 x 4 link matrices are
-// written out through LDS in contiguous order.
+// them with the links around each plaquette, read from the operator's
+// site-tiled FP64 copy of the links.  One work-group covers 64 sites; its
+// wave w computes the links of direction w, so every branch on the direction
+// is wave-uniform, and the work-group's 64 x 4 link matrices are written out
+// through LDS in contiguous order.
 //
 // Output: P_TA(G U^H) = (M - M^H)/2 - tr(M - M^H)/6 (the su(3) projection),
 // or G itself (raw), canonical [V][4][3][3] complex128.
@@ -82,31 +83,35 @@ __device__ __forceinline__ M3 mmul(const M3 &x, const M3 &y) {
     return m;
 }
 
-// acc += x * y
-__device__ __forceinline__ void mmul_acc(M3 &acc, const M3 &x, const M3 &y) {
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) acc.a[3 * i + j] = cfma(acc.a[3 * i + j], x.a[3 * i + k], y.a[3 * k + j]);
+// links site-tiled, U[((site / 64) * 36 + 9 mu + e) * 64 + site % 64] (e = 3 row
+// + column): the lanes of a wave, at consecutive sites, read contiguous memory,
+// and a link's nine entries lie 1 KB apart from one per-lane address
+constexpr int kLinkTile = 64;
+__device__ __forceinline__ const double2 *link_ptr(const double2 *U, int site, int mu) {
+    return U + ((size_t)(site / kLinkTile) * 36 + 9 * mu) * kLinkTile + site % kLinkTile;
 }
 
 __device__ __forceinline__ M3 link(const double2 *U, int site, int mu) {
     M3 m;
-    const double2 *p = U + ((size_t)4 * site + mu) * 9;
+    const double2 *p = link_ptr(U, site, mu);
 #pragma unroll
-    for (int e = 0; e < 9; e++) m.a[e] = {p[e].x, p[e].y};
+    for (int e = 0; e < 9; e++) {
+        const double2 v = p[e * kLinkTile];
+        m.a[e] = {v.x, v.y};
+    }
     return m;
 }
 
 __device__ __forceinline__ M3 link_dag(const double2 *U, int site, int mu) {
     M3 m;
-    const double2 *p = U + ((size_t)4 * site + mu) * 9;
+    const double2 *p = link_ptr(U, site, mu);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++) m.a[3 * j + i] = {p[3 * i + j].x, -p[3 * i + j].y};
+        for (int j = 0; j < 3; j++) {
+            const double2 v = p[(3 * i + j) * kLinkTile];
+            m.a[3 * j + i] = {v.x, -v.y};
+        }
     return m;
 }
 
@@ -202,20 +207,92 @@ __device__ __forceinline__ void store_insert(double2 *__restrict__ out, int V, i
     o[(size_t)4 * V] = make_double2(m[8], 0.0);
 }
 
-__device__ __forceinline__ M3 load_insert(const double2 *__restrict__ M, int V, int plane, int s) {
+// An insertion matrix as stored: anti-Hermitian, so its diagonal is imaginary
+// (d = Im M_kk) and its lower triangle is minus the conjugate of the upper
+// (u = M_01, M_02, M_12).  Products with it skip the zero real parts of the
+// diagonal and rebuild the lower triangle from the upper.
+struct AH {
+    double d[3];
+    C u[3];
+};
+
+__device__ __forceinline__ AH load_ah(const double2 *__restrict__ M, int V, int plane, int s) {
     const double2 *p = M + (size_t)plane * kInsertVec * V + s;
     const double2 a = p[0], b = p[(size_t)V], c = p[(size_t)2 * V], d = p[(size_t)3 * V], e = p[(size_t)4 * V];
-    M3 m;
-    m.a[0] = {0.0, a.x};
-    m.a[4] = {0.0, a.y};
-    m.a[8] = {0.0, b.x};
-    m.a[1] = {b.y, c.x};
-    m.a[2] = {c.y, d.x};
-    m.a[5] = {d.y, e.x};
-    m.a[3] = {-b.y, c.x};
-    m.a[6] = {-c.y, d.x};
-    m.a[7] = {-d.y, e.x};
+    AH m;
+    m.d[0] = a.x;
+    m.d[1] = a.y;
+    m.d[2] = b.x;
+    m.u[0] = {b.y, c.x};
+    m.u[1] = {c.y, d.x};
+    m.u[2] = {d.y, e.x};
     return m;
+}
+
+// index of M_jk (j < k) in AH::u
+__device__ __forceinline__ constexpr int ah_u(int j, int k) { return j == 0 ? k - 1 : 2; }
+
+// acc - conj(a) * b
+__device__ __forceinline__ C cjfms(C acc, C a, C b) {
+    acc.r = fma(-a.r, b.r, acc.r);
+    acc.r = fma(-a.i, b.i, acc.r);
+    acc.i = fma(-a.r, b.i, acc.i);
+    acc.i = fma(a.i, b.r, acc.i);
+    return acc;
+}
+// acc - a * conj(b)
+__device__ __forceinline__ C cfms_cj(C acc, C a, C b) {
+    acc.r = fma(-a.r, b.r, acc.r);
+    acc.r = fma(-a.i, b.i, acc.r);
+    acc.i = fma(-a.i, b.r, acc.i);
+    acc.i = fma(a.r, b.i, acc.i);
+    return acc;
+}
+// acc + i d b
+__device__ __forceinline__ C cfma_i(C acc, double d, C b) {
+    acc.r = fma(-d, b.i, acc.r);
+    acc.i = fma(d, b.r, acc.i);
+    return acc;
+}
+
+// acc += M y
+__device__ __forceinline__ void ah_mul_acc(M3 &acc, const AH &m, const M3 &y) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            C s = acc.a[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                if (k == i) s = cfma_i(s, m.d[i], y.a[3 * k + j]);
+                else if (k > i) s = cfma(s, m.u[ah_u(i, k)], y.a[3 * k + j]);
+                else s = cjfms(s, m.u[ah_u(k, i)], y.a[3 * k + j]);
+            }
+            acc.a[3 * i + j] = s;
+        }
+}
+// acc += x M
+__device__ __forceinline__ void mul_ah_acc(M3 &acc, const M3 &x, const AH &m) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            C s = acc.a[3 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                if (k == j) s = cfma_i(s, m.d[j], x.a[3 * i + k]);
+                else if (k < j) s = cfma(s, x.a[3 * i + k], m.u[ah_u(k, j)]);
+                else s = cfms_cj(s, x.a[3 * i + k], m.u[ah_u(j, k)]);
+            }
+            acc.a[3 * i + j] = s;
+        }
+}
+__device__ __forceinline__ M3 ah_mul(const AH &m, const M3 &y) {
+    M3 r;
+#pragma unroll
+    for (int q = 0; q < 9; q++) r.a[q] = cz();
+    ah_mul_acc(r, m, y);
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,13 +387,13 @@ __device__ M3 link_force(const double2 *__restrict__ U, const double2 *__restric
         // X = U_rho(y+nu)^H M(y+nu) U_nu(y)^H + W M(y) + M(y+rho+nu) W
         {
             const M3 W = mmul(link_dag(U, yn, RHO), link_dag(U, y, nu));
-            M3 X = mmul(link_dag(U, yn, RHO), mmul(load_insert(Mins, V, plane, yn), link_dag(U, y, nu)));
-            mmul_acc(X, W, load_insert(Mins, V, plane, y));
-            mmul_acc(X, load_insert(Mins, V, plane, yrn), W);
+            M3 X = mmul(link_dag(U, yn, RHO), ah_mul(load_ah(Mins, V, plane, yn), link_dag(U, y, nu)));
+            mul_ah_acc(X, W, load_ah(Mins, V, plane, y));
+            ah_mul_acc(X, load_ah(Mins, V, plane, yrn), W);
             const M3 A = link(U, yr, nu);
             const M3 S = mmul(A, W);
             M3 T = mmul(A, X);
-            mmul_acc(T, load_insert(Mins, V, plane, yr), S);
+            ah_mul_acc(T, load_ah(Mins, V, plane, yr), S);
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -329,15 +406,15 @@ __device__ M3 link_force(const double2 *__restrict__ U, const double2 *__restric
         // plaquette below: T = U_nu(a)^H Z + R M(y+rho) + M(y) R, R = U_nu(a)^H U_rho(a) U_nu(b),
         // Z = (M(a) U_rho(a) + U_rho(a) M(b)) U_nu(b)
         {
-            M3 Z = mmul(load_insert(Mins, V, plane, ya), link(U, ya, RHO));
-            mmul_acc(Z, link(U, ya, RHO), load_insert(Mins, V, plane, yb));
+            M3 Z = ah_mul(load_ah(Mins, V, plane, ya), link(U, ya, RHO));
+            mul_ah_acc(Z, link(U, ya, RHO), load_ah(Mins, V, plane, yb));
             Z = mmul(Z, link(U, yb, nu));
             const M3 E = mmul(link(U, ya, RHO), link(U, yb, nu));
             const M3 a = link_dag(U, ya, nu);
             M3 T = mmul(a, Z);
             const M3 R = mmul(a, E);
-            mmul_acc(T, R, load_insert(Mins, V, plane, yr));
-            mmul_acc(T, load_insert(Mins, V, plane, y), R);
+            mul_ah_acc(T, R, load_ah(Mins, V, plane, yr));
+            ah_mul_acc(T, load_ah(Mins, V, plane, y), R);
 #pragma unroll
             for (int e = 0; e < 9; e++) {
                 G.a[e].r = fma(kap, T.a[e].r, G.a[e].r);
@@ -425,6 +502,26 @@ __global__ __launch_bounds__(256, 2) void force_link_kernel(double2 *__restrict_
     for (int t = threadIdx.x; t < nsite * 36; t += blockDim.x) dst[t] = stage[(t / 36) * kLdsPitch + t % 36];
 }
 
+// canonical [V][4][3][3] complex links -> the force kernel's site tiles (zeros past V in the last tile)
+__global__ __launch_bounds__(256) void force_layout_kernel(double2 *__restrict__ dst, const double2 *__restrict__ src,
+                                                           int V) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntile = (V + kLinkTile - 1) / kLinkTile;
+    if (t >= (long long)ntile * 36 * kLinkTile) return;
+    const int l = (int)(t % kLinkTile), q = (int)(t / kLinkTile % 36), tile = (int)(t / (36 * kLinkTile));
+    const int s = tile * kLinkTile + l;
+    dst[t] = s < V ? src[(size_t)s * 36 + q] : make_double2(0.0, 0.0);
+}
+
+size_t force_links_bytes(int V) { return (size_t)(V + kLinkTile - 1) / kLinkTile * kLinkTile * 36 * sizeof(double2); }
+
+hipError_t force_links_layout(double *dst, const double *canon, int V, hipStream_t st) {
+    const long long n = (long long)(V + kLinkTile - 1) / kLinkTile * kLinkTile * 36;
+    hipLaunchKernelGGL(force_layout_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<double2 *>(dst), reinterpret_cast<const double2 *>(canon), V);
+    return hipGetLastError();
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -457,7 +554,7 @@ extern "C" int dirac_force(const dirac_op *op, double *dU, const double *eta, co
     const int slice = op->g.stride[0];
     const int eighth = ((slice + 7) / 8 + kLinkSites - 1) / kLinkSites * kLinkSites;
     hipLaunchKernelGGL(force_link_kernel, dim3(op->g.n[0] * 8 * (eighth / kLinkSites)), dim3(4 * kLinkSites), 0, st,
-                       reinterpret_cast<double2 *>(dU), reinterpret_cast<const double2 *>(op->links_canon),
+                       reinterpret_cast<double2 *>(dU), reinterpret_cast<const double2 *>(op->links_force),
                        (const double2 *)M, e2, x2, nrhs, op->g, (op->flags & WDIRAC_ANTIPERIODIC_T) ? 1 : 0,
                        with_clover, op->csw, raw ? 1 : 0, eighth);
     hipError_t e = hipGetLastError();
