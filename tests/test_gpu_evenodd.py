@@ -157,24 +157,25 @@ def test_even_odd_errors():
                                        s) == _lib.EINVAL
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
-def test_paired_rhs_equal_single_launches(prec):
+@pytest.mark.parametrize("prec,n", [("f64", 5), ("f32", 5), ("f16s", 5), ("f64", 18), ("f16s", 18)])
+def test_paired_rhs_equal_single_launches(prec, n):
     """Right-hand sides applied together (pairs, or fours at FP16S: one lane,
     shared link and A loads) and one at a time give the same bytes; five leave
-    a lone last one in both groupings."""
+    a lone last one in both groupings, eighteen span a 16-RHS launch and a
+    launch of two."""
     need_gpu()
     dims = (4, 6, 2, 10)
     U, _ = fields(dims, 29, "smooth")
     Vh = synth.volume(dims) // 2
     rng = np.random.default_rng(8)
-    xe = rng.standard_normal((5, Vh, 12)) + 1j * rng.standard_normal((5, Vh, 12))
+    xe = rng.standard_normal((n, Vh, 12)) + 1j * rng.standard_normal((n, Vh, 12))
     op = DiracOp(dims, U, -0.3, 1.0, even_odd=True, compress_links=True, compress_clover=True)
     inp = dev_parity(op, xe, 0, prec)
     rb = op.parity_field_bytes(prec, 1)
-    out3, tmp3 = op.empty_parity(prec, 5), op.empty_parity(prec, 5)
+    out3, tmp3 = op.empty_parity(prec, n), op.empty_parity(prec, n)
     out3.zero_()
-    op.apply_schur_native(out3, inp, tmp3, 5, prec)
-    for r in range(5):
+    op.apply_schur_native(out3, inp, tmp3, n, prec)
+    for r in range(n):
         o1, t1 = op.empty_parity(prec, 1), op.empty_parity(prec, 1)
         o1.zero_()
         op.apply_schur_native(o1, inp[r * rb:(r + 1) * rb], t1, 1, prec)
