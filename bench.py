@@ -79,6 +79,13 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip every measurement after the main one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solve-profile", action="store_true",
+                    help="only the mixed even-odd solve of --fgmres-rhs right-hand sides, bracketed by one FP32 "
+                         "apply on each side (markers for a kernel trace)")
+    ap.add_argument("--solve-wave", type=int, default=0,
+                    help="right-hand sides per wave of --solve-profile (0: as many as the free HBM allows)")
+    ap.add_argument("--summarize-solve", nargs=3, metavar=("TRACE_DIR", "SOLVE_LOG", "OUT_MD"),
+                    help="kernel-time breakdown of a --solve-profile run under rocprofv3 --kernel-trace")
     ap.add_argument("--fixed-launch", type=int, nargs=4, metavar=("ORDER", "BLOCK", "TCHUNK", "NR"),
                     help="use this launch configuration for every stencil launch instead of autotuning "
                          "(reproducible profiling runs)")
@@ -318,6 +325,97 @@ def amg_run(torch, op, dims, stream, steps=10):
            "precond_ms": ms_m, "coarse_applies_per_precond": (s1["coarse_applies"] - s0["coarse_applies"]) / 3}
     del b, c
     return res, mg
+
+
+# the mixed solver on S as the bench's one-RHS sweep picks it at 48^3 x 96 (outer FGMRES(16), inner GMRES(10) on the
+# FP16S S to 0.05): the configuration --solve-profile runs without sweeping
+EO_MIXED_PROFILE = dict(tol=1e-10, restart=16, maxit=500, mode="mixed_f16s", schur=True, inner_restart=10,
+                        inner_tol=0.05, inner_maxit=10)
+MARKER = r"dslash_\w*kernel<1, "   # the FP32 full-lattice stencil, which the even-odd mixed solve never launches
+
+
+def solve_profile_run(torch, op, dims, nrhs_total, wave_max=0):
+    """The mixed even-odd solve alone, in waves sized to the free HBM as in fgmres_run, between two FP32 applies
+    whose dispatches mark the solve's window in a kernel trace."""
+    from paper_2407_00041_amd import synth
+    for n in (1, 2, 3, 6):
+        op.autotune("f64", n)
+        op.autotune("f16s", n)
+    kw = EO_MIXED_PROFILE
+    fb = op.field_bytes("f64", 1)
+    b_all = op.pack(torch.cat([synth.gaussian_spinor(dims, 3000 + q, nrhs=1, device="cuda")
+                               for q in range(nrhs_total)]), "f64")
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    per = op.workspace_bytes(1, kw["restart"], kw["mode"], kw["inner_restart"], wave=1, schur=True) + 3 * fb
+    wave = int(max(1, min(nrhs_total, (free - (8 << 30)) // per)))
+    if wave_max > 0:
+        wave = min(wave, wave_max)
+    work = torch.empty(op.workspace_bytes(wave, kw["restart"], kw["mode"], kw["inner_restart"], wave=wave,
+                                          schur=True), dtype=torch.uint8, device="cuda")
+    bs = [b_all[w0 * fb:min(w0 + wave, nrhs_total) * fb] for w0 in range(0, nrhs_total, wave)]
+    m_in, m_out = op.empty("f32", 1), op.empty("f32", 1)
+    m_in.zero_()
+    torch.cuda.synchronize()
+    op.apply_native(m_out, m_in, 1, "f32")
+    t, applies, inner = time.perf_counter(), 0, 0
+    for w0, b in zip(range(0, nrhs_total, wave), bs):
+        nw = min(wave, nrhs_total - w0)
+        x, st, _ = op.solve(b, nrhs=nw, work=work, wave=wave, **kw)
+        applies += sum(st[k]["applies"] for k in range(nw))
+        inner += sum(st[k]["inner_applies"] for k in range(nw))
+        del x
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    op.apply_native(m_out, m_in, 1, "f32")
+    torch.cuda.synchronize()
+    log(f"[bench] solve-profile: mixed on S, {nrhs_total} RHS in waves of {wave}: {el:.3f} s, {applies} outer "
+        f"applications of S, {inner} FP16S ones")
+
+
+def summarize_solve(trace_dir, solve_log, out_md, command):
+    """Kernel time of the --solve-profile window (between the last two FP32 stencil dispatches), per kernel and
+    per role."""
+    import re
+    kt = sorted(_read_csv(_find(trace_dir, "kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(kt) if re.search(MARKER, r["Kernel_Name"])]
+    if len(marks) < 2:
+        raise ValueError("fewer than two FP32 stencil dispatches in the trace")
+    win = kt[marks[-2] + 1:marks[-1]]
+    wall = (int(win[-1]["End_Timestamp"]) - int(win[0]["Start_Timestamp"])) * 1e-9
+    roles = [("FP16S S, inner GMRES (parity kernels)", r"parity_\w*kernel<2, "),
+             ("FP64 parity kernels: outer S, prepare, reconstruct, true residual", r"parity_\w*kernel<0, "),
+             ("inner vector kernels (FP16S basis)", r"k_site_"),
+             ("outer vector kernels (FP64 basis)", r"k_mdot_all|k_axpy_multi|k_update|k_residual|k_scale"),
+             ("reductions and small solver kernels", r"k_colsum|k_inner_"),
+             ("copies (runtime blits, parity split and merge)", r"copyBuffer|parity_copy_kernel")]
+    per, role_t = {}, {name: 0.0 for name, _ in roles}
+    role_t["other"] = 0.0
+    total = 0.0
+    for r in win:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        total += d
+        name = re.sub(r"^void |\(anonymous namespace\)::", "", r["Kernel_Name"]).split("(")[0]
+        c, t = per.get(name, (0, 0.0))
+        per[name] = (c + 1, t + d)
+        role = next((n for n, pat in roles if re.search(pat, r["Kernel_Name"])), "other")
+        role_t[role] += d
+    line = next((ln for ln in open(solve_log).read().splitlines() if ln.startswith("[bench] solve-profile")), "")
+    lines = ["# Mixed even-odd FGMRES, 48^3 x 96, 12 right-hand sides to 1e-10: kernel time by role", "",
+             "Command (repo root, MI355X):", "", "```", command, "```", "",
+             f"Solve log: `{line.strip()}`.", "",
+             f"Window: {len(win)} dispatches between the two FP32 marker applies; {wall:.3f} s from the first "
+             f"dispatch's start to the last one's end, {total:.3f} s of kernel time ({total / wall:.1%} busy).", "",
+             "| role | kernel s | share of kernel time |", "|---|---|---|"]
+    for name, t in sorted(role_t.items(), key=lambda kv: -kv[1]):
+        lines.append(f"| {name} | {t:.3f} | {t / total:.1%} |")
+    lines += ["", "| kernel | calls | total s | avg us |", "|---|---|---|---|"]
+    for name, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:12]:
+        lines.append(f"| `{name[:100]}` | {c} | {t:.3f} | {t / c * 1e6:.1f} |")
+    lines += ["", f"sources_sha256_16: {all_sources_hash()}", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    log(f"[bench] wrote {out_md}")
 
 
 def fgmres_run(torch, op, dims, nrhs_total, mg=None, amg_setup_s=None):
@@ -1027,6 +1125,9 @@ def main():
     if a.summarize:
         summarize_profile(*a.summarize, command=a.summary_command)
         return
+    if a.summarize_solve:
+        summarize_solve(*a.summarize_solve, command=a.summary_command)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no multi-GPU "
                                    "halo exchange"}))
@@ -1054,6 +1155,10 @@ def main():
     log(f"[bench] inputs ready in {time.time() - t0:.1f}s; creating operator")
     op = wd.DiracOp(dims, U, a.m0, a.csw, precisions=("f64", "f32", "f16s"), compress_links=True,
                     compress_clover=True, even_odd=True)
+    if a.solve_profile:
+        del psid
+        solve_profile_run(torch, op, dims, a.fgmres_rhs, a.solve_wave)
+        return
     stream = torch.cuda.current_stream()
     inp = {p: op.pack(psid, p) for p in ("f64", "f32", "f16s")}
     out = {p: op.empty(p, 1) for p in ("f64", "f32", "f16s")}

@@ -133,3 +133,43 @@ def test_committed_summaries_match_their_own_format():
         assert t == pytest.approx((float(r[8]) + float(r[9])) * 1e9)
     if f"sources_sha256_16: {bench.all_sources_hash()}" in md:
         assert "dslash_column_kernel<0, false, 1>" in bench.kernel_profile_rows()
+
+
+def test_solve_summary_takes_the_marked_window(tmp_path):
+    """Dispatches before the second-to-last FP32 stencil marker (operator setup, autotuning, an earlier marker)
+    and after the last one are left out; the window's kernels are summed per role."""
+    seq = [("void wd::dslash_column_kernel<1, false, 1>(wd::ChunkTable<1>, int)", 5_000),     # autotune-time marker
+           ("void wd::parity_kernel<2, false, 0, true, true, 2, 4>(wd::ParityTable)", 7_000),  # before the window
+           ("void wd::dslash_column_kernel<1, false, 1>(wd::ChunkTable<1>, int)", 5_000),     # first marker
+           ("void wd::(anonymous namespace)::parity_kernel<2, false, 0, true, true, 2, 4>(wd::(anonymous namespace)::ParityTable)", 3_000),
+           ("void wd::parity_kernel<2, false, 2, true, false, 2, 4>(wd::ParityTable)", 3_000),
+           ("void wd::parity_column_kernel<0, false, 0, true, true, 2, 2, 4>(wd::ParityTable)", 6_000),
+           ("void wd::k_site_mdot<2>(int)", 2_000),
+           ("void wd::k_mdot_all<double2, 8>(int)", 1_000),
+           ("void wd::dslash_column_kernel<0, false, 1>(wd::ChunkTable<1>, int)", 4_000),
+           ("void other_kernel(int)", 1_000),
+           ("void wd::dslash_column_kernel<1, false, 1>(wd::ChunkTable<1>, int)", 5_000)]     # last marker
+    trace, t0 = [], 0
+    for i, (name, dur) in enumerate(seq):
+        dur *= 1000                                             # microseconds -> milliseconds
+        trace.append({"Dispatch_Id": i + 1, "Kernel_Name": name, "Start_Timestamp": t0, "End_Timestamp": t0 + dur})
+        t0 += dur + 1_000
+    _write_csv(str(tmp_path / "tr" / "x_kernel_trace.csv"), trace)
+    log = tmp_path / "s.log"
+    log.write_text("[bench] solve-profile: mixed on S, 12 RHS in waves of 4: 1.000 s, 120 outer applications of S, "
+                   "708 FP16S ones\n")
+    out = tmp_path / "s.md"
+    bench.summarize_solve(str(tmp_path / "tr"), str(log), str(out), "cmd")
+    md = out.read_text()
+    roles = {}
+    for line in md.splitlines():
+        c = [x.strip() for x in line.split("|")]
+        if len(c) == 5 and c[2].replace(".", "").isdigit() and c[3].endswith("%"):
+            roles[c[1]] = float(c[2])
+    assert "7 dispatches" in md
+    assert roles["FP16S S, inner GMRES (parity kernels)"] == pytest.approx(6e-3)
+    assert roles["FP64 parity kernels: outer S, prepare, reconstruct, true residual"] == pytest.approx(6e-3)
+    assert roles["inner vector kernels (FP16S basis)"] == pytest.approx(2e-3)
+    assert roles["outer vector kernels (FP64 basis)"] == pytest.approx(1e-3)
+    assert roles["other"] == pytest.approx(5e-3)         # the FP64 full-lattice stencil is no role of this solve
+    assert "| `wd::parity_kernel<2, false, 0, true, true, 2, 4>` | 1 |" in md
