@@ -456,7 +456,9 @@ typedef struct {
 #define FGMRES_HIST_MAX 4096
 
 typedef struct {
-    long long applies;          /* FP64 operator applications                */
+    long long applies;          /* FP64 operator applications (a product   */
+                                /* with the zero initial guess is counted  */
+                                /* but, being zero, not launched)          */
     long long inner_applies;    /* low-precision applications (mixed)        */
     long long restarts;         /* outer cycles                              */
     int converged;              /* 1 if the tolerance was met                */

@@ -349,6 +349,7 @@ struct Rhs {
     double r0norm = -1, relres = 1;
     bool breakdown = false, converged = false;
     bool nonfinite = false;  // a NaN or Inf reached a residual norm or a Hessenberg column
+    bool x_zero = false;     // x is still the zero initial guess, so D x (or S x) is zero without an application
     long long applies = 0, inner_applies = 0, restarts = 0;
     std::vector<double> hist;
 };
@@ -634,6 +635,22 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         }
     } ev;
     for (hipEvent_t &x : ev.e) WD_TRY(hipEventCreate(&x));
+    // |x0|^2 of every right-hand side, in one synchronisation: with the usual zero initial guess the products
+    // D x0 of the set-up and of the first residual are zero, so they are counted without being launched (an x0
+    // whose entries all lie below ~1e-162 in magnitude also reads as zero; its product is far below the FP64
+    // resolution of any residual)
+    {
+        std::vector<std::pair<const double2 *, int>> xs;
+        const void *none = nullptr;
+        for (Rhs &r : R) {
+            WD_TRY(mdot_all<double2>(&none, 0, r.xu, 12LL * op->g.V, r.partial, r.nrm, c.st));
+            xs.emplace_back(r.nrm, 1);
+        }
+        std::vector<std::vector<zc>> got;
+        const int rc = fetch(c, xs, got);
+        if (rc) return rc;
+        for (size_t k = 0; k < R.size(); k++) R[k].x_zero = got[k][0].real() == 0.0;
+    }
     if (c.schur) {
         // |b - D x0| over both parities (the tolerance's reference, so that tol means the same as for D x = b),
         // then the reduced right-hand side bhat = b_e - H_eo A_oo^{-1} b_o
@@ -642,10 +659,12 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
             double2 *xo = static_cast<double2 *>(r.V[0]), *bo = static_cast<double2 *>(r.V[1]);
             WD_TRY(parity_split_launch(op, WDIRAC_F64, r.x, xo, r.xu, 1, c.st));
             WD_TRY(parity_split_launch(op, WDIRAC_F64, r.bh, bo, r.bu, 1, c.st));
-            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 0, r.w, r.x, xo, 1, c.st));
-            WD_TRY(residual(r.bh, r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.nrm, c.st));
-            WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 1, r.w, xo, r.x, 1, c.st));
-            WD_TRY(residual(bo, r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.hcol2, c.st));
+            // with x0 = 0 its zero halves stand for the zero halves of D x0
+            if (!r.x_zero) WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 0, r.w, r.x, xo, 1, c.st));
+            WD_TRY(residual(r.bh, r.x_zero ? xo : r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.nrm, c.st));
+            if (!r.x_zero) WD_TRY(parity_launch(kParApply, WDIRAC_F64, false, op, 1, r.w, xo, r.x, 1, c.st));
+            WD_TRY(residual(bo, r.x_zero ? r.x : r.w, static_cast<double2 *>(r.t64), c.N, r.partial, r.hcol2,
+                            c.st));
             WD_TRY(parity_launch(kParInvSelf, WDIRAC_F64, false, op, 1, r.t64, bo, nullptr, 1, c.st));
             WD_TRY(parity_launch(kParSelfSub, WDIRAC_F64, false, op, 0, r.bh, r.bh, r.t64, 1, c.st));
             src.emplace_back(r.nrm, 1);
@@ -694,13 +713,16 @@ int solve(const dirac_op *op, double *x, const double *b, int nrhs, const fgmres
         WD_TRY(hipEventRecord(ev.e[1], c.st));
         // one batched FP64 application for all of them (restart residuals and Arnoldi products)
         std::vector<ApplyItem> bat;
-        for (Rhs *r : res) bat.push_back({r->w, r->x, r->t64});
+        for (Rhs *r : res)
+            if (!r->x_zero) bat.push_back({r->w, r->x, r->t64});
         for (Rhs *r : arn) bat.push_back({r->V[r->outer.j + 1], r->Z[r->outer.j], r->t64});
         WD_TRY(apply_many(c, WDIRAC_F64, bat, c.st));
         WD_TRY(hipEventRecord(ev.e[2], c.st));
         for (Rhs *r : res) {
-            r->applies++;
-            WD_TRY(residual(r->b, r->w, static_cast<double2 *>(r->V[0]), c.N, r->partial, r->nrm, c.st));
+            r->applies++;  // counted also when x is still zero and x itself stands for the zero product
+            WD_TRY(residual(r->b, r->x_zero ? r->x : r->w, static_cast<double2 *>(r->V[0]), c.N, r->partial,
+                            r->nrm, c.st));
+            r->x_zero = false;  // the cycle's update changes x
         }
         for (Rhs *r : arn) {
             // classical Gram-Schmidt of w = V[j+1] = D Z[j] against V[0..j]: one launch of inner products (w read
