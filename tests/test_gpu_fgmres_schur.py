@@ -191,3 +191,27 @@ def test_full_size_reduced_mixed_fgmres_bench_configuration():
     del op, x, bn
     torch.cuda.empty_cache()
     assert true_relres(dims, U, m0, csw, xg, bd.cpu().numpy()[0]) <= 1e-10 * 1.01
+
+
+@pytest.mark.parametrize("schur", [False, True])
+def test_zero_and_warm_initial_guesses_in_one_call(schur):
+    """One call with a zero initial guess (its products D x0 counted, not launched) next to a warm start gives
+    what two separate calls give, bit for bit, and each true residual is the oracle's relative to its own x0."""
+    need_gpu()
+    dims = (4, 4, 6, 4)
+    m0, csw = -0.3, 1.0
+    U, b, op, bn = setup(dims, 21, m0, csw, nrhs=2)
+    fb = op.field_bytes("f64", 1)
+    kw = dict(restart=8, tol=1e-10, maxit=2000, schur=schur)
+    warm, _, _ = op.solve(bn[fb:], restart=5, tol=1e-12, maxit=6, schur=schur)   # a non-zero start for RHS 1
+    x0 = torch.cat([torch.zeros_like(warm), warm])
+    x, st, rc = op.solve(bn, nrhs=2, x0=x0, **kw)
+    assert rc == 0 and all(s["converged"] for s in st)
+    x_a, st_a, _ = op.solve(bn[:fb], **kw)
+    x_b, st_b, _ = op.solve(bn[fb:], x0=warm, **kw)
+    assert torch.equal(x[:fb], x_a) and torch.equal(x[fb:], x_b)
+    assert [s["applies"] for s in st] == [st_a[0]["applies"], st_b[0]["applies"]]
+    xw = op.unpack(warm, "f64").cpu().numpy()[0]
+    xs = op.unpack(x, "f64").cpu().numpy()
+    assert abs(st[0]["true_residual"] - true_relres(dims, U, m0, csw, xs[0], b[0])) < 1e-13
+    assert abs(st[1]["true_residual"] - true_relres(dims, U, m0, csw, xs[1], b[1], xw)) < 1e-13
